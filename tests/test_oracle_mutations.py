@@ -1,0 +1,105 @@
+"""Planted mistakes: each case copies the oracle source, plants one plausible
+mistake (a dropped term, a wrong sign, a wrong index, a transposed operand),
+compiles the copy on the CPU and checks that the pins reject it.  This shows
+the pins are strong enough to catch such errors in the oracle itself."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "tft_oracle.c")
+
+MUTATIONS = {
+    # natural-order root index instead of the bit-reversed one
+    "omega_not_reversed": ("return or_powmod(or_root_chain(p, g, k), or_rev(s, k), p);\n}\n\n/* Same root",
+                           "return or_powmod(or_root_chain(p, g, k), s, p);\n}\n\n/* Same root"),
+    # Horner evaluation drops the constant term
+    "eval_drops_term": ("for (u64 t = n; t-- > 0;)", "for (u64 t = n; t-- > 1;)"),
+    # paper TFT: the odd-length correction is skipped
+    "paper_no_correction": ("*last = or_addmod(*last, correction_value(c, q, r, m), p);", "(void)last;"),
+    # paper TFT: butterfly sign flipped
+    "paper_sign": ("*o = or_submod(a, t, p);\n    }\n}", "*o = or_addmod(a, t, p);\n    }\n}"),
+    # paper TFT: twiddle index off (w_j instead of w_{2j})
+    "paper_twiddle_index": ("u64 t = or_mulmod(c->w[2 * j], *o, p);", "u64 t = or_mulmod(c->w[j], *o, p);"),
+    # padded FFT: output not permuted
+    "padded_no_permutation": ("for (u64 s = 0; s < n; s++) X[s] = a[or_rev(s, k)];", "for (u64 s = 0; s < n; s++) X[s] = a[s];"),
+    # schoolbook: transposed index
+    "schoolbook_index": ("C[i + j] = or_addmod(C[i + j], or_mulmod(A[i] % p, B[j] % p, p), p);",
+                         "C[i + j] = or_addmod(C[i + j], or_mulmod(A[j % m] % p, B[i % nb] % p, p), p);"),
+    # interpolation: sign slip in building M
+    "lagrange_sign": ("M[0] = or_submod(0, or_mulmod(M[0], w[s], p), p);", "M[0] = or_mulmod(M[0], w[s], p);"),
+}
+
+
+def build_variant(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / f"{name}.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", str(so), str(path)], check=True)
+    return so
+
+
+def pins_pass(so):
+    """A compact subset of the pins of tests/test_oracle_*.py, run against a
+    library at an arbitrary path.  Returns False on the first failing pin."""
+    import json
+    L = ctypes.CDLL(str(so))
+    u64, P = ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)
+    for f in ("or_tft_direct", "or_itft_lagrange", "or_tft_paper", "or_mul_schoolbook"):
+        getattr(L, f).restype = ctypes.c_int
+    L.or_fft_padded.restype = ctypes.c_int
+    L.or_fft_padded.argtypes = [u64, u64, P, u64, ctypes.c_uint, P]
+    L.or_omega.restype = u64
+    L.or_omega.argtypes = [u64, u64, u64]
+
+    def arr(v):
+        return np.ascontiguousarray(np.asarray(v, dtype=np.uint64))
+
+    def call(fn, p, g, F, out_len=None):
+        F = arr(F)
+        X = np.zeros(out_len or len(F), dtype=np.uint64)
+        getattr(L, fn)(u64(p), u64(g), F.ctypes.data_as(P), u64(len(F)), X.ctypes.data_as(P))
+        return [int(x) for x in X]
+
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tft_p17.json")))
+    if [int(L.or_omega(17, 3, s)) for s in range(16)] != gold["omega"]:
+        return False
+    for c in gold["cases"]:
+        if call("or_tft_direct", 17, 3, c["F"]) != c["X"]:
+            return False
+        if call("or_itft_lagrange", 17, 3, c["X"]) != c["F"]:
+            return False
+        X = arr(c["F"]).copy()
+        L.or_tft_paper(u64(17), u64(3), X.ctypes.data_as(P), u64(len(X)))
+        if [int(x) for x in X] != c["X"]:
+            return False
+        Xp = np.zeros(len(c["F"]), dtype=np.uint64)
+        L.or_fft_padded(17, 3, arr(c["F"]).ctypes.data_as(P), len(c["F"]), 0, Xp.ctypes.data_as(P))
+        if [int(x) for x in Xp] != c["X"]:
+            return False
+    rng = np.random.default_rng(0)
+    A, B = rng.integers(0, 1000, 9), rng.integers(0, 1000, 5)
+    C = np.zeros(13, dtype=np.uint64)
+    L.or_mul_schoolbook(u64(998244353), arr(A).ctypes.data_as(P), u64(9), arr(B).ctypes.data_as(P), u64(5),
+                        C.ctypes.data_as(P))
+    if [int(c) for c in C] != [int(x) for x in np.convolve(A, B) % 998244353]:
+        return False
+    return True
+
+
+def test_unmutated_oracle_passes(tmp_path):
+    so = build_variant(tmp_path, "clean", "/* k-bit reversal of s (s < 2^k). */", "/* k-bit reversal of s (s < 2^k). */")
+    assert pins_pass(so)
+
+
+@pytest.mark.parametrize("name", list(MUTATIONS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    old, new = MUTATIONS[name]
+    so = build_variant(tmp_path, name, old, new)
+    assert not pins_pass(so), f"planted mistake {name} was not caught by the pins"
