@@ -1,0 +1,131 @@
+/*
+ * libtft — in-place truncated Fourier transform over Z/pZ on one AMD MI355X
+ * (gfx950) GPU, after D. Harvey and D. S. Roche, "An in-place truncated
+ * Fourier transform and applications to polynomial multiplication" (2010).
+ *
+ * Notation (paper, section 2.2): w[k] is a primitive 2^k-th root of unity and
+ * the roots are compatible, w[k+1]^2 = w[k]; here w[k] = g^((p-1)/2^k) for
+ * the generator g given at context creation.  w_s = w[k]^(rev_k s) for any
+ * k >= bitlen(s), and the transform of a polynomial F of degree < n is
+ * F^_s = F(w_s), 0 <= s < n: the first n outputs of the length-2^ceil(lg n)
+ * DFT in bit-reversed order (section 1.2).
+ *
+ * Words.  A context for a prime p < 2^31 works on uint32_t words; the context
+ * for p = 2^64 - 2^32 + 1 works on uint64_t words.  Every data argument is a
+ * device pointer to canonical residues in [0, p); results are canonical.
+ * Results are exact (no rounding), so they are bit-identical to any other
+ * correct implementation.
+ *
+ * Memory.  The caller owns every data buffer.  The transforms run in place on
+ * the n words given: there is no padding to 2^ceil(lg n) and no per-call
+ * allocation.  A context owns only constant tables (two-level root tables,
+ * independent of n) and one fixed scratch area (the "extra evaluations" of the
+ * partial last row, at most 2^16 words, independent of n).  Calls that share
+ * a context must therefore be ordered: issue them on one stream, or
+ * synchronise between streams.  All work is enqueued on the caller's stream
+ * (a hipStream_t passed as void*; NULL is the default stream) and the calls
+ * return without waiting for it.
+ *
+ * Errors.  Functions return a tft_status and never throw.  Argument errors are
+ * detected on the host before anything is enqueued; a launch failure reports
+ * TFT_EDEVICE.  Asynchronous device faults surface at the caller's next
+ * synchronisation, as for any HIP kernel.
+ */
+#ifndef LIBTFT_H
+#define LIBTFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TFT_OK = 0,
+    TFT_EINVAL = -1,   /* null pointer, zero length, bad generator */
+    TFT_ERANGE = -2,   /* length above 2^v (v = 2-adic order of p-1) or above this build's limit; unsupported p */
+    TFT_ENOMEM = -3,   /* context or queue allocation failed */
+    TFT_EDEVICE = -4,  /* a HIP call failed */
+    TFT_EAGAIN = -5    /* queue: the request does not fit the free pool now */
+} tft_status;
+
+typedef struct tft_ctx tft_ctx;
+
+/* Create a context for prime p with generator g of (Z/pZ)^* on HIP device
+ * `device` (section 2.1: the ring needs 2^k-th roots of unity and 2 must be a
+ * unit).  Supported: odd primes p < 2^31 with 2 | p-1, and p = 2^64-2^32+1.
+ * g must generate the 2-part of the group: g^((p-1)/2) = -1.  On success
+ * *out owns device tables of about 1 MiB; release it with tft_ctx_destroy. */
+tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out);
+void tft_ctx_destroy(tft_ctx* ctx);
+
+/* v = 2-adic order of p-1, capped at this build's limit: every length n must
+ * satisfy n <= 2^v (section 6: a root of order 2^ceil(lg n) is needed). */
+unsigned tft_ctx_max_log2(const tft_ctx* ctx);
+/* 4 (uint32_t words) or 8 (uint64_t words). */
+unsigned tft_ctx_word_bytes(const tft_ctx* ctx);
+
+/* InplaceTFT (section 3, Algorithm 1; Proposition 3.2): X[0..n) holds F_0..F_{n-1}
+ * on entry and F^_0..F^_{n-1} on exit.  X is a device pointer to n words. */
+tft_status tft_forward(tft_ctx* ctx, void* X, size_t n, void* hip_stream);
+
+/* InplaceITFT (section 4, Algorithm 2; Proposition 4.2): the inverse map,
+ * X[0..n) holds F^_0..F^_{n-1} on entry and F_0..F_{n-1} on exit. */
+tft_status tft_inverse(tft_ctx* ctx, void* X, size_t n, void* hip_stream);
+
+/* X[i] <- X[i] * Y[i] mod p for i < n (the pointwise step of section 5). */
+tft_status tft_pointwise_mul(tft_ctx* ctx, void* X, const void* Y, size_t n, void* hip_stream);
+
+/* Product C = A B (section 5: A has m coefficients, B has nb; the output has
+ * r = m + nb - 1 coefficients).  A and B are read only.  X (r words) receives
+ * C; Y (r words) is caller-owned workspace holding B's transform, required
+ * unless r fits the single-workgroup path (then it may be NULL).  The path is
+ * transform A and B in r slots each, multiply pointwise, inverse-transform X. */
+tft_status poly_mul(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X, void* Y,
+                    void* hip_stream);
+
+/* Comparator, not the method: the ordinary padded radix-2 transform
+ * (section 1.1) that the TFT smooths.  With N = 2^ceil(lg n):
+ * tft_padded_forward copies X[0..n) into Xpad (N caller-owned words),
+ * zero-fills Xpad[n..N), runs the length-N transform in Xpad and copies the
+ * first n outputs back to X (the same values tft_forward produces), leaving
+ * all N outputs in Xpad.  tft_padded_inverse takes those N outputs in Xpad,
+ * runs the length-N inverse there and copies the first n coefficients to X.
+ * Time and memory jump at powers of two, which is what it is measured for. */
+tft_status tft_padded_forward(tft_ctx* ctx, void* X, size_t n, void* Xpad, void* hip_stream);
+tft_status tft_padded_inverse(tft_ctx* ctx, void* X, size_t n, void* Xpad, void* hip_stream);
+
+/* Padded product for comparison: A and B zero-extended to N = 2^ceil(lg r)
+ * words in Apad and Bpad (caller-owned), N-point transforms, pointwise
+ * product, N-point inverse, first r coefficients to X. */
+tft_status poly_mul_padded(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X, void* Apad,
+                           void* Bpad, void* hip_stream);
+
+/* Schedule chosen for length n (for tests and benchmarks).  kind 0: the
+ * single-workgroup path (whole transform in LDS); kind 1: the two-pass path
+ * with n = a W + b, W = 2^logW columns of the tree at depth logW (paper,
+ * section 3: node (c, logW) is the strided subarray X_{c + i W}). */
+typedef struct {
+    int kind;
+    unsigned logW;
+    size_t W, a, b;
+    size_t col_block;      /* power-of-two LDS block per column */
+    unsigned cols_per_tile;
+    size_t lds_bytes_col, lds_bytes_row;
+} tft_plan_desc;
+tft_status tft_plan_info(tft_ctx* ctx, size_t n, tft_plan_desc* out);
+
+/* Force the two-pass path with column width 2^logW for every length n > 2^logW
+ * (0 restores the planner's choice).  Used by the tuner and by tests that
+ * exercise many tiles at small n; any valid choice gives the same result.
+ * Lengths whose tiles would not fit in LDS then return TFT_ERANGE. */
+tft_status tft_set_plan_override(tft_ctx* ctx, unsigned logW);
+
+/* Human-readable name of a status code. */
+const char* tft_strerror(tft_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBTFT_H */

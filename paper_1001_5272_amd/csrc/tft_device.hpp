@@ -1,0 +1,302 @@
+// Device-side arithmetic and in-LDS transform routines for the in-place
+// truncated Fourier transform (Harvey & Roche 2010) on gfx950.
+//
+// Notation follows section 2.2 of the paper: w[k] is a primitive 2^k-th root
+// of unity with w[k+1]^2 = w[k]; w_s = w[k]^(rev_k s); the transform of F is
+// F^_s = F(w_s).  Every routine below computes exactly these values (all
+// arithmetic is exact modulo p), so results are bit-identical to any other
+// correct implementation.
+//
+// Transforms inside LDS use the "modular splitting" form of the radix-2 FFT:
+// a block of size 2h at global block index i holds F mod (x^{2h} - w_i), and
+// because x^{2h} - w_i = (x^h - w_{2i})(x^h + w_{2i}) with w_{2i+1} = -w_{2i}
+// (section 2.2 identities) one stage maps (lo, hi) to (lo + w_{2i} hi,
+// lo - w_{2i} hi).  After the last stage position s holds F(w_s).  This is the
+// same output the paper's even/odd recursion (eq. 1) produces; it is chosen
+// here because its stages are layer-parallel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tft {
+
+// ----------------------------------------------------------------- tables
+// Two-level root tables, independent of the transform length:
+//   w_s = f1[s mod 2^B1] * f2[s >> B1]          (forward)
+//   w_s^-1 / 2 = i1[s mod 2^B1] * i2[s >> B1]   (inverse, halving folded in)
+// For 31-bit primes the entries are stored in Montgomery form (x 2^32).
+constexpr int kB1 = 15;
+constexpr uint32_t kMask1 = (1u << kB1) - 1;
+
+template <class Word>
+struct Tables {
+    const Word* f1;
+    const Word* f2;
+    const Word* i1;
+    const Word* i2;
+};
+
+// ---------------------------------------------------------- 31-bit primes
+// Residues in [0, p), p < 2^31 odd.  Twiddles are kept in Montgomery form
+// (w 2^32 mod p) so that mul_tw(x, w 2^32) = x w mod p.
+struct ModU32 {
+    using Word = uint32_t;
+    uint32_t p;        // modulus
+    uint32_t pneg;     // -p^-1 mod 2^32
+    uint32_t r2;       // 2^64 mod p
+    uint32_t halfp1;   // (p + 1) / 2
+
+    __device__ __forceinline__ Word add(Word a, Word b) const {
+        Word s = a + b;                      // < 2p < 2^32
+        return s < s - p ? s : s - p;        // min(s, s - p) as unsigned
+    }
+    __device__ __forceinline__ Word sub(Word a, Word b) const {
+        Word d = a - b;
+        Word e = d + p;
+        return d < e ? d : e;
+    }
+    // Montgomery product a b 2^-32 mod p for a < 2^32, b < p.
+    __device__ __forceinline__ Word mont(Word a, Word b) const {
+        uint32_t lo = a * b;
+        uint32_t hi = __umulhi(a, b);
+        uint32_t m = lo * pneg;
+        uint32_t mh = __umulhi(m, p);
+        uint32_t u = hi + mh + (lo != 0u);   // (a b + m p) / 2^32 < 2p
+        uint32_t v = u - p;
+        return u < v ? u : v;
+    }
+    __device__ __forceinline__ Word mul_tw(Word a, Word twm) const { return mont(a, twm); }
+    __device__ __forceinline__ Word tw_mul_tw(Word t1, Word t2) const { return mont(t1, t2); }
+    // plain product of two residues
+    __device__ __forceinline__ Word mul(Word a, Word b) const { return mont(mont(a, b), r2); }
+    __device__ __forceinline__ Word half(Word x) const { return (x >> 1) + ((x & 1u) ? halfp1 : 0u); }
+};
+
+// ------------------------------------------------- p = 2^64 - 2^32 + 1
+// Residues in [0, p).  2^64 = 2^32 - 1 and 2^96 = -1 modulo p, so a 128-bit
+// product reduces with shifts, adds and subtracts only.
+struct ModGL {
+    using Word = uint64_t;
+    static constexpr uint64_t P = 0xFFFFFFFF00000001ull;
+    static constexpr uint64_t EPS = 0xFFFFFFFFull;       // 2^64 mod p
+    static constexpr uint64_t HALF = 0x7FFFFFFF80000001ull; // (p + 1) / 2
+
+    __device__ __forceinline__ Word add(Word a, Word b) const {
+        Word s = a + b;
+        return (s < a || s >= P) ? s - P : s;   // wraps: s + 2^64 - p when carried
+    }
+    __device__ __forceinline__ Word sub(Word a, Word b) const {
+        Word d = a - b;
+        return (a < b) ? d + P : d;
+    }
+    __device__ __forceinline__ Word reduce128(uint64_t lo, uint64_t hi) const {
+        uint64_t hh = hi >> 32, hl = hi & EPS;
+        uint64_t t0 = lo - hh;
+        if (lo < hh) t0 -= EPS;                  // borrow: add p
+        uint64_t t1 = (hl << 32) - hl;           // hl (2^32 - 1)
+        uint64_t r = t0 + t1;
+        if (r < t0) r += EPS;                    // carry: add 2^64 mod p
+        return r >= P ? r - P : r;
+    }
+    __device__ __forceinline__ Word mul(Word a, Word b) const {
+        unsigned __int128 t = (unsigned __int128)a * b;
+        return reduce128((uint64_t)t, (uint64_t)(t >> 64));
+    }
+    __device__ __forceinline__ Word mul_tw(Word a, Word tw) const { return mul(a, tw); }
+    __device__ __forceinline__ Word tw_mul_tw(Word t1, Word t2) const { return mul(t1, t2); }
+    __device__ __forceinline__ Word half(Word x) const { return (x >> 1) + ((x & 1ull) ? HALF : 0ull); }
+};
+
+template <class Mod>
+__device__ __forceinline__ typename Mod::Word tw_fwd(const Mod& md, const Tables<typename Mod::Word>& T,
+                                                      uint64_t s) {
+    typename Mod::Word t = T.f1[s & kMask1];
+    uint64_t h = s >> kB1;
+    if (h) t = md.tw_mul_tw(t, T.f2[h]);
+    return t;
+}
+
+template <class Mod>
+__device__ __forceinline__ typename Mod::Word tw_inv_half(const Mod& md, const Tables<typename Mod::Word>& T,
+                                                           uint64_t s) {
+    typename Mod::Word t = T.i1[s & kMask1];
+    uint64_t h = s >> kB1;
+    if (h) t = md.tw_mul_tw(t, T.i2[h]);
+    return t;
+}
+
+// ------------------------------------------------------- LDS block views
+// A tile in LDS holds C interleaved vectors ("lanes"): element d of lane c is
+// buf[d * C + c].  Rows use C = 1.  All routines are called by every thread of
+// the workgroup and end with a barrier.
+
+// Pruned forward transform.  The block at the root has size M (a power of
+// two) and global block index g0 (the root is F mod (x^M - w_{g0})).  Only the
+// output positions in [out_lo, out_hi) are produced; a butterfly whose two
+// halves feed no wanted output is skipped and a half that feeds none is not
+// written.  Positions outside the wanted range end with unspecified values.
+template <class Mod>
+__device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+                            int logC, uint32_t M, uint32_t out_lo, uint32_t out_hi, uint64_t g0) {
+    using Word = typename Mod::Word;
+    const uint32_t C = 1u << logC;
+    for (uint32_t h = M >> 1; h >= 1; h >>= 1) {
+        const uint32_t two_h = h << 1;
+        const uint32_t i_lo = out_lo / two_h;
+        const uint32_t i_hi = (out_hi - 1) / two_h;
+        const uint32_t logh = __builtin_ctz(h);
+        const uint32_t items = (i_hi - i_lo + 1) * h * C;
+        const uint64_t gbase = g0 * (uint64_t)(M / two_h);   // global index of local block 0
+        uint32_t cached_i = 0xFFFFFFFFu;
+        Word tw = 0;
+        for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+            const uint32_t c = it & (C - 1);
+            const uint32_t u = it >> logC;
+            const uint32_t i = i_lo + (u >> logh);
+            const uint32_t j = u & (h - 1);
+            const uint32_t lpos = i * two_h + j, rpos = lpos + h;
+            const bool needL = (i * two_h < out_hi) && (i * two_h + h > out_lo);
+            const bool needR = (i * two_h + h < out_hi) && (i * two_h + two_h > out_lo);
+            if (i != cached_i) { tw = tw_fwd(md, T, 2 * (gbase + i)); cached_i = i; }
+            const Word x = buf[lpos * C + c];
+            const Word t = md.mul_tw(buf[rpos * C + c], tw);
+            if (needL) buf[lpos * C + c] = md.add(x, t);
+            if (needR) buf[rpos * C + c] = md.sub(x, t);
+        }
+        __syncthreads();
+    }
+}
+
+// Full inverse of the forward stages on a block of size S at offset off with
+// global block index g: stages h = 1, 2, ..., S/2, each undoing
+// (lo, hi) -> (lo + w hi, lo - w hi) by ((x + y)/2, (x - y) w^-1 / 2).
+template <class Mod>
+__device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+                             int logC, uint32_t off, uint32_t S, uint64_t g) {
+    using Word = typename Mod::Word;
+    const uint32_t C = 1u << logC;
+    for (uint32_t h = 1; h < S; h <<= 1) {
+        const uint32_t two_h = h << 1;
+        const uint32_t logh = __builtin_ctz(h);
+        const uint32_t items = (S >> 1) * C;
+        const uint64_t gbase = g * (uint64_t)(S / two_h);
+        uint32_t cached_i = 0xFFFFFFFFu;
+        Word tw = 0;
+        for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+            const uint32_t c = it & (C - 1);
+            const uint32_t u = it >> logC;
+            const uint32_t i = u >> logh;
+            const uint32_t j = u & (h - 1);
+            const uint32_t lpos = off + i * two_h + j, rpos = lpos + h;
+            if (i != cached_i) { tw = tw_inv_half(md, T, 2 * (gbase + i)); cached_i = i; }
+            const Word x = buf[lpos * C + c];
+            const Word y = buf[rpos * C + c];
+            buf[lpos * C + c] = md.half(md.add(x, y));
+            buf[rpos * C + c] = md.mul_tw(md.sub(x, y), tw);
+        }
+        __syncthreads();
+    }
+}
+
+// Generalised inverse truncated transform of one block.
+//
+// On entry, a block of size M (power of two) at global index g0 has its first
+// m positions holding transform values (the polynomial B of degree < M taken
+// at w_{g0 M + s}, s < m) and positions [m, M) holding the coefficients
+// B_m..B_{M-1}, which are known.  On exit all M positions hold B's
+// coefficients.  (For an ordinary inverse TFT of length m the known
+// coefficients are zeros.)
+//
+// The recursion follows the truncation boundary down the splitting tree.  At
+// a block of size 2h with twiddle w = w_{2g}, writing C0 = lo + w hi and
+// C1 = lo - w hi for its children:
+//   m >= h: C0's h values are all known, so C0 is recovered by a full inverse;
+//           for j >= m - h the coefficient hi_j is known, so C1_j = C0_j - 2 w hi_j
+//           becomes a known coefficient of the right child, which is solved
+//           recursively with m - h known values; then (lo, hi) follow from
+//           (C0, C1) by the inverse butterfly.
+//   m <  h: for j >= m both lo_j and hi_j are known, so C0_j = lo_j + w hi_j is
+//           a known coefficient of the left child, which is solved
+//           recursively; then lo_j = C0_j - w hi_j.
+// Positions are updated in place throughout.
+template <class Mod>
+__device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+                      uint32_t M, uint32_t m, uint64_t g0) {
+    using Word = typename Mod::Word;
+    const uint32_t C = 1u << logC;
+    uint32_t lv_off[32];
+    uint32_t lv_h[32];
+    uint64_t lv_g[32];
+    bool lv_right[32];
+    int depth = 0;
+    uint32_t off = 0, size = M;
+    uint64_t g = g0;
+    while (size > 1 && m > 0 && m < size) {
+        const uint32_t h = size >> 1;
+        const Word w = tw_fwd(md, T, 2 * g);
+        lv_off[depth] = off;
+        lv_h[depth] = h;
+        lv_g[depth] = g;
+        if (m >= h) {
+            full_inverse(md, T, buf, logC, off, h, 2 * g);
+            // right child's known coefficients: C1_j = C0_j - 2 w hi_j, j in [m - h, h)
+            const uint32_t j0 = m - h;
+            const uint32_t items = (h - j0) * C;
+            for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+                const uint32_t c = it & (C - 1);
+                const uint32_t j = j0 + (it >> logC);
+                const Word c0 = buf[(off + j) * C + c];
+                const Word t = md.mul_tw(buf[(off + h + j) * C + c], w);
+                buf[(off + h + j) * C + c] = md.sub(md.sub(c0, t), t);
+            }
+            __syncthreads();
+            lv_right[depth] = true;
+            off += h;
+            g = 2 * g + 1;
+            m -= h;
+        } else {
+            // left child's known coefficients: C0_j = lo_j + w hi_j, j in [m, h)
+            const uint32_t items = (h - m) * C;
+            for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+                const uint32_t c = it & (C - 1);
+                const uint32_t j = m + (it >> logC);
+                const Word lo = buf[(off + j) * C + c];
+                const Word t = md.mul_tw(buf[(off + h + j) * C + c], w);
+                buf[(off + j) * C + c] = md.add(lo, t);
+            }
+            __syncthreads();
+            lv_right[depth] = false;
+            g = 2 * g;
+        }
+        size = h;
+        depth++;
+    }
+    if (size > 1 && m == size) full_inverse(md, T, buf, logC, off, size, g);
+    // ascend
+    for (int d = depth - 1; d >= 0; d--) {
+        const uint32_t o = lv_off[d], h = lv_h[d];
+        const uint32_t items = h * C;
+        if (lv_right[d]) {
+            const Word wi = tw_inv_half(md, T, 2 * lv_g[d]);
+            for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+                const uint32_t c = it & (C - 1);
+                const uint32_t j = it >> logC;
+                const Word x = buf[(o + j) * C + c];
+                const Word y = buf[(o + h + j) * C + c];
+                buf[(o + j) * C + c] = md.half(md.add(x, y));
+                buf[(o + h + j) * C + c] = md.mul_tw(md.sub(x, y), wi);
+            }
+        } else {
+            const Word w = tw_fwd(md, T, 2 * lv_g[d]);
+            for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+                const uint32_t c = it & (C - 1);
+                const uint32_t j = it >> logC;
+                const Word t = md.mul_tw(buf[(o + h + j) * C + c], w);
+                buf[(o + j) * C + c] = md.sub(buf[(o + j) * C + c], t);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace tft

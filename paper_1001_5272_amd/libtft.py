@@ -1,0 +1,188 @@
+"""Thin Python binding of libtft (include/libtft.h).
+
+Argument marshalling only: every step of the transform runs in the HIP
+kernels of ``libtft.so``.  PyTorch supplies device memory (tensors) and
+streams; tensors must be contiguous ``torch.uint32`` (primes below 2^31) or
+``torch.uint64`` (p = 2^64 - 2^32 + 1) on the context's device.  Functions
+carry the names of the C entry points; a failing status raises ``TftError``.
+
+There is no fallback: if ``libtft.so`` has not been built, or no GPU is
+visible, using the library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library shares)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libtft.so")
+
+TFT_OK, TFT_EINVAL, TFT_ERANGE, TFT_ENOMEM, TFT_EDEVICE, TFT_EAGAIN = 0, -1, -2, -3, -4, -5
+
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_st = ctypes.c_int
+
+# name -> (restype, argtypes); must list every function of include/libtft.h
+SIGNATURES = {
+    "tft_ctx_create": (_st, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "tft_ctx_destroy": (None, [_vp]),
+    "tft_ctx_max_log2": (ctypes.c_uint, [_vp]),
+    "tft_ctx_word_bytes": (ctypes.c_uint, [_vp]),
+    "tft_forward": (_st, [_vp, _vp, _sz, _vp]),
+    "tft_inverse": (_st, [_vp, _vp, _sz, _vp]),
+    "tft_pointwise_mul": (_st, [_vp, _vp, _vp, _sz, _vp]),
+    "poly_mul": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp, _vp]),
+    "tft_padded_forward": (_st, [_vp, _vp, _sz, _vp, _vp]),
+    "tft_padded_inverse": (_st, [_vp, _vp, _sz, _vp, _vp]),
+    "poly_mul_padded": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp, _vp, _vp]),
+    "tft_plan_info": (_st, [_vp, _sz, _vp]),
+    "tft_set_plan_override": (_st, [_vp, ctypes.c_uint]),
+    "tft_strerror": (ctypes.c_char_p, [_st]),
+}
+
+
+class TftError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("logW", ctypes.c_uint), ("W", _sz), ("a", _sz), ("b", _sz),
+                ("col_block", _sz), ("cols_per_tile", ctypes.c_uint), ("lds_bytes_col", _sz),
+                ("lds_bytes_row", _sz)]
+
+
+_lib = None
+
+
+def load():
+    """Load libtft.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1001_5272_amd/build.py "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return load().tft_strerror(status).decode()
+
+
+def _check(status: int, what: str):
+    if status != TFT_OK:
+        raise TftError(status, what)
+
+
+def _stream(stream):
+    if stream is None:
+        return _vp(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return _vp(stream.cuda_stream)
+    return _vp(int(stream))
+
+
+class Context:
+    """A context for one prime on one device (tft_ctx_create)."""
+
+    def __init__(self, p: int, g: int, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libtft needs a GPU; none is visible")
+        h = _vp()
+        _check(load().tft_ctx_create(p, g, device, ctypes.byref(h)), "tft_ctx_create")
+        self.handle = h
+        self.p, self.g, self.device = p, g, device
+        self.word_bytes = load().tft_ctx_word_bytes(h)
+        self.max_log2 = load().tft_ctx_max_log2(h)
+        self.dtype = torch.uint32 if self.word_bytes == 4 else torch.uint64
+
+    def close(self):
+        if self.handle:
+            load().tft_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _t(self, x, name):
+        if not isinstance(x, torch.Tensor) or x.dtype != self.dtype or not x.is_cuda or not x.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous {self.dtype} CUDA tensor")
+        return _vp(x.data_ptr())
+
+
+def tft_ctx_create(p: int, g: int, device: int = 0) -> Context:
+    return Context(p, g, device)
+
+
+def tft_ctx_destroy(ctx: Context):
+    ctx.close()
+
+
+def tft_forward(ctx: Context, X, n: int | None = None, stream=None):
+    n = X.numel() if n is None else n
+    _check(load().tft_forward(ctx.handle, ctx._t(X, "X"), n, _stream(stream)), "tft_forward")
+    return X
+
+
+def tft_inverse(ctx: Context, X, n: int | None = None, stream=None):
+    n = X.numel() if n is None else n
+    _check(load().tft_inverse(ctx.handle, ctx._t(X, "X"), n, _stream(stream)), "tft_inverse")
+    return X
+
+
+def tft_pointwise_mul(ctx: Context, X, Y, n: int | None = None, stream=None):
+    n = X.numel() if n is None else n
+    _check(load().tft_pointwise_mul(ctx.handle, ctx._t(X, "X"), ctx._t(Y, "Y"), n, _stream(stream)),
+           "tft_pointwise_mul")
+    return X
+
+
+def poly_mul(ctx: Context, A, B, X, Y=None, stream=None):
+    y = ctx._t(Y, "Y") if Y is not None else _vp(0)
+    _check(load().poly_mul(ctx.handle, ctx._t(A, "A"), A.numel(), ctx._t(B, "B"), B.numel(), ctx._t(X, "X"), y,
+                           _stream(stream)), "poly_mul")
+    return X
+
+
+def tft_padded_forward(ctx: Context, X, Xpad, n: int | None = None, stream=None):
+    n = X.numel() if n is None else n
+    _check(load().tft_padded_forward(ctx.handle, ctx._t(X, "X"), n, ctx._t(Xpad, "Xpad"), _stream(stream)),
+           "tft_padded_forward")
+    return X
+
+
+def tft_padded_inverse(ctx: Context, X, Xpad, n: int | None = None, stream=None):
+    n = X.numel() if n is None else n
+    _check(load().tft_padded_inverse(ctx.handle, ctx._t(X, "X"), n, ctx._t(Xpad, "Xpad"), _stream(stream)),
+           "tft_padded_inverse")
+    return X
+
+
+def poly_mul_padded(ctx: Context, A, B, X, Apad, Bpad, stream=None):
+    _check(load().poly_mul_padded(ctx.handle, ctx._t(A, "A"), A.numel(), ctx._t(B, "B"), B.numel(),
+                                  ctx._t(X, "X"), ctx._t(Apad, "Apad"), ctx._t(Bpad, "Bpad"), _stream(stream)),
+           "poly_mul_padded")
+    return X
+
+
+def tft_plan_info(ctx: Context, n: int) -> dict:
+    d = PlanDesc()
+    _check(load().tft_plan_info(ctx.handle, n, ctypes.byref(d)), "tft_plan_info")
+    return {f: getattr(d, f) for f, _ in PlanDesc._fields_}
+
+
+def tft_set_plan_override(ctx: Context, logW: int):
+    _check(load().tft_set_plan_override(ctx.handle, logW), "tft_set_plan_override")

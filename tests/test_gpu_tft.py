@@ -1,0 +1,130 @@
+"""GPU parity: libtft's forward/inverse TFT and product against the oracle,
+element by element, bit-exact (all arithmetic is exact modulo p, so the
+tolerance is zero).  Inputs are seeded uniform residues (synth)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import PRIMES
+from gpu_util import gpu_forward, gpu_inverse, gpu_mul
+
+pytestmark = pytest.mark.gpu
+
+libtft = pytest.importorskip("paper_1001_5272_amd.libtft")
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    out = {name: libtft.Context(*PRIMES[name]) for name in
+           ["p998244353", "goldilocks", "p12289", "p7681", "p2013265921", "p469762049", "p1811939329"]}
+    yield out
+    for c in out.values():
+        c.close()
+
+
+def check_roundtrip(ctx, p, g, n, seed, direct=False):
+    F = synth.residues(p, n, seed)
+    X = gpu_forward(ctx, F)
+    ref = oracle.tft_direct(p, g, F) if direct else oracle.fft_padded(p, g, F)
+    bad = np.nonzero(X != ref)[0]
+    assert len(bad) == 0, f"p={p} n={n}: {len(bad)} forward mismatches, first at {bad[:5]}"
+    back = gpu_inverse(ctx, X)
+    bad = np.nonzero(back != F)[0]
+    assert len(bad) == 0, f"p={p} n={n}: {len(bad)} inverse mismatches, first at {bad[:5]}"
+
+
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+def test_every_small_length(ctxs, name):
+    p, g = PRIMES[name]
+    ctx = ctxs[name]
+    print(f"[gpu] every n in 1..1100 for {name}", flush=True)
+    for n in range(1, 1101):
+        check_roundtrip(ctx, p, g, n, seed=n, direct=(n <= 64))
+
+
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+def test_single_workgroup_sizes(ctxs, name):
+    p, g = PRIMES[name]
+    ctx = ctxs[name]
+    for n in [1536, 2047, 2048, 2049, 2499, 3000, 4095, 4096, 6000, 8191, 8192]:
+        print(f"[gpu] {name} n={n}", flush=True)
+        check_roundtrip(ctx, p, g, n, seed=7 * n)
+
+
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("logW", [3, 4, 5, 6, 7])
+def test_two_pass_forced_small(ctxs, name, logW):
+    # the two-pass schedule at sizes the oracle handles quickly: many column
+    # tiles, partial tiles and every kind of last row (b = 0, 1, W-1, other)
+    p, g = PRIMES[name]
+    ctx = ctxs[name]
+    C = 16 if ctx.word_bytes == 4 else 8
+    if (1 << logW) < C:
+        pytest.skip("W below one column tile")
+    libtft.tft_set_plan_override(ctx, logW)
+    try:
+        W = 1 << logW
+        ns = sorted({W + 1, 2 * W - 1, 2 * W, 3 * W + 1, 5 * W - 1, 17 * W, 17 * W + 3, 33 * W + W // 2,
+                     100 * W + 7, 1000, 2499, 4097})
+        for n in ns:
+            if n <= W:
+                continue
+            print(f"[gpu] {name} logW={logW} n={n}", flush=True)
+            check_roundtrip(ctx, p, g, n, seed=n + 31 * logW)
+    finally:
+        libtft.tft_set_plan_override(ctx, 0)
+
+
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+def test_two_pass_planner_sizes(ctxs, name):
+    p, g = PRIMES[name]
+    ctx = ctxs[name]
+    for n in [8193, 10000, 16383, 16384, 16385, 40000, 65535, 65536, 65537, 100003, 262145]:
+        plan = libtft.tft_plan_info(ctx, n)
+        print(f"[gpu] {name} n={n} plan={plan}", flush=True)
+        check_roundtrip(ctx, p, g, n, seed=3 * n)
+
+
+@pytest.mark.parametrize("name", ["p12289", "p7681", "p2013265921", "p469762049", "p1811939329"])
+def test_other_primes(ctxs, name):
+    p, g = PRIMES[name]
+    ctx = ctxs[name]
+    v = oracle.two_adic(p)
+    top = 1 << min(v, 14)
+    for n in [1, 2, 3, 5, 100, 255, 256, 257, 1000, top - 1, top, 5000, 20001]:
+        if (n - 1).bit_length() > v:
+            continue
+        print(f"[gpu] {name} n={n}", flush=True)
+        check_roundtrip(ctx, p, g, n, seed=n + 5)
+
+
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+def test_products(ctxs, name):
+    p, g = PRIMES[name]
+    ctx = ctxs[name]
+    for m, nb in [(1, 1), (1, 7), (5, 1), (3, 4), (1000, 1500), (4096, 4097), (5000, 3000), (30000, 40001)]:
+        print(f"[gpu] {name} product {m}x{nb}", flush=True)
+        A = synth.residues(p, m, 100 + m)
+        B = synth.residues(p, nb, 200 + nb)
+        C = gpu_mul(ctx, A, B)
+        ref = oracle.mul_schoolbook(p, A, B) if m * nb <= 4_000_000 else oracle.mul_padded(p, g, A, B)
+        assert (C == ref).all(), f"product {m}x{nb} mismatches at {np.nonzero(C != ref)[0][:5]}"
+
+
+def test_rejects_bad_arguments(ctxs):
+    import torch
+    ctx = ctxs["p998244353"]
+    X = torch.zeros(16, dtype=torch.uint32, device="cuda")
+    with pytest.raises(libtft.TftError) as e:
+        libtft.tft_forward(ctx, X, 0)
+    assert e.value.status == libtft.TFT_EINVAL
+    big = torch.zeros(1, dtype=torch.uint32, device="cuda")
+    with pytest.raises(libtft.TftError) as e:
+        libtft.tft_forward(ctx, big, (1 << 23) + 1)   # needs a root of order 2^24
+    assert e.value.status == libtft.TFT_ERANGE
+    with pytest.raises(libtft.TftError):
+        libtft.Context(998244353, 4)                   # 4 is a square: not a generator
