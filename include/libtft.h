@@ -122,6 +122,32 @@ tft_status tft_plan_info(tft_ctx* ctx, size_t n, tft_plan_desc* out);
  * Lengths whose tiles would not fit in LDS then return TFT_ERANGE. */
 tft_status tft_set_plan_override(tft_ctx* ctx, unsigned logW);
 
+/* Measurement mode.  While enabled, each kernel a context launches is
+ * bracketed by two HIP events recorded on the caller's stream, so that a
+ * benchmark can report per-kernel durations measured live (the events are
+ * created on first use and kept by the context; this mode is for
+ * measurement, not for production loops).  tft_timing_read waits for the
+ * events recorded so far and returns, for kernel `id`, the number of launches
+ * and their summed duration in milliseconds since the last tft_timing_reset. */
+typedef enum {
+    TFT_K_SMALL_FWD = 0,   /* single-workgroup forward */
+    TFT_K_SMALL_INV,       /* single-workgroup inverse */
+    TFT_K_SMALL_MUL,       /* single-workgroup product */
+    TFT_K_COL_FWD,         /* forward column pass (large-stride layers) */
+    TFT_K_ROW_FWD,         /* forward row pass (small-stride layers) and last row */
+    TFT_K_ROW_INV,         /* inverse row pass */
+    TFT_K_COL_INV_SHORT,   /* inverse columns c >= b, re-deriving the extra evaluations */
+    TFT_K_LAST_INV,        /* inverse of the partial last row */
+    TFT_K_COL_INV_LONG,    /* inverse columns c < b */
+    TFT_K_POINTWISE,       /* pointwise product */
+    TFT_K_COPY,            /* zero-extending copy */
+    TFT_K_COUNT
+} tft_kernel_id;
+tft_status tft_timing_enable(tft_ctx* ctx, int on);
+tft_status tft_timing_read(tft_ctx* ctx, int id, uint64_t* launches, double* total_ms);
+tft_status tft_timing_reset(tft_ctx* ctx);
+const char* tft_kernel_name(int id);
+
 /* Human-readable name of a status code. */
 const char* tft_strerror(tft_status s);
 

@@ -75,6 +75,13 @@ struct tft_ctx {
     void* tables;        // f1 | f2 | i1 | i2
     size_t n1, n2;       // entries per level
     void* scratch;       // V_c area
+    // measurement mode (tft_timing_*): events bracketing each launch
+    bool timing;
+    struct Rec { int kid; hipEvent_t e0, e1; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    uint64_t launches[TFT_K_COUNT];
+    double total_ms[TFT_K_COUNT];
 };
 
 namespace {
@@ -92,6 +99,35 @@ struct DeviceGuard {
 };
 
 inline tft_status launch_status() { return hipGetLastError() == hipSuccess ? TFT_OK : TFT_EDEVICE; }
+
+hipEvent_t take_event(tft_ctx* ctx) {
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Every kernel goes through here; in measurement mode the launch is bracketed
+// by two events on its stream.
+template <typename Kernel, typename... Args>
+void launch(tft_ctx* ctx, int kid, Kernel kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+            Args... args) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->timing) {
+        e0 = take_event(ctx);
+        e1 = take_event(ctx);
+        if (e0 && e1) (void)hipEventRecord(e0, st);
+    }
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+    if (e0 && e1) {
+        (void)hipEventRecord(e1, st);
+        ctx->recs.push_back({kid, e0, e1});
+    }
+}
 
 unsigned small_max_log2(unsigned wbytes) { return wbytes == 4 ? 13 : 12; }
 
@@ -177,21 +213,21 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
     if (P.kind < 0) return TFT_ERANGE;
     if (P.kind == 0) {
         if (src != X) {
-            hipLaunchKernelGGL(tft::k_copy_pad<Word>, dim3(1), dim3(kThreads), 0, st, X, n, src, n_src);
+            launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3(1), dim3(kThreads), 0, st, X, n, src, n_src);
         }
-        hipLaunchKernelGGL(tft::k_small_fwd<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, X, (uint32_t)n,
+        launch(ctx, TFT_K_SMALL_FWD, tft::k_small_fwd<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, X, (uint32_t)n,
                            P.M);
         return launch_status();
     }
     Word* V = reinterpret_cast<Word*>(ctx->scratch);
     const uint32_t tiles = (uint32_t)(P.W >> P.logC);
     if (P.logC == 3)
-        hipLaunchKernelGGL((tft::k_col_fwd<Mod, 3>), dim3(tiles), dim3(kThreads), P.lds_col, st, md, T, src, n_src, X,
+        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(kThreads), P.lds_col, st, md, T, src, n_src, X,
                            n, P.logW, (uint32_t)P.a, (uint32_t)P.b, P.Lout, P.M, V, tiles);
     else
-        hipLaunchKernelGGL((tft::k_col_fwd<Mod, 4>), dim3(tiles), dim3(kThreads), P.lds_col, st, md, T, src, n_src, X,
+        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(kThreads), P.lds_col, st, md, T, src, n_src, X,
                            n, P.logW, (uint32_t)P.a, (uint32_t)P.b, P.Lout, P.M, V, tiles);
-    hipLaunchKernelGGL(tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(kThreads), P.lds_row, st, md,
+    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(kThreads), P.lds_row, st, md,
                        T, X, P.logW, (uint32_t)P.a, (uint32_t)P.b, V);
     return launch_status();
 }
@@ -206,30 +242,33 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     const Plan P = make_plan(ctx, n);
     if (P.kind < 0) return TFT_ERANGE;
     if (P.kind == 0) {
-        if (Y) hipLaunchKernelGGL(tft::k_pointwise<Mod>, dim3(1), dim3(kThreads), 0, st, md, X, Y, n);
-        hipLaunchKernelGGL(tft::k_small_inv<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, X, (uint32_t)n,
+        if (Y) launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3(1), dim3(kThreads), 0, st, md, X, Y, n);
+        launch(ctx, TFT_K_SMALL_INV, tft::k_small_inv<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, X, (uint32_t)n,
                            P.M);
         return launch_status();
     }
     Word* V = reinterpret_cast<Word*>(ctx->scratch);
     const uint32_t C = 1u << P.logC;
     const uint32_t tiles_all = (uint32_t)(P.W >> P.logC);
-    hipLaunchKernelGGL(tft::k_row_inv<Mod>, dim3((uint32_t)P.a), dim3(kThreads), P.lds_row, st, md, T, X, Y, P.logW);
+    tft::PieceList pieces{};
+    pieces.count = P.b ? tft::gitft_pieces((uint32_t)P.W, (uint32_t)P.b, P.a, pieces.p) : 0;
+    launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3((uint32_t)P.a + pieces.count), dim3(kThreads), P.lds_row, st,
+           md, T, X, Y, P.logW, (uint32_t)P.a, pieces);
     // columns c >= b
     {
         const uint32_t t0 = (uint32_t)(P.b / C);
         const uint32_t nt = tiles_all - t0;
         auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
-        hipLaunchKernelGGL(kern, dim3(nt), dim3(kThreads), P.lds_col, st, md, T, X, P.logW, (uint32_t)P.a,
-                           (uint32_t)P.b, P.M, V, 0, t0, nt);
+        launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(kThreads), P.lds_col, st, md, T, X, P.logW,
+               (uint32_t)P.a, (uint32_t)P.b, P.M, V, 0, t0, nt);
     }
     if (P.b) {
-        hipLaunchKernelGGL(tft::k_last_inv<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, X, Y, P.logW,
-                           (uint32_t)P.a, (uint32_t)P.b, (const Word*)V);
+        launch(ctx, TFT_K_LAST_INV, tft::k_last_inv<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, X, P.logW,
+               (uint32_t)P.a, (uint32_t)P.b, (const Word*)V);
         const uint32_t nt = (uint32_t)((P.b + C - 1) / C);
         auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
-        hipLaunchKernelGGL(kern, dim3(nt), dim3(kThreads), P.lds_col, st, md, T, X, P.logW, (uint32_t)P.a,
-                           (uint32_t)P.b, P.M, V, 1, 0u, nt);
+        launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(kThreads), P.lds_col, st, md, T, X, P.logW,
+               (uint32_t)P.a, (uint32_t)P.b, P.M, V, 1, 0u, nt);
     }
     return launch_status();
 }
@@ -240,7 +279,7 @@ tft_status pointwise_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mo
     const Mod& md = mod_of<Mod>(ctx);
     uint64_t blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(tft::k_pointwise<Mod>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, md, X, Y, n);
+    launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, md, X, Y, n);
     return launch_status();
 }
 
@@ -253,7 +292,7 @@ tft_status mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const
     if (P.kind == 0 && 2 * P.lds_row <= kLdsHard - 32 * 1024) {
         const Mod& md = mod_of<Mod>(ctx);
         const auto T = tables_of<typename Mod::Word>(ctx);
-        hipLaunchKernelGGL(tft::k_small_mul<Mod>, dim3(1), dim3(kThreads), 2 * P.lds_row, st, md, T, A, (uint32_t)m,
+        launch(ctx, TFT_K_SMALL_MUL, tft::k_small_mul<Mod>, dim3(1), dim3(kThreads), 2 * P.lds_row, st, md, T, A, (uint32_t)m,
                            B, (uint32_t)nb, X, P.M);
         return launch_status();
     }
@@ -272,12 +311,12 @@ tft_status padded_forward_impl(tft_ctx* ctx, typename Mod::Word* X, uint64_t n, 
     const uint64_t N = pow2ceil(n);
     uint64_t blocks = (N + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, Xp, N, (const Word*)X, n);
+    launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, Xp, N, (const Word*)X, n);
     tft_status s = forward_impl<Mod>(ctx, Xp, N, Xp, N, st);
     if (s != TFT_OK) return s;
     blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, X, n, (const Word*)Xp, n);
+    launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, X, n, (const Word*)Xp, n);
     return launch_status();
 }
 
@@ -290,7 +329,7 @@ tft_status padded_inverse_impl(tft_ctx* ctx, typename Mod::Word* X, uint64_t n, 
     if (s != TFT_OK) return s;
     uint64_t blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, X, n, (const Word*)Xp, n);
+    launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, X, n, (const Word*)Xp, n);
     return launch_status();
 }
 
@@ -303,28 +342,27 @@ tft_status padded_mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m
     const uint64_t N = pow2ceil(r);
     uint64_t blocks = (N + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, Ap, N, A, m);
-    hipLaunchKernelGGL(tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, Bp, N, B, nb);
+    launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, Ap, N, A, m);
+    launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, Bp, N, B, nb);
     tft_status s = forward_impl<Mod>(ctx, Ap, N, Ap, N, st);
     if (s == TFT_OK) s = forward_impl<Mod>(ctx, Bp, N, Bp, N, st);
     if (s == TFT_OK) s = inverse_impl<Mod>(ctx, Ap, Bp, N, st);
     if (s != TFT_OK) return s;
     blocks = (r + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, X, r, (const Word*)Ap, r);
+    launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, X, r, (const Word*)Ap, r);
     return launch_status();
 }
 
 // -------------------------------------------------------------- tables
 template <class Word>
 std::vector<Word> build_tables(uint64_t p, uint64_t g, unsigned v, size_t n1, size_t n2, bool montgomery) {
-    // f1[s] = w_s (s < n1), f2[h] = w_{h 2^B1} (h < n2), i1[s] = w_s^-1 / 2, i2[h] = w_{h 2^B1}^-1
+    // f1[s] = w_s (s < n1), f2[h] = w_{h 2^B1} (h < n2), i1[s] = w_s^-1, i2[h] = w_{h 2^B1}^-1
     std::vector<Word> out(2 * (n1 + n2), Word(0));
     auto root = [&](unsigned k) { return powmod_h(g, (p - 1) >> k, p); };
     auto enc = [&](uint64_t x) -> Word {
         return montgomery ? (Word)(((u128)x << 32) % p) : (Word)x;
     };
-    const uint64_t inv2 = (p + 1) / 2;
     const unsigned k1 = v < (unsigned)kB1 ? v : (unsigned)kB1;
     const uint64_t lim1 = 1ull << k1;
     {
@@ -336,8 +374,7 @@ std::vector<Word> build_tables(uint64_t p, uint64_t g, unsigned v, size_t n1, si
         for (uint64_t s = 0; s < lim1; s++) {
             const uint64_t w = pw[rev_bits(s, k1)];
             out[s] = enc(w);
-            const uint64_t wi = powmod_h(w, p - 2, p);
-            out[n1 + n2 + s] = enc(mulmod_h(wi, inv2, p));
+            out[n1 + n2 + s] = enc(powmod_h(w, p - 2, p));
         }
     }
     if (n2 > 1) {
@@ -422,6 +459,8 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
     c->v = v < kMaxLog2 ? v : kMaxLog2;
     c->wbytes = wide ? 8 : 4;
     c->override_logW = 0;
+    c->timing = false;
+    for (int i = 0; i < TFT_K_COUNT; i++) { c->launches[i] = 0; c->total_ms[i] = 0.0; }
     if (!wide) {
         uint32_t inv = 1;                          // p^-1 mod 2^32 by Newton iteration
         for (int i = 0; i < 5; i++) inv *= 2u - (uint32_t)p * inv;
@@ -463,6 +502,8 @@ void tft_ctx_destroy(tft_ctx* ctx) {
     DeviceGuard guard(ctx->device);
     (void)hipFree(ctx->tables);
     (void)hipFree(ctx->scratch);
+    for (auto& r : ctx->recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -583,6 +624,51 @@ tft_status tft_set_plan_override(tft_ctx* ctx, unsigned logW) {
     if (!ctx || logW > 16) return TFT_EINVAL;
     ctx->override_logW = logW;
     return TFT_OK;
+}
+
+tft_status tft_timing_enable(tft_ctx* ctx, int on) {
+    if (!ctx) return TFT_EINVAL;
+    ctx->timing = on != 0;
+    return TFT_OK;
+}
+
+static tft_status timing_collect(tft_ctx* ctx) {
+    tft_status s = TFT_OK;
+    for (auto& r : ctx->recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess)
+            s = TFT_EDEVICE;
+        ctx->launches[r.kid] += 1;
+        ctx->total_ms[r.kid] += ms;
+        ctx->pool.push_back(r.e0);
+        ctx->pool.push_back(r.e1);
+    }
+    ctx->recs.clear();
+    return s;
+}
+
+tft_status tft_timing_read(tft_ctx* ctx, int id, uint64_t* launches, double* total_ms) {
+    if (!ctx || id < 0 || id >= TFT_K_COUNT || !launches || !total_ms) return TFT_EINVAL;
+    DeviceGuard guard(ctx->device);
+    tft_status s = timing_collect(ctx);
+    *launches = ctx->launches[id];
+    *total_ms = ctx->total_ms[id];
+    return s;
+}
+
+tft_status tft_timing_reset(tft_ctx* ctx) {
+    if (!ctx) return TFT_EINVAL;
+    DeviceGuard guard(ctx->device);
+    tft_status s = timing_collect(ctx);
+    for (int i = 0; i < TFT_K_COUNT; i++) { ctx->launches[i] = 0; ctx->total_ms[i] = 0.0; }
+    return s;
+}
+
+const char* tft_kernel_name(int id) {
+    static const char* names[TFT_K_COUNT] = {"small_fwd", "small_inv", "small_mul", "col_fwd", "row_fwd",
+                                             "row_inv", "col_inv_short", "last_inv", "col_inv_long",
+                                             "pointwise", "copy_pad"};
+    return (id >= 0 && id < TFT_K_COUNT) ? names[id] : "unknown";
 }
 
 }  // extern "C"

@@ -22,8 +22,8 @@ namespace tft {
 
 // ----------------------------------------------------------------- tables
 // Two-level root tables, independent of the transform length:
-//   w_s = f1[s mod 2^B1] * f2[s >> B1]          (forward)
-//   w_s^-1 / 2 = i1[s mod 2^B1] * i2[s >> B1]   (inverse, halving folded in)
+//   w_s    = f1[s mod 2^B1] * f2[s >> B1]
+//   w_s^-1 = i1[s mod 2^B1] * i2[s >> B1]
 // For 31-bit primes the entries are stored in Montgomery form (x 2^32).
 constexpr int kB1 = 15;
 constexpr uint32_t kMask1 = (1u << kB1) - 1;
@@ -111,90 +111,185 @@ template <class Mod>
 __device__ __forceinline__ typename Mod::Word tw_fwd(const Mod& md, const Tables<typename Mod::Word>& T,
                                                       uint64_t s) {
     typename Mod::Word t = T.f1[s & kMask1];
-    uint64_t h = s >> kB1;
+    const uint64_t h = s >> kB1;
     if (h) t = md.tw_mul_tw(t, T.f2[h]);
     return t;
 }
 
 template <class Mod>
-__device__ __forceinline__ typename Mod::Word tw_inv_half(const Mod& md, const Tables<typename Mod::Word>& T,
-                                                           uint64_t s) {
+__device__ __forceinline__ typename Mod::Word tw_inv(const Mod& md, const Tables<typename Mod::Word>& T,
+                                                      uint64_t s) {
     typename Mod::Word t = T.i1[s & kMask1];
-    uint64_t h = s >> kB1;
+    const uint64_t h = s >> kB1;
     if (h) t = md.tw_mul_tw(t, T.i2[h]);
     return t;
 }
+
+// ------------------------------------------------------- register units
+// A radix-2^S unit holds 2^S values x[t] taken at a fixed stride inside one
+// block of size 2h (global block index G) and applies the S stages h, h/2,
+// ..., h/2^(S-1) to them in registers.  At stage s the unit meets 2^s
+// sub-blocks, with global indices G 2^s + q, whose twiddle is w_{2(G 2^s + q)}.
+template <class Mod, int S>
+struct Unit {
+    using Word = typename Mod::Word;
+    static constexpr int R = 1 << S;
+    Word tw[R - 1];     // twiddle of sub-block q at stage s is tw[(1 << s) - 1 + q]
+    uint64_t G = ~0ull;
+
+    __device__ __forceinline__ void load_fwd(const Mod& md, const Tables<Word>& T, uint64_t g) {
+        if (g == G) return;
+        G = g;
+#pragma unroll
+        for (int s = 0; s < S; s++)
+#pragma unroll
+            for (int q = 0; q < (1 << s); q++) tw[(1 << s) - 1 + q] = tw_fwd(md, T, 2 * ((g << s) + q));
+    }
+    __device__ __forceinline__ void load_inv(const Mod& md, const Tables<Word>& T, uint64_t g) {
+        if (g == G) return;
+        G = g;
+#pragma unroll
+        for (int s = 0; s < S; s++)
+#pragma unroll
+            for (int q = 0; q < (1 << s); q++) tw[(1 << s) - 1 + q] = tw_inv(md, T, 2 * ((g << s) + q));
+    }
+    // forward: (a, b) -> (a + w b, a - w b), stages s = 0 .. S-1
+    __device__ __forceinline__ void forward(const Mod& md, Word (&x)[R]) const {
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            const int dist = R >> (s + 1);
+#pragma unroll
+            for (int q = 0; q < (1 << s); q++) {
+                const Word w = tw[(1 << s) - 1 + q];
+#pragma unroll
+                for (int t = 0; t < dist; t++) {
+                    const int a = q * 2 * dist + t, b = a + dist;
+                    const Word v = md.mul_tw(x[b], w);
+                    const Word u = x[a];
+                    x[a] = md.add(u, v);
+                    x[b] = md.sub(u, v);
+                }
+            }
+        }
+    }
+    // inverse: (a, b) -> ((a + b)/2, (a - b) w^-1 / 2), stages s = S-1 .. 0
+    __device__ __forceinline__ void inverse(const Mod& md, Word (&x)[R]) const {
+#pragma unroll
+        for (int s = S - 1; s >= 0; s--) {
+            const int dist = R >> (s + 1);
+#pragma unroll
+            for (int q = 0; q < (1 << s); q++) {
+                const Word w = tw[(1 << s) - 1 + q];
+#pragma unroll
+                for (int t = 0; t < dist; t++) {
+                    const int a = q * 2 * dist + t, b = a + dist;
+                    const Word u = x[a], v = x[b];
+                    x[a] = md.half(md.add(u, v));
+                    x[b] = md.mul_tw(md.half(md.sub(u, v)), w);
+                }
+            }
+        }
+    }
+};
 
 // ------------------------------------------------------- LDS block views
 // A tile in LDS holds C interleaved vectors ("lanes"): element d of lane c is
 // buf[d * C + c].  Rows use C = 1.  All routines are called by every thread of
 // the workgroup and end with a barrier.
 
-// Pruned forward transform.  The block at the root has size M (a power of
-// two) and global block index g0 (the root is F mod (x^M - w_{g0})).  Only the
-// output positions in [out_lo, out_hi) are produced; a butterfly whose two
-// halves feed no wanted output is skipped and a half that feeds none is not
-// written.  Positions outside the wanted range end with unspecified values.
-template <class Mod>
-__device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
-                            int logC, uint32_t M, uint32_t out_lo, uint32_t out_hi, uint64_t g0) {
+// One group of S forward stages starting at half-size h over the blocks of
+// size 2h that meet the wanted outputs [out_lo, out_hi).
+template <class Mod, int S>
+__device__ __forceinline__ void dif_group(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+                                          int logC, uint32_t M, uint32_t h, uint32_t out_lo, uint32_t out_hi,
+                                          uint64_t g0) {
     using Word = typename Mod::Word;
+    constexpr int R = 1 << S;
     const uint32_t C = 1u << logC;
-    for (uint32_t h = M >> 1; h >= 1; h >>= 1) {
-        const uint32_t two_h = h << 1;
-        const uint32_t i_lo = out_lo / two_h;
-        const uint32_t i_hi = (out_hi - 1) / two_h;
-        const uint32_t logh = __builtin_ctz(h);
-        const uint32_t items = (i_hi - i_lo + 1) * h * C;
-        const uint64_t gbase = g0 * (uint64_t)(M / two_h);   // global index of local block 0
-        uint32_t cached_i = 0xFFFFFFFFu;
-        Word tw = 0;
-        for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
-            const uint32_t c = it & (C - 1);
-            const uint32_t u = it >> logC;
-            const uint32_t i = i_lo + (u >> logh);
-            const uint32_t j = u & (h - 1);
-            const uint32_t lpos = i * two_h + j, rpos = lpos + h;
-            const bool needL = (i * two_h < out_hi) && (i * two_h + h > out_lo);
-            const bool needR = (i * two_h + h < out_hi) && (i * two_h + two_h > out_lo);
-            if (i != cached_i) { tw = tw_fwd(md, T, 2 * (gbase + i)); cached_i = i; }
-            const Word x = buf[lpos * C + c];
-            const Word t = md.mul_tw(buf[rpos * C + c], tw);
-            if (needL) buf[lpos * C + c] = md.add(x, t);
-            if (needR) buf[rpos * C + c] = md.sub(x, t);
-        }
-        __syncthreads();
+    const uint32_t q = h >> (S - 1);            // element stride inside a unit = units per block
+    const uint32_t logq = __builtin_ctz(q);
+    const uint32_t two_h = h << 1;
+    const uint32_t i_lo = out_lo / two_h, i_hi = (out_hi - 1) / two_h;
+    const uint32_t items = ((i_hi - i_lo + 1) << logq) << logC;
+    const uint64_t gbase = g0 * (uint64_t)(M / two_h);
+    Unit<Mod, S> un;
+    for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+        const uint32_t c = it & (C - 1);
+        const uint32_t u = it >> logC;
+        const uint32_t i = i_lo + (u >> logq);
+        const uint32_t j = u & (q - 1);
+        const uint32_t base = i * two_h + j;
+        Word x[R];
+#pragma unroll
+        for (int t = 0; t < R; t++) x[t] = buf[(base + t * q) * C + c];
+        un.load_fwd(md, T, gbase + i);
+        un.forward(md, x);
+#pragma unroll
+        for (int t = 0; t < R; t++) buf[(base + t * q) * C + c] = x[t];
     }
+    __syncthreads();
 }
 
-// Full inverse of the forward stages on a block of size S at offset off with
-// global block index g: stages h = 1, 2, ..., S/2, each undoing
-// (lo, hi) -> (lo + w hi, lo - w hi) by ((x + y)/2, (x - y) w^-1 / 2).
+// Forward transform of the block of size M at global index g0 (the block is
+// F mod (x^M - w_{g0})); only blocks meeting [out_lo, out_hi) are computed, so
+// positions outside that range end with unspecified values.
 template <class Mod>
-__device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
-                             int logC, uint32_t off, uint32_t S, uint64_t g) {
+__device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+                            uint32_t M, uint32_t out_lo, uint32_t out_hi, uint64_t g0) {
+    uint32_t h = M >> 1;
+    while (h >= 4) {
+        dif_group<Mod, 3>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
+        h >>= 3;
+    }
+    if (h == 2) dif_group<Mod, 2>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
+    if (h == 1) dif_group<Mod, 1>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
+}
+
+// One group of S inverse stages ending at half-size h (stages h/2^(S-1) .. h)
+// over every block of size 2h inside [off, off + Sz).
+template <class Mod, int S>
+__device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+                                          int logC, uint32_t off, uint32_t Sz, uint32_t h, uint64_t g) {
     using Word = typename Mod::Word;
+    constexpr int R = 1 << S;
     const uint32_t C = 1u << logC;
-    for (uint32_t h = 1; h < S; h <<= 1) {
-        const uint32_t two_h = h << 1;
-        const uint32_t logh = __builtin_ctz(h);
-        const uint32_t items = (S >> 1) * C;
-        const uint64_t gbase = g * (uint64_t)(S / two_h);
-        uint32_t cached_i = 0xFFFFFFFFu;
-        Word tw = 0;
-        for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
-            const uint32_t c = it & (C - 1);
-            const uint32_t u = it >> logC;
-            const uint32_t i = u >> logh;
-            const uint32_t j = u & (h - 1);
-            const uint32_t lpos = off + i * two_h + j, rpos = lpos + h;
-            if (i != cached_i) { tw = tw_inv_half(md, T, 2 * (gbase + i)); cached_i = i; }
-            const Word x = buf[lpos * C + c];
-            const Word y = buf[rpos * C + c];
-            buf[lpos * C + c] = md.half(md.add(x, y));
-            buf[rpos * C + c] = md.mul_tw(md.sub(x, y), tw);
-        }
-        __syncthreads();
+    const uint32_t q = h >> (S - 1);
+    const uint32_t logq = __builtin_ctz(q);
+    const uint32_t two_h = h << 1;
+    const uint32_t items = (Sz >> S) << logC;   // one unit per R elements
+    const uint64_t gbase = g * (uint64_t)(Sz / two_h);
+    Unit<Mod, S> un;
+    for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+        const uint32_t c = it & (C - 1);
+        const uint32_t u = it >> logC;
+        const uint32_t i = u >> logq;
+        const uint32_t j = u & (q - 1);
+        const uint32_t base = off + i * two_h + j;
+        Word x[R];
+#pragma unroll
+        for (int t = 0; t < R; t++) x[t] = buf[(base + t * q) * C + c];
+        un.load_inv(md, T, gbase + i);
+        un.inverse(md, x);
+#pragma unroll
+        for (int t = 0; t < R; t++) buf[(base + t * q) * C + c] = x[t];
+    }
+    __syncthreads();
+}
+
+// Full inverse of the forward stages on the block of size Sz at offset off with
+// global block index g: stages 1, 2, ..., Sz/2.
+template <class Mod>
+__device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+                             uint32_t off, uint32_t Sz, uint64_t g) {
+    if (Sz < 2) return;
+    const uint32_t L = __builtin_ctz(Sz);     // number of stages
+    uint32_t done = 0;                         // stages 2^0 .. 2^(done-1) finished
+    const uint32_t first = L % 3;              // leading short group so that the rest are radix-8
+    if (first == 1) { dit_group<Mod, 1>(md, T, buf, logC, off, Sz, 1, g); done = 1; }
+    if (first == 2) { dit_group<Mod, 2>(md, T, buf, logC, off, Sz, 2, g); done = 2; }
+    while (done < L) {
+        dit_group<Mod, 3>(md, T, buf, logC, off, Sz, 1u << (done + 2), g);
+        done += 3;
     }
 }
 
@@ -218,16 +313,18 @@ __device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T,
 //   m <  h: for j >= m both lo_j and hi_j are known, so C0_j = lo_j + w hi_j is
 //           a known coefficient of the left child, which is solved
 //           recursively; then lo_j = C0_j - w hi_j.
-// Positions are updated in place throughout.
+// The full inverses act on disjoint dyadic pieces of [0, m) and read only
+// known values, so a caller may run them beforehand (in parallel, elsewhere)
+// and pass skip_full = true.
 template <class Mod>
 __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
-                      uint32_t M, uint32_t m, uint64_t g0) {
+                      uint32_t M, uint32_t m, uint64_t g0, bool skip_full = false) {
     using Word = typename Mod::Word;
     const uint32_t C = 1u << logC;
-    uint32_t lv_off[32];
-    uint32_t lv_h[32];
-    uint64_t lv_g[32];
-    bool lv_right[32];
+    uint32_t lv_off[20];
+    uint32_t lv_h[20];
+    uint64_t lv_g[20];
+    uint32_t right_mask = 0;
     int depth = 0;
     uint32_t off = 0, size = M;
     uint64_t g = g0;
@@ -238,7 +335,7 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
         lv_h[depth] = h;
         lv_g[depth] = g;
         if (m >= h) {
-            full_inverse(md, T, buf, logC, off, h, 2 * g);
+            if (!skip_full) full_inverse(md, T, buf, logC, off, h, 2 * g);
             // right child's known coefficients: C1_j = C0_j - 2 w hi_j, j in [m - h, h)
             const uint32_t j0 = m - h;
             const uint32_t items = (h - j0) * C;
@@ -250,7 +347,7 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
                 buf[(off + h + j) * C + c] = md.sub(md.sub(c0, t), t);
             }
             __syncthreads();
-            lv_right[depth] = true;
+            right_mask |= 1u << depth;
             off += h;
             g = 2 * g + 1;
             m -= h;
@@ -265,26 +362,25 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
                 buf[(off + j) * C + c] = md.add(lo, t);
             }
             __syncthreads();
-            lv_right[depth] = false;
             g = 2 * g;
         }
         size = h;
         depth++;
     }
-    if (size > 1 && m == size) full_inverse(md, T, buf, logC, off, size, g);
+    if (size > 1 && m == size && !skip_full) full_inverse(md, T, buf, logC, off, size, g);
     // ascend
     for (int d = depth - 1; d >= 0; d--) {
         const uint32_t o = lv_off[d], h = lv_h[d];
         const uint32_t items = h * C;
-        if (lv_right[d]) {
-            const Word wi = tw_inv_half(md, T, 2 * lv_g[d]);
+        if (right_mask & (1u << d)) {
+            const Word wi = tw_inv(md, T, 2 * lv_g[d]);
             for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
                 const uint32_t c = it & (C - 1);
                 const uint32_t j = it >> logC;
                 const Word x = buf[(o + j) * C + c];
                 const Word y = buf[(o + h + j) * C + c];
                 buf[(o + j) * C + c] = md.half(md.add(x, y));
-                buf[(o + h + j) * C + c] = md.mul_tw(md.sub(x, y), wi);
+                buf[(o + h + j) * C + c] = md.mul_tw(md.half(md.sub(x, y)), wi);
             }
         } else {
             const Word w = tw_fwd(md, T, 2 * lv_g[d]);
@@ -297,6 +393,38 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
         }
         __syncthreads();
     }
+}
+
+// The full-inverse pieces of gitft(M, m, g0): dyadic blocks (offset, size,
+// global index) that partition [0, m) (a final piece may have size 1, whose
+// inverse is the identity).  Returns the count (at most 1 + log2 M).
+struct Piece {
+    uint32_t off, size;
+    uint64_t g;
+};
+constexpr int kMaxPieces = 20;
+struct PieceList {
+    int count;
+    Piece p[kMaxPieces];
+};
+__host__ __device__ inline int gitft_pieces(uint32_t M, uint32_t m, uint64_t g0, Piece* out) {
+    int k = 0;
+    uint32_t off = 0, size = M;
+    uint64_t g = g0;
+    while (size > 1 && m > 0 && m < size) {
+        const uint32_t h = size >> 1;
+        if (m >= h) {
+            out[k++] = Piece{off, h, 2 * g};
+            off += h;
+            g = 2 * g + 1;
+            m -= h;
+        } else {
+            g = 2 * g;
+        }
+        size = h;
+    }
+    if (m > 0 && m == size) out[k++] = Piece{off, size, g};   // may be a single element
+    return k;
 }
 
 }  // namespace tft

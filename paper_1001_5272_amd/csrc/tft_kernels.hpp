@@ -212,49 +212,59 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(Mod md, Tables<typename Mo
     }
 }
 
-// Inverse row pass over the full rows j < a.  With Y non-null, each row is
-// first multiplied pointwise by the same row of Y (the product step fused into
-// the load).
+// Inverse row pass.  Workgroups j < a invert full row j (global block index j
+// at size W).  Workgroups a + k invert piece k of the partial last row: the
+// dyadic blocks of its b known outputs that the last-row inverse would
+// otherwise invert one after another (they read only known outputs, so they
+// run here, in parallel with the rows).  With Y non-null, values are first
+// multiplied pointwise by Y (the product step fused into the load).
 template <class Mod>
 __global__ __launch_bounds__(kThreads) void k_row_inv(Mod md, Tables<typename Mod::Word> T, typename Mod::Word* X,
-                                                      const typename Mod::Word* Y, uint32_t logW) {
+                                                      const typename Mod::Word* Y, uint32_t logW, uint32_t a,
+                                                      PieceList pieces) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
-    const uint32_t j = blockIdx.x;
     const uint32_t W = 1u << logW;
-    Word* row = X + (uint64_t)j * W;
-    if (Y) {
-        const Word* yr = Y + (uint64_t)j * W;
-        for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = md.mul(row[i], yr[i]);
+    uint64_t start;
+    uint32_t len;
+    uint64_t g;
+    if (blockIdx.x < a) {
+        start = (uint64_t)blockIdx.x * W;
+        len = W;
+        g = blockIdx.x;
     } else {
-        for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = row[i];
+        const Piece pc = pieces.p[blockIdx.x - a];
+        start = (uint64_t)a * W + pc.off;
+        len = pc.size;
+        g = pc.g;
+    }
+    Word* row = X + start;
+    if (Y) {
+        const Word* yr = Y + start;
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) buf[i] = md.mul(row[i], yr[i]);
+    } else {
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) buf[i] = row[i];
     }
     __syncthreads();
-    full_inverse(md, T, buf, 0, 0, W, j);
-    for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) row[i] = buf[i];
+    full_inverse(md, T, buf, 0, 0, len, g);
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) row[i] = buf[i];
 }
 
-// Inverse of the last row: b known outputs (optionally multiplied by Y first)
-// and the W - b known values V_c as coefficients of the block; recover the b
-// column values P_c(w_a), c < b.
+// Inverse of the last row after its pieces were inverted by k_row_inv: the b
+// slots now hold the pieces' coefficients and the W - b values V_c are the
+// known coefficients of the block; the remaining (elementwise) steps of the
+// truncated inverse recover the b column values P_c(w_a), c < b.
 template <class Mod>
 __global__ __launch_bounds__(kThreads) void k_last_inv(Mod md, Tables<typename Mod::Word> T, typename Mod::Word* X,
-                                                       const typename Mod::Word* Y, uint32_t logW, uint32_t a,
-                                                       uint32_t b, const typename Mod::Word* V) {
+                                                       uint32_t logW, uint32_t a, uint32_t b,
+                                                       const typename Mod::Word* V) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
     const uint32_t W = 1u << logW;
     Word* row = X + (uint64_t)a * W;
-    for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) {
-        Word v;
-        if (i < b)
-            v = Y ? md.mul(row[i], Y[(uint64_t)a * W + i]) : row[i];
-        else
-            v = V[i];
-        buf[i] = v;
-    }
+    for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = i < b ? row[i] : V[i];
     __syncthreads();
-    gitft(md, T, buf, 0, W, b, a);
+    gitft(md, T, buf, 0, W, b, a, /*skip_full=*/true);
     for (uint32_t i = threadIdx.x; i < b; i += blockDim.x) row[i] = buf[i];
 }
 

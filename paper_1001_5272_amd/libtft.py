@@ -40,8 +40,15 @@ SIGNATURES = {
     "poly_mul_padded": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp, _vp, _vp]),
     "tft_plan_info": (_st, [_vp, _sz, _vp]),
     "tft_set_plan_override": (_st, [_vp, ctypes.c_uint]),
+    "tft_timing_enable": (_st, [_vp, ctypes.c_int]),
+    "tft_timing_read": (_st, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
+    "tft_timing_reset": (_st, [_vp]),
+    "tft_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
     "tft_strerror": (ctypes.c_char_p, [_st]),
 }
+
+KERNEL_NAMES = ["small_fwd", "small_inv", "small_mul", "col_fwd", "row_fwd", "row_inv", "col_inv_short",
+                "last_inv", "col_inv_long", "pointwise", "copy_pad"]
 
 
 class TftError(RuntimeError):
@@ -186,3 +193,26 @@ def tft_plan_info(ctx: Context, n: int) -> dict:
 
 def tft_set_plan_override(ctx: Context, logW: int):
     _check(load().tft_set_plan_override(ctx.handle, logW), "tft_set_plan_override")
+
+
+def tft_timing_enable(ctx: Context, on: bool = True):
+    _check(load().tft_timing_enable(ctx.handle, 1 if on else 0), "tft_timing_enable")
+
+
+def tft_timing_reset(ctx: Context):
+    _check(load().tft_timing_reset(ctx.handle), "tft_timing_reset")
+
+
+def tft_timing_read(ctx: Context) -> dict:
+    """{kernel name: (launches, total_ms)} for kernels launched since the last reset."""
+    out = {}
+    for i, name in enumerate(KERNEL_NAMES):
+        cnt, ms = ctypes.c_uint64(), ctypes.c_double()
+        _check(load().tft_timing_read(ctx.handle, i, ctypes.byref(cnt), ctypes.byref(ms)), "tft_timing_read")
+        if cnt.value:
+            out[name] = (int(cnt.value), float(ms.value))
+    return out
+
+
+def tft_kernel_name(i: int) -> str:
+    return load().tft_kernel_name(i).decode()
