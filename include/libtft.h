@@ -102,6 +102,57 @@ tft_status tft_padded_inverse(tft_ctx* ctx, void* X, size_t n, void* Xpad, void*
 tft_status poly_mul_padded(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X, void* Apad,
                            void* Bpad, void* hip_stream);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent products (or forward transforms) of uneven lengths.  A
+ * descriptor names one product C = A B as in poly_mul: a (la words) and b (lb
+ * words) read only, out (la + lb - 1 words) receives C, work (la + lb - 1
+ * words) is caller workspace, required only when the product is too long for
+ * the single-workgroup path (NULL otherwise).  For forward transforms a
+ * descriptor names X = a = out with n = la; b, lb and work are ignored.
+ *
+ * tft_batch_create plans the batch and uploads its work lists (it allocates
+ * device memory and waits for the upload); tft_batch_run only enqueues kernels
+ * on the stream -- products short enough for LDS run as a persistent kernel
+ * that takes the next instance (longest first) from an atomic counter, the
+ * others as one launch per pass over a work list of (instance, tile) items --
+ * so a run can be captured in a HIP graph and replayed.  The descriptors'
+ * buffers must stay valid while runs are in flight; one batch must not run
+ * concurrently with itself.  poly_mul_batch and tft_forward_batch plan and
+ * run in one call (allocating per call); the batch is kept by the context
+ * until its next such call. */
+typedef struct {
+    const void* a;
+    size_t la;
+    const void* b;
+    size_t lb;
+    void* out;
+    void* work;
+} tft_mul_desc;
+typedef struct tft_batch tft_batch;
+typedef struct {
+    size_t count, single_workgroup, two_pass, device_bytes;
+    unsigned launches;
+} tft_batch_desc;
+tft_status tft_batch_create(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, tft_batch** out);
+tft_status tft_batch_run(tft_batch* batch, void* hip_stream);
+tft_status tft_batch_info(const tft_batch* batch, tft_batch_desc* out);
+void tft_batch_destroy(tft_batch* batch);
+tft_status poly_mul_batch(tft_ctx* ctx, const tft_mul_desc* d, size_t count, void* hip_stream);
+tft_status tft_forward_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t count, void* hip_stream);
+
+/* ------------------------------------------------ exact integer products
+ * tft_from_signed: dst[i] = src[i] mod p in [0, p) for n signed 64-bit inputs
+ * (src on the device, dst n words of ctx's width).
+ * tft_crt3: Chinese remaindering of three residue vectors r1, r2, r3 (n words
+ * each, modulo the primes of ctxs[0..2], all 31-bit word contexts on one
+ * device) into the signed representatives in [-M/2, M/2), M = p1 p2 p3, as
+ * n little-endian 128-bit integers (16 n bytes at out).  With products of
+ * signed inputs whose exact coefficients lie in that range this recovers the
+ * integer product exactly. */
+tft_status tft_from_signed(tft_ctx* ctx, const int64_t* src, size_t n, void* dst, void* hip_stream);
+tft_status tft_crt3(tft_ctx* const ctxs[3], const void* r1, const void* r2, const void* r3, size_t n, void* out,
+                    void* hip_stream);
+
 /* Schedule chosen for length n (for tests and benchmarks).  kind 0: the
  * single-workgroup path (whole transform in LDS); kind 1: the two-pass path
  * with n = a W + b, W = 2^logW columns of the tree at depth logW (paper,
@@ -140,7 +191,9 @@ typedef enum {
     TFT_K_LAST_INV,        /* inverse of the partial last row */
     TFT_K_COL_INV_LONG,    /* inverse columns c < b */
     TFT_K_POINTWISE,       /* pointwise product */
-    TFT_K_COPY,            /* zero-extending copy */
+    TFT_K_COPY,            /* zero-extending copy, counter reset, signed-to-residue */
+    TFT_K_SMALL_LIST,      /* persistent single-workgroup jobs of a batch */
+    TFT_K_CRT,             /* three-prime Chinese remaindering */
     TFT_K_COUNT
 } tft_kernel_id;
 tft_status tft_timing_enable(tft_ctx* ctx, int on);

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "libtft.h"
@@ -22,6 +23,7 @@ constexpr unsigned kMaxLog2 = 28;               // longest transform supported b
 constexpr size_t kScratchWords = size_t(1) << 16;   // V_c area: one word per column, W <= 2^16
 constexpr size_t kLdsSoft = 64 * 1024;          // preferred LDS per workgroup
 constexpr size_t kLdsHard = 160 * 1024;         // gfx950 LDS per workgroup
+constexpr size_t kLdsDynMax = 144 * 1024;       // dynamic LDS any launch may request
 
 typedef unsigned __int128 u128;
 
@@ -82,6 +84,8 @@ struct tft_ctx {
     std::vector<hipEvent_t> pool;
     uint64_t launches[TFT_K_COUNT];
     double total_ms[TFT_K_COUNT];
+    struct tft_batch* last_batch;   // kept alive for the convenience batch calls
+    hipEvent_t last_done;
 };
 
 namespace {
@@ -156,13 +160,22 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
     const unsigned logC = (unsigned)P.logC;
     if (ctx->override_logW) {
         fill(ctx->override_logW);
-        if (P.W < (1ull << logC) || P.a < 1 || P.lds_col > kLdsHard || P.lds_row > kLdsHard) P.kind = -1;
+        if (P.W < (1ull << logC) || P.a < 1 || P.lds_col > kLdsDynMax || P.lds_row > kLdsDynMax) P.kind = -1;
         return P;
     }
+    // balanced split: W close to sqrt(n), within the LDS budget (preferred
+    // budget first, then the larger one)
+    const unsigned k = log2u(n);
     for (size_t lim : {kLdsSoft, kLdsHard - 32 * 1024}) {
-        for (unsigned logW = logC; logW <= 16 && (1ull << logW) <= n; logW++) {
+        int best = -1;
+        for (unsigned logW = logC; logW <= 16 && (1ull << logW) < n; logW++) {
             fill(logW);
-            if (P.lds_col <= lim && P.lds_row <= lim) return P;
+            if (P.lds_col > lim || P.lds_row > lim) continue;
+            if (best < 0 || std::abs(2 * (int)logW - (int)k) <= std::abs(2 * best - (int)k)) best = (int)logW;
+        }
+        if (best >= 0) {
+            fill((unsigned)best);
+            return P;
         }
     }
     P.kind = -1;   // beyond this build's two-pass limit
@@ -187,19 +200,43 @@ const tft::ModU32& mod_of<tft::ModU32>(const tft_ctx* ctx) { return ctx->m32; }
 template <>
 const tft::ModGL& mod_of<tft::ModGL>(const tft_ctx* ctx) { return ctx->m64; }
 
+// Allow each kernel the dynamic LDS the planner may give it (the largest tile
+// plus headroom, below the 160 KiB per workgroup minus static LDS).
 template <class Mod>
-void set_lds_limits() {
-    const int lim = (int)kLdsHard;
-    (void)hipFuncSetAttribute((const void*)tft::k_small_fwd<Mod>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)tft::k_small_inv<Mod>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)tft::k_small_mul<Mod>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)tft::k_col_fwd<Mod, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)tft::k_col_fwd<Mod, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)tft::k_col_inv<Mod, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)tft::k_col_inv<Mod, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)tft::k_row_fwd<Mod>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)tft::k_row_inv<Mod>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)tft::k_last_inv<Mod>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+bool set_lds_limits() {
+    const int lim = (int)kLdsDynMax;
+    const void* ks[] = {
+        (const void*)tft::k_small_fwd<Mod>,       (const void*)tft::k_small_inv<Mod>,
+        (const void*)tft::k_small_mul<Mod>,       (const void*)tft::k_small_list<Mod>,
+        (const void*)tft::k_col_fwd<Mod, 3>,      (const void*)tft::k_col_fwd<Mod, 4>,
+        (const void*)tft::k_col_inv<Mod, 3>,      (const void*)tft::k_col_inv<Mod, 4>,
+        (const void*)tft::k_row_fwd<Mod>,         (const void*)tft::k_row_inv<Mod>,
+        (const void*)tft::k_last_inv<Mod>,        (const void*)tft::k_col_fwd_list<Mod, 3>,
+        (const void*)tft::k_col_fwd_list<Mod, 4>, (const void*)tft::k_col_inv_list<Mod, 3>,
+        (const void*)tft::k_col_inv_list<Mod, 4>, (const void*)tft::k_row_fwd_list<Mod>,
+        (const void*)tft::k_row_inv_list<Mod>,    (const void*)tft::k_last_inv_list<Mod>,
+    };
+    for (const void* k : ks) {
+        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) return false;
+    }
+    return true;
+}
+
+template <class Word>
+tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t n_src, const Word* Y, Word* V) {
+    tft::TwoPass<Word> G;
+    G.X = X;
+    G.src = src;
+    G.Y = Y;
+    G.V = V;
+    G.n_src = n_src;
+    G.n = P.n;
+    G.logW = P.logW;
+    G.a = (uint32_t)P.a;
+    G.b = (uint32_t)P.b;
+    G.Lout = P.Lout;
+    G.M = P.M;
+    return G;
 }
 
 // -------------------------------------------------------------- forward
@@ -220,15 +257,14 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
         return launch_status();
     }
     Word* V = reinterpret_cast<Word*>(ctx->scratch);
+    const auto G = two_pass_of<Word>(P, X, src, n_src, nullptr, V);
     const uint32_t tiles = (uint32_t)(P.W >> P.logC);
     if (P.logC == 3)
-        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(kThreads), P.lds_col, st, md, T, src, n_src, X,
-                           n, P.logW, (uint32_t)P.a, (uint32_t)P.b, P.Lout, P.M, V, tiles);
+        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(kThreads), P.lds_col, st, md, T, G, tiles);
     else
-        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(kThreads), P.lds_col, st, md, T, src, n_src, X,
-                           n, P.logW, (uint32_t)P.a, (uint32_t)P.b, P.Lout, P.M, V, tiles);
-    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(kThreads), P.lds_row, st, md,
-                       T, X, P.logW, (uint32_t)P.a, (uint32_t)P.b, V);
+        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(kThreads), P.lds_col, st, md, T, G, tiles);
+    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(kThreads), P.lds_row,
+           st, md, T, G);
     return launch_status();
 }
 
@@ -248,27 +284,21 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
         return launch_status();
     }
     Word* V = reinterpret_cast<Word*>(ctx->scratch);
+    const auto G = two_pass_of<Word>(P, X, X, n, Y, V);
     const uint32_t C = 1u << P.logC;
     const uint32_t tiles_all = (uint32_t)(P.W >> P.logC);
-    tft::PieceList pieces{};
-    pieces.count = P.b ? tft::gitft_pieces((uint32_t)P.W, (uint32_t)P.b, P.a, pieces.p) : 0;
-    launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3((uint32_t)P.a + pieces.count), dim3(kThreads), P.lds_row, st,
-           md, T, X, Y, P.logW, (uint32_t)P.a, pieces);
-    // columns c >= b
-    {
+    const uint32_t nrows = tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
+    launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows), dim3(kThreads), P.lds_row, st, md, T, G);
+    auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
+    {   // columns c >= b
         const uint32_t t0 = (uint32_t)(P.b / C);
         const uint32_t nt = tiles_all - t0;
-        auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
-        launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(kThreads), P.lds_col, st, md, T, X, P.logW,
-               (uint32_t)P.a, (uint32_t)P.b, P.M, V, 0, t0, nt);
+        launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(kThreads), P.lds_col, st, md, T, G, 0, t0, nt);
     }
     if (P.b) {
-        launch(ctx, TFT_K_LAST_INV, tft::k_last_inv<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, X, P.logW,
-               (uint32_t)P.a, (uint32_t)P.b, (const Word*)V);
+        launch(ctx, TFT_K_LAST_INV, tft::k_last_inv<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, G);
         const uint32_t nt = (uint32_t)((P.b + C - 1) / C);
-        auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
-        launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(kThreads), P.lds_col, st, md, T, X, P.logW,
-               (uint32_t)P.a, (uint32_t)P.b, P.M, V, 1, 0u, nt);
+        launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(kThreads), P.lds_col, st, md, T, G, 1, 0u, nt);
     }
     return launch_status();
 }
@@ -423,6 +453,255 @@ tft_status dispatch(tft_ctx* ctx, F&& f) {
     return f();
 }
 
+// ================================================================= batches
+// A batch is planned once (host) and its work lists uploaded once; running it
+// only launches kernels, so a run can be captured in a HIP graph and replayed.
+enum { PH_COL_FWD = 0, PH_ROW_FWD, PH_ROW_INV, PH_COL_INV_SHORT, PH_LAST_INV, PH_COL_INV_LONG, PH_COUNT };
+
+}  // namespace
+
+struct tft_batch {
+    tft_ctx* ctx;
+    int products;              // 1: products, 0: forward transforms
+    size_t count;
+    size_t n_small, n_two;     // instances on each path
+    void* dmem;                // recs | items | jobs | V areas | counter
+    size_t dbytes;
+    void* recs;
+    tft::Item* items[PH_COUNT];
+    uint32_t n_items[PH_COUNT];
+    void* jobs;
+    uint32_t* counter;
+    size_t lds_col, lds_row, lds_small;
+    int logC;
+    uint32_t small_grid;
+    hipStream_t side;          // the single-workgroup jobs run here, beside the two-pass phases
+    hipEvent_t fork, join;
+};
+
+namespace {
+
+template <class Mod>
+tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, tft_batch* B) {
+    using Word = typename Mod::Word;
+    const unsigned w = ctx->wbytes;
+    std::vector<tft::SmallJob<Word>> jobs;
+    std::vector<tft::TwoPass<Word>> recs;
+    std::vector<tft::Item> items[PH_COUNT];
+    std::vector<size_t> vwords;   // V area size per record
+    size_t v_total = 0;
+    B->lds_col = B->lds_row = B->lds_small = 0;
+    B->logC = (w == 4) ? 4 : 3;
+    const size_t small_lds_cap = kLdsHard - 32 * 1024;
+    for (size_t k = 0; k < count; k++) {
+        const tft_mul_desc& D = d[k];
+        if (!D.a || !D.out || D.la == 0 || (products && (!D.b || D.lb == 0))) return TFT_EINVAL;
+        const uint64_t r = products ? D.la + D.lb - 1 : D.la;
+        if (log2u(r) > ctx->v) return TFT_ERANGE;
+        const Plan P = make_plan(ctx, r);
+        if (P.kind < 0) return TFT_ERANGE;
+        const size_t small_lds = (products ? 2 : 1) * (size_t)pow2ceil(r) * w;
+        if (P.kind == 0 && small_lds <= small_lds_cap) {
+            tft::SmallJob<Word> J;
+            J.A = (const Word*)D.a;
+            J.B = products ? (const Word*)D.b : nullptr;
+            J.X = (Word*)D.out;
+            J.m = (uint32_t)D.la;
+            J.nb = products ? (uint32_t)D.lb : 0;
+            J.M = (uint32_t)pow2ceil(r);
+            jobs.push_back(J);
+            if (small_lds > B->lds_small) B->lds_small = small_lds;
+            continue;
+        }
+        if (P.kind != 1) return TFT_ERANGE;
+        if (products && !D.work) return TFT_EINVAL;
+        B->lds_col = std::max(B->lds_col, P.lds_col);
+        B->lds_row = std::max(B->lds_row, P.lds_row);
+        const uint32_t tiles = (uint32_t)(P.W >> P.logC);
+        const uint32_t C = 1u << P.logC;
+        const int nops = products ? 2 : 1;
+        const uint32_t rec0 = (uint32_t)recs.size();
+        for (int op = 0; op < nops; op++) {
+            Word* X = op == 0 ? (Word*)D.out : (Word*)D.work;
+            const Word* src = op == 0 ? (const Word*)D.a : (const Word*)D.b;
+            const uint64_t n_src = op == 0 ? D.la : D.lb;
+            const Word* Y = (products && op == 0) ? (const Word*)D.work : nullptr;
+            recs.push_back(two_pass_of<Word>(P, X, products ? src : X, products ? n_src : r, Y, nullptr));
+            vwords.push_back(P.W);
+            v_total += P.W;
+            const uint32_t rec = rec0 + op;
+            for (uint32_t t = 0; t < tiles; t++) items[PH_COL_FWD].push_back({rec, t});
+            for (uint32_t j = 0; j < P.a + (P.b ? 1 : 0); j++) items[PH_ROW_FWD].push_back({rec, j});
+        }
+        if (products) {
+            const uint32_t nr = tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
+            for (uint32_t j = 0; j < nr; j++) items[PH_ROW_INV].push_back({rec0, j});
+            for (uint32_t t = (uint32_t)(P.b / C); t < tiles; t++) items[PH_COL_INV_SHORT].push_back({rec0, t});
+            if (P.b) {
+                items[PH_LAST_INV].push_back({rec0, 0});
+                for (uint32_t t = 0; t < (P.b + C - 1) / C; t++) items[PH_COL_INV_LONG].push_back({rec0, t});
+            }
+        }
+    }
+    // longest single-workgroup jobs first
+    std::stable_sort(jobs.begin(), jobs.end(), [](const tft::SmallJob<Word>& x, const tft::SmallJob<Word>& y) {
+        return (uint64_t)x.m + x.nb > (uint64_t)y.m + y.nb;
+    });
+    B->n_small = jobs.size();
+    B->n_two = recs.size() / (products ? 2 : 1);
+    // one device allocation: recs | items per phase | jobs | V areas | counter
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t off = 0;
+    const size_t o_recs = off;
+    off = align(off + recs.size() * sizeof(tft::TwoPass<Word>));
+    size_t o_items[PH_COUNT];
+    for (int ph = 0; ph < PH_COUNT; ph++) {
+        o_items[ph] = off;
+        off = align(off + items[ph].size() * sizeof(tft::Item));
+    }
+    const size_t o_jobs = off;
+    off = align(off + jobs.size() * sizeof(tft::SmallJob<Word>));
+    const size_t o_v = off;
+    off = align(off + v_total * w);
+    const size_t o_ctr = off;
+    off = align(off + 256);
+    B->dbytes = off;
+    hipError_t e = hipMalloc(&B->dmem, off);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? TFT_ENOMEM : TFT_EDEVICE;
+    char* base = (char*)B->dmem;
+    size_t vo = 0;
+    for (size_t i = 0; i < recs.size(); i++) {
+        recs[i].V = (Word*)(base + o_v) + vo;
+        vo += vwords[i];
+    }
+    std::vector<char> host(off, 0);
+    std::memcpy(host.data() + o_recs, recs.data(), recs.size() * sizeof(tft::TwoPass<Word>));
+    for (int ph = 0; ph < PH_COUNT; ph++)
+        std::memcpy(host.data() + o_items[ph], items[ph].data(), items[ph].size() * sizeof(tft::Item));
+    std::memcpy(host.data() + o_jobs, jobs.data(), jobs.size() * sizeof(tft::SmallJob<Word>));
+    e = hipMemcpy(B->dmem, host.data(), off, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return TFT_EDEVICE;
+    B->recs = base + o_recs;
+    for (int ph = 0; ph < PH_COUNT; ph++) {
+        B->items[ph] = (tft::Item*)(base + o_items[ph]);
+        B->n_items[ph] = (uint32_t)items[ph].size();
+    }
+    B->jobs = base + o_jobs;
+    B->counter = (uint32_t*)(base + o_ctr);
+    // persistent grid: as many workgroups as fit at once (LDS-limited), at most one per job
+    uint32_t per_cu = B->lds_small ? (uint32_t)std::max<size_t>(1, kLdsHard / B->lds_small) : 1;
+    per_cu = std::min<uint32_t>(per_cu, 8);
+    int ncu = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) ncu = prop.multiProcessorCount;
+    B->small_grid = (uint32_t)std::min<size_t>(jobs.size(), (size_t)ncu * per_cu);
+    return TFT_OK;
+}
+
+template <class Mod>
+tft_status batch_run(tft_batch* B, hipStream_t st) {
+    using Word = typename Mod::Word;
+    tft_ctx* ctx = B->ctx;
+    const Mod& md = mod_of<Mod>(ctx);
+    const auto T = tables_of<Word>(ctx);
+    const auto* recs = (const tft::TwoPass<Word>*)B->recs;
+    const bool both = B->n_small && B->n_two;
+    hipStream_t small_st = st;
+    if (both) {
+        if (hipEventRecord(B->fork, st) != hipSuccess || hipStreamWaitEvent(B->side, B->fork, 0) != hipSuccess)
+            return TFT_EDEVICE;
+        small_st = B->side;
+    }
+    if (B->n_small) {
+        launch(ctx, TFT_K_COPY, tft::k_reset_counter, dim3(1), dim3(64), 0, small_st, B->counter);
+        launch(ctx, TFT_K_SMALL_LIST, tft::k_small_list<Mod>, dim3(B->small_grid), dim3(kThreads), B->lds_small,
+               small_st, md, T, (const tft::SmallJob<Word>*)B->jobs, (uint32_t)B->n_small, B->counter);
+    }
+    const bool c3 = B->logC == 3;
+    if (B->n_items[PH_COL_FWD])
+        launch(ctx, TFT_K_COL_FWD, c3 ? tft::k_col_fwd_list<Mod, 3> : tft::k_col_fwd_list<Mod, 4>,
+               dim3(B->n_items[PH_COL_FWD]), dim3(kThreads), B->lds_col, st, md, T, recs,
+               (const tft::Item*)B->items[PH_COL_FWD]);
+    if (B->n_items[PH_ROW_FWD])
+        launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd_list<Mod>, dim3(B->n_items[PH_ROW_FWD]), dim3(kThreads), B->lds_row,
+               st, md, T, recs, (const tft::Item*)B->items[PH_ROW_FWD]);
+    if (B->n_items[PH_ROW_INV])
+        launch(ctx, TFT_K_ROW_INV, tft::k_row_inv_list<Mod>, dim3(B->n_items[PH_ROW_INV]), dim3(kThreads), B->lds_row,
+               st, md, T, recs, (const tft::Item*)B->items[PH_ROW_INV]);
+    if (B->n_items[PH_COL_INV_SHORT])
+        launch(ctx, TFT_K_COL_INV_SHORT, c3 ? tft::k_col_inv_list<Mod, 3> : tft::k_col_inv_list<Mod, 4>,
+               dim3(B->n_items[PH_COL_INV_SHORT]), dim3(kThreads), B->lds_col, st, md, T, recs,
+               (const tft::Item*)B->items[PH_COL_INV_SHORT], 0);
+    if (B->n_items[PH_LAST_INV])
+        launch(ctx, TFT_K_LAST_INV, tft::k_last_inv_list<Mod>, dim3(B->n_items[PH_LAST_INV]), dim3(kThreads),
+               B->lds_row, st, md, T, recs, (const tft::Item*)B->items[PH_LAST_INV]);
+    if (B->n_items[PH_COL_INV_LONG])
+        launch(ctx, TFT_K_COL_INV_LONG, c3 ? tft::k_col_inv_list<Mod, 3> : tft::k_col_inv_list<Mod, 4>,
+               dim3(B->n_items[PH_COL_INV_LONG]), dim3(kThreads), B->lds_col, st, md, T, recs,
+               (const tft::Item*)B->items[PH_COL_INV_LONG], 1);
+    if (both) {
+        if (hipEventRecord(B->join, B->side) != hipSuccess || hipStreamWaitEvent(st, B->join, 0) != hipSuccess)
+            return TFT_EDEVICE;
+    }
+    return launch_status();
+}
+
+void batch_free(tft_batch* B) {
+    if (!B) return;
+    DeviceGuard guard(B->ctx->device);
+    if (B->dmem) (void)hipFree(B->dmem);
+    if (B->side) (void)hipStreamDestroy(B->side);
+    if (B->fork) (void)hipEventDestroy(B->fork);
+    if (B->join) (void)hipEventDestroy(B->join);
+    delete B;
+}
+
+tft_status batch_create(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, tft_batch** out) {
+    if (!ctx || !out || (count && !d)) return TFT_EINVAL;
+    *out = nullptr;
+    DeviceGuard guard(ctx->device);
+    tft_batch* B = new (std::nothrow) tft_batch();
+    if (!B) return TFT_ENOMEM;
+    B->ctx = ctx;
+    B->products = products;
+    B->count = count;
+    tft_status s = ctx->wbytes == 4 ? batch_build<tft::ModU32>(ctx, d, count, products, B)
+                                    : batch_build<tft::ModGL>(ctx, d, count, products, B);
+    if (s == TFT_OK) {
+        if (hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&B->join, hipEventDisableTiming) != hipSuccess)
+            s = TFT_EDEVICE;
+    }
+    if (s != TFT_OK) {
+        batch_free(B);
+        return s;
+    }
+    *out = B;
+    return TFT_OK;
+}
+
+// Convenience calls keep their batch alive until the next convenience call
+// (or context destruction) so that work already enqueued can finish.
+tft_status batch_once(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, hipStream_t st) {
+    if (ctx->last_batch) {
+        (void)hipEventSynchronize(ctx->last_done);
+        batch_free(ctx->last_batch);
+        ctx->last_batch = nullptr;
+    }
+    if (count == 0) return TFT_OK;
+    tft_batch* B = nullptr;
+    tft_status s = batch_create(ctx, d, count, products, &B);
+    if (s != TFT_OK) return s;
+    DeviceGuard guard(ctx->device);
+    s = ctx->wbytes == 4 ? batch_run<tft::ModU32>(B, st) : batch_run<tft::ModGL>(B, st);
+    ctx->last_batch = B;
+    if (!ctx->last_done && hipEventCreateWithFlags(&ctx->last_done, hipEventDisableTiming) != hipSuccess)
+        return TFT_EDEVICE;
+    if (hipEventRecord(ctx->last_done, st) != hipSuccess) return TFT_EDEVICE;
+    return s;
+}
+
 }  // namespace
 
 // ============================================================== C entry points
@@ -460,6 +739,8 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
     c->wbytes = wide ? 8 : 4;
     c->override_logW = 0;
     c->timing = false;
+    c->last_batch = nullptr;
+    c->last_done = nullptr;
     for (int i = 0; i < TFT_K_COUNT; i++) { c->launches[i] = 0; c->total_ms[i] = 0.0; }
     if (!wide) {
         uint32_t inv = 1;                          // p^-1 mod 2^32 by Newton iteration
@@ -479,13 +760,13 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
         bytes = t.size() * 8;
         e = hipMalloc(&c->tables, bytes);
         if (e == hipSuccess) e = hipMemcpy(c->tables, t.data(), bytes, hipMemcpyHostToDevice);
-        set_lds_limits<tft::ModGL>();
+        if (e == hipSuccess && !set_lds_limits<tft::ModGL>()) e = hipErrorInvalidValue;
     } else {
         auto t = build_tables<uint32_t>(p, g, c->v, c->n1, c->n2, true);
         bytes = t.size() * 4;
         e = hipMalloc(&c->tables, bytes);
         if (e == hipSuccess) e = hipMemcpy(c->tables, t.data(), bytes, hipMemcpyHostToDevice);
-        set_lds_limits<tft::ModU32>();
+        if (e == hipSuccess && !set_lds_limits<tft::ModU32>()) e = hipErrorInvalidValue;
     }
     if (e == hipSuccess) e = hipMalloc(&c->scratch, kScratchWords * c->wbytes);
     if (e != hipSuccess) {
@@ -500,6 +781,11 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
 void tft_ctx_destroy(tft_ctx* ctx) {
     if (!ctx) return;
     DeviceGuard guard(ctx->device);
+    if (ctx->last_batch) {
+        (void)hipEventSynchronize(ctx->last_done);
+        batch_free(ctx->last_batch);
+    }
+    if (ctx->last_done) (void)hipEventDestroy(ctx->last_done);
     (void)hipFree(ctx->tables);
     (void)hipFree(ctx->scratch);
     for (auto& r : ctx->recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
@@ -626,6 +912,87 @@ tft_status tft_set_plan_override(tft_ctx* ctx, unsigned logW) {
     return TFT_OK;
 }
 
+tft_status tft_batch_create(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, tft_batch** out) {
+    return batch_create(ctx, d, count, products ? 1 : 0, out);
+}
+
+tft_status tft_batch_run(tft_batch* B, void* stream) {
+    if (!B) return TFT_EINVAL;
+    DeviceGuard guard(B->ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    return B->ctx->wbytes == 4 ? batch_run<tft::ModU32>(B, st) : batch_run<tft::ModGL>(B, st);
+}
+
+tft_status tft_batch_info(const tft_batch* B, tft_batch_desc* out) {
+    if (!B || !out) return TFT_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->count = B->count;
+    out->single_workgroup = B->n_small;
+    out->two_pass = B->n_two;
+    out->device_bytes = B->dbytes;
+    uint32_t launches = B->n_small ? 2 : 0;
+    for (int ph = 0; ph < PH_COUNT; ph++) launches += B->n_items[ph] ? 1 : 0;
+    out->launches = launches;
+    return TFT_OK;
+}
+
+void tft_batch_destroy(tft_batch* B) { batch_free(B); }
+
+tft_status poly_mul_batch(tft_ctx* ctx, const tft_mul_desc* d, size_t count, void* stream) {
+    if (!ctx || (count && !d)) return TFT_EINVAL;
+    DeviceGuard guard(ctx->device);
+    return batch_once(ctx, d, count, 1, (hipStream_t)stream);
+}
+
+tft_status tft_forward_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t count, void* stream) {
+    if (!ctx || (count && (!X || !n))) return TFT_EINVAL;
+    std::vector<tft_mul_desc> d(count);
+    for (size_t k = 0; k < count; k++) {
+        d[k] = tft_mul_desc{X[k], n[k], nullptr, 0, X[k], nullptr};
+    }
+    DeviceGuard guard(ctx->device);
+    return batch_once(ctx, d.data(), count, 0, (hipStream_t)stream);
+}
+
+tft_status tft_from_signed(tft_ctx* ctx, const int64_t* src, size_t n, void* dst, void* stream) {
+    if (!ctx || !src || !dst || n == 0) return TFT_EINVAL;
+    DeviceGuard guard(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t blocks = std::min<uint64_t>((n + kThreads - 1) / kThreads, 8192);
+    if (ctx->wbytes == 4)
+        launch(ctx, TFT_K_COPY, tft::k_from_signed<uint32_t>, dim3((uint32_t)blocks), dim3(kThreads), 0, st,
+               (uint32_t*)dst, src, (uint64_t)n, ctx->p);
+    else
+        launch(ctx, TFT_K_COPY, tft::k_from_signed<uint64_t>, dim3((uint32_t)blocks), dim3(kThreads), 0, st,
+               (uint64_t*)dst, src, (uint64_t)n, ctx->p);
+    return launch_status();
+}
+
+tft_status tft_crt3(tft_ctx* const ctxs[3], const void* r1, const void* r2, const void* r3, size_t n, void* out,
+                    void* stream) {
+    if (!ctxs || !ctxs[0] || !ctxs[1] || !ctxs[2] || !r1 || !r2 || !r3 || !out || n == 0) return TFT_EINVAL;
+    for (int i = 0; i < 3; i++)
+        if (ctxs[i]->wbytes != 4 || ctxs[i]->device != ctxs[0]->device) return TFT_EINVAL;
+    const uint64_t p1 = ctxs[0]->p, p2 = ctxs[1]->p, p3 = ctxs[2]->p;
+    if (p1 == p2 || p1 == p3 || p2 == p3) return TFT_EINVAL;
+    tft::Crt3 c;
+    c.p1 = p1;
+    c.p2 = p2;
+    c.p3 = p3;
+    c.inv_p1_mod_p2 = powmod_h(p1 % p2, p2 - 2, p2);
+    c.p1p2_mod_p3 = mulmod_h(p1 % p3, p2 % p3, p3);
+    c.inv_p1p2_mod_p3 = powmod_h(c.p1p2_mod_p3, p3 - 2, p3);
+    c.M = (u128)p1 * p2 * p3;
+    c.half_M = (c.M + 1) / 2;
+    tft_ctx* ctx = ctxs[0];
+    DeviceGuard guard(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t blocks = std::min<uint64_t>((n + kThreads - 1) / kThreads, 16384);
+    launch(ctx, TFT_K_CRT, tft::k_crt3, dim3((uint32_t)blocks), dim3(kThreads), 0, st, c, (const uint32_t*)r1,
+           (const uint32_t*)r2, (const uint32_t*)r3, (uint64_t*)out, (uint64_t)n);
+    return launch_status();
+}
+
 tft_status tft_timing_enable(tft_ctx* ctx, int on) {
     if (!ctx) return TFT_EINVAL;
     ctx->timing = on != 0;
@@ -667,7 +1034,7 @@ tft_status tft_timing_reset(tft_ctx* ctx) {
 const char* tft_kernel_name(int id) {
     static const char* names[TFT_K_COUNT] = {"small_fwd", "small_inv", "small_mul", "col_fwd", "row_fwd",
                                              "row_inv", "col_inv_short", "last_inv", "col_inv_long",
-                                             "pointwise", "copy_pad"};
+                                             "pointwise", "copy_pad", "small_list", "crt3"};
     return (id >= 0 && id < TFT_K_COUNT) ? names[id] : "unknown";
 }
 

@@ -316,24 +316,44 @@ __device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T,
 // The full inverses act on disjoint dyadic pieces of [0, m) and read only
 // known values, so a caller may run them beforehand (in parallel, elsewhere)
 // and pass skip_full = true.
+// Level d of gitft's descent along the truncation boundary: offset and half
+// size of the block met there, its global index, and whether the walk went to
+// the right child.  Recomputed on demand so that no per-level array is kept.
+struct Level {
+    uint32_t off, h;
+    uint64_t g;
+    bool right;
+};
+__device__ __forceinline__ Level gitft_level(uint32_t M, uint32_t m, uint64_t g0, int d) {
+    uint32_t off = 0, size = M;
+    uint64_t g = g0;
+    for (int i = 0;; i++) {
+        const uint32_t h = size >> 1;
+        const bool right = m >= h;
+        if (i == d) return Level{off, h, g, right};
+        if (right) {
+            off += h;
+            g = 2 * g + 1;
+            m -= h;
+        } else {
+            g = 2 * g;
+        }
+        size = h;
+    }
+}
+
 template <class Mod>
 __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                       uint32_t M, uint32_t m, uint64_t g0, bool skip_full = false) {
     using Word = typename Mod::Word;
     const uint32_t C = 1u << logC;
-    uint32_t lv_off[20];
-    uint32_t lv_h[20];
-    uint64_t lv_g[20];
-    uint32_t right_mask = 0;
+    const uint32_t m0 = m;
     int depth = 0;
     uint32_t off = 0, size = M;
     uint64_t g = g0;
     while (size > 1 && m > 0 && m < size) {
         const uint32_t h = size >> 1;
         const Word w = tw_fwd(md, T, 2 * g);
-        lv_off[depth] = off;
-        lv_h[depth] = h;
-        lv_g[depth] = g;
         if (m >= h) {
             if (!skip_full) full_inverse(md, T, buf, logC, off, h, 2 * g);
             // right child's known coefficients: C1_j = C0_j - 2 w hi_j, j in [m - h, h)
@@ -347,7 +367,6 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
                 buf[(off + h + j) * C + c] = md.sub(md.sub(c0, t), t);
             }
             __syncthreads();
-            right_mask |= 1u << depth;
             off += h;
             g = 2 * g + 1;
             m -= h;
@@ -370,10 +389,11 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
     if (size > 1 && m == size && !skip_full) full_inverse(md, T, buf, logC, off, size, g);
     // ascend
     for (int d = depth - 1; d >= 0; d--) {
-        const uint32_t o = lv_off[d], h = lv_h[d];
+        const Level L = gitft_level(M, m0, g0, d);
+        const uint32_t o = L.off, h = L.h;
         const uint32_t items = h * C;
-        if (right_mask & (1u << d)) {
-            const Word wi = tw_inv(md, T, 2 * lv_g[d]);
+        if (L.right) {
+            const Word wi = tw_inv(md, T, 2 * L.g);
             for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
                 const uint32_t c = it & (C - 1);
                 const uint32_t j = it >> logC;
@@ -383,7 +403,7 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
                 buf[(o + h + j) * C + c] = md.mul_tw(md.half(md.sub(x, y)), wi);
             }
         } else {
-            const Word w = tw_fwd(md, T, 2 * lv_g[d]);
+            const Word w = tw_fwd(md, T, 2 * L.g);
             for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
                 const uint32_t c = it & (C - 1);
                 const uint32_t j = it >> logC;
@@ -403,6 +423,26 @@ struct Piece {
     uint64_t g;
 };
 constexpr int kMaxPieces = 20;
+
+// The piece number `want` of gitft_pieces(M, m, g0) (same walk, no array).
+__host__ __device__ inline Piece gitft_piece(uint32_t M, uint32_t m, uint64_t g0, int want) {
+    int k = 0;
+    uint32_t off = 0, size = M;
+    uint64_t g = g0;
+    while (size > 1 && m > 0 && m < size) {
+        const uint32_t h = size >> 1;
+        if (m >= h) {
+            if (k++ == want) return Piece{off, h, 2 * g};
+            off += h;
+            g = 2 * g + 1;
+            m -= h;
+        } else {
+            g = 2 * g;
+        }
+        size = h;
+    }
+    return Piece{off, size, g};
+}
 struct PieceList {
     int count;
     Piece p[kMaxPieces];

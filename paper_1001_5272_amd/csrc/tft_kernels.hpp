@@ -113,134 +113,101 @@ __global__ __launch_bounds__(kThreads) void k_small_mul(Mod md, Tables<typename 
     small_mul_body(md, T, A, m, B, nb, X, M);
 }
 
-// ------------------------------------------------------------ column pass
-// Forward column pass.  Reads columns from src (n_src words; src may equal dst,
-// or be a shorter read-only operand that is implicitly zero-extended to n),
+// ------------------------------------------------------------ two passes
+// One in-place two-pass transform of length n = a W + b (W = 2^logW): the data
+// X, the column-pass source (X itself, or a shorter read-only operand that is
+// implicitly zero-extended to n), the W-word area V for the extra column
+// evaluations, and an optional pointwise multiplier Y applied on the first
+// inverse load.
+template <class Word>
+struct TwoPass {
+    Word* X;
+    const Word* src;
+    const Word* Y;
+    Word* V;
+    uint64_t n_src, n;
+    uint32_t logW, a, b, Lout, M;
+};
+
+// Forward column pass over the tile of C columns starting at column tile*C:
 // evaluates each column polynomial at w_0..w_{Lout-1} (Lout = a + (b > 0)) in
-// an LDS block of M = 2^ceil(lg Lout) words per column, writes outputs that
-// have a slot in dst and the extra value P_c(w_a) of columns c >= b to V[c].
+// an LDS block of M = 2^ceil(lg Lout) words per column, writes the outputs
+// that have a slot and the extra value P_c(w_a) of columns c >= b to V[c].
 template <class Mod, int LOGC>
-__global__ __launch_bounds__(kThreads) void k_col_fwd(Mod md, Tables<typename Mod::Word> T,
-                                                      const typename Mod::Word* src, uint64_t n_src,
-                                                      typename Mod::Word* dst, uint64_t n, uint32_t logW,
-                                                      uint32_t a, uint32_t b, uint32_t Lout, uint32_t M,
-                                                      typename Mod::Word* V, uint32_t tiles) {
+__device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T,
+                             const TwoPass<typename Mod::Word>& P, uint32_t tile) {
     using Word = typename Mod::Word;
     constexpr uint32_t C = 1u << LOGC;
     Word* buf = lds_buf<Word>();
-    const uint32_t c0 = xcd_remap(blockIdx.x, tiles) * C;
-    const uint64_t W = 1ull << logW;
-    for (uint32_t it = threadIdx.x; it < M * C; it += blockDim.x) {
+    const uint32_t c0 = tile * C;
+    const uint64_t W = 1ull << P.logW;
+    for (uint32_t it = threadIdx.x; it < P.M * C; it += blockDim.x) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint64_t idx = (c0 + c) + (uint64_t)d * W;
-        buf[it] = (d < Lout && idx < n_src) ? src[idx] : Word(0);
+        buf[it] = (d < P.Lout && idx < P.n_src) ? P.src[idx] : Word(0);
     }
     __syncthreads();
-    dif_forward(md, T, buf, LOGC, M, 0, Lout, 0);
-    for (uint32_t it = threadIdx.x; it < Lout * C; it += blockDim.x) {
+    dif_forward(md, T, buf, LOGC, P.M, 0, P.Lout, 0);
+    for (uint32_t it = threadIdx.x; it < P.Lout * C; it += blockDim.x) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint64_t idx = (c0 + c) + (uint64_t)d * W;
-        if (idx < n)
-            dst[idx] = buf[it];
-        else if (b && d == a)
-            V[c0 + c] = buf[it];
+        if (idx < P.n)
+            P.X[idx] = buf[it];
+        else if (P.b && d == P.a)
+            P.V[c0 + c] = buf[it];
     }
 }
 
-// Inverse column pass for one class of columns: phase 0 handles c >= b (length
-// a) and, when b > 0, re-evaluates V_c = P_c(w_a) from the restored
-// coefficients; phase 1 handles c < b (length a + 1).  Tiles [tile0, tile0 +
-// tiles) are covered; columns of the other class inside a tile are skipped.
-template <class Mod, int LOGC>
-__global__ __launch_bounds__(kThreads) void k_col_inv(Mod md, Tables<typename Mod::Word> T, typename Mod::Word* X,
-                                                      uint32_t logW, uint32_t a, uint32_t b, uint32_t M,
-                                                      typename Mod::Word* V, int phase, uint32_t tile0,
-                                                      uint32_t tiles) {
-    using Word = typename Mod::Word;
-    constexpr uint32_t C = 1u << LOGC;
-    Word* buf = lds_buf<Word>();
-    const uint32_t c0 = (tile0 + xcd_remap(blockIdx.x, tiles)) * C;
-    const uint64_t W = 1ull << logW;
-    const uint32_t len = phase ? a + 1 : a;
-    uint32_t Mg = 1;
-    while (Mg < len) Mg <<= 1;
-    for (uint32_t it = threadIdx.x; it < M * C; it += blockDim.x) {
-        const uint32_t c = it & (C - 1), d = it >> LOGC;
-        const uint32_t col = c0 + c;
-        const bool mine = phase ? (col < b) : (col >= b);
-        buf[it] = (mine && d < len) ? X[col + (uint64_t)d * W] : Word(0);
-    }
-    __syncthreads();
-    gitft(md, T, buf, LOGC, Mg, len, 0);
-    for (uint32_t it = threadIdx.x; it < len * C; it += blockDim.x) {
-        const uint32_t c = it & (C - 1), d = it >> LOGC;
-        const uint32_t col = c0 + c;
-        const bool mine = phase ? (col < b) : (col >= b);
-        if (mine) X[col + (uint64_t)d * W] = buf[it];
-    }
-    if (phase == 0 && b) {
-        __syncthreads();
-        dif_forward(md, T, buf, LOGC, M, a, a + 1, 0);
-        for (uint32_t c = threadIdx.x; c < C; c += blockDim.x)
-            if (c0 + c >= b) V[c0 + c] = buf[a * C + c];
-    }
-}
-
-// --------------------------------------------------------------- row pass
-// Forward row pass: workgroup j < a transforms full row j (global block index
-// j at size W); workgroup a (when b > 0) builds the last row from its b slots
-// and V_c (c >= b) and keeps b outputs.
+// Forward row pass: row j < a is transformed in full (global block index j at
+// size W); row a (when b > 0) is built from its b slots and V_c (c >= b) and
+// keeps b outputs.
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_row_fwd(Mod md, Tables<typename Mod::Word> T, typename Mod::Word* X,
-                                                      uint32_t logW, uint32_t a, uint32_t b,
-                                                      const typename Mod::Word* V) {
+__device__ void row_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T,
+                             const TwoPass<typename Mod::Word>& P, uint32_t j) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
-    const uint32_t j = blockIdx.x;
-    const uint32_t W = 1u << logW;
-    Word* row = X + (uint64_t)j * W;
-    if (j < a) {
+    const uint32_t W = 1u << P.logW;
+    Word* row = P.X + (uint64_t)j * W;
+    if (j < P.a) {
         for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = row[i];
         __syncthreads();
         dif_forward(md, T, buf, 0, W, 0, W, j);
         for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) row[i] = buf[i];
     } else {
-        for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = i < b ? row[i] : V[i];
+        for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = i < P.b ? row[i] : P.V[i];
         __syncthreads();
-        dif_forward(md, T, buf, 0, W, 0, b, a);
-        for (uint32_t i = threadIdx.x; i < b; i += blockDim.x) row[i] = buf[i];
+        dif_forward(md, T, buf, 0, W, 0, P.b, P.a);
+        for (uint32_t i = threadIdx.x; i < P.b; i += blockDim.x) row[i] = buf[i];
     }
 }
 
-// Inverse row pass.  Workgroups j < a invert full row j (global block index j
-// at size W).  Workgroups a + k invert piece k of the partial last row: the
-// dyadic blocks of its b known outputs that the last-row inverse would
-// otherwise invert one after another (they read only known outputs, so they
-// run here, in parallel with the rows).  With Y non-null, values are first
-// multiplied pointwise by Y (the product step fused into the load).
+// Inverse row pass, item k: k < a inverts full row k (global block index k at
+// size W); k >= a inverts piece k - a of the partial last row -- the dyadic
+// blocks of its b known outputs that the last-row inverse would otherwise
+// invert one after another (they read only known outputs, so they run here,
+// in parallel with the rows).  With P.Y set, values are first multiplied
+// pointwise by Y (the product step fused into the load).
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_row_inv(Mod md, Tables<typename Mod::Word> T, typename Mod::Word* X,
-                                                      const typename Mod::Word* Y, uint32_t logW, uint32_t a,
-                                                      PieceList pieces) {
+__device__ void row_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
+                             const TwoPass<typename Mod::Word>& P, uint32_t k) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
-    const uint32_t W = 1u << logW;
-    uint64_t start;
+    const uint32_t W = 1u << P.logW;
+    uint64_t start, g;
     uint32_t len;
-    uint64_t g;
-    if (blockIdx.x < a) {
-        start = (uint64_t)blockIdx.x * W;
+    if (k < P.a) {
+        start = (uint64_t)k * W;
         len = W;
-        g = blockIdx.x;
+        g = k;
     } else {
-        const Piece pc = pieces.p[blockIdx.x - a];
-        start = (uint64_t)a * W + pc.off;
+        const Piece pc = gitft_piece(W, P.b, P.a, (int)(k - P.a));
+        start = (uint64_t)P.a * W + pc.off;
         len = pc.size;
         g = pc.g;
     }
-    Word* row = X + start;
-    if (Y) {
-        const Word* yr = Y + start;
+    Word* row = P.X + start;
+    if (P.Y) {
+        const Word* yr = P.Y + start;
         for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) buf[i] = md.mul(row[i], yr[i]);
     } else {
         for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) buf[i] = row[i];
@@ -250,22 +217,170 @@ __global__ __launch_bounds__(kThreads) void k_row_inv(Mod md, Tables<typename Mo
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) row[i] = buf[i];
 }
 
-// Inverse of the last row after its pieces were inverted by k_row_inv: the b
-// slots now hold the pieces' coefficients and the W - b values V_c are the
-// known coefficients of the block; the remaining (elementwise) steps of the
+// Number of inverse-row items: a rows plus the last row's pieces.
+__host__ __device__ inline uint32_t row_inv_items(uint32_t W, uint32_t a, uint32_t b) {
+    if (!b) return a;
+    Piece pcs[kMaxPieces];
+    return a + (uint32_t)gitft_pieces(W, b, a, pcs);
+}
+
+// Inverse column pass over one tile for one class of columns: phase 0 handles
+// c >= b (length a) and, when b > 0, re-evaluates V_c = P_c(w_a) from the
+// restored coefficients; phase 1 handles c < b (length a + 1).  Columns of the
+// other class inside the tile are skipped.
+template <class Mod, int LOGC>
+__device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
+                             const TwoPass<typename Mod::Word>& P, int phase, uint32_t tile) {
+    using Word = typename Mod::Word;
+    constexpr uint32_t C = 1u << LOGC;
+    Word* buf = lds_buf<Word>();
+    const uint32_t c0 = tile * C;
+    const uint64_t W = 1ull << P.logW;
+    const uint32_t len = phase ? P.a + 1 : P.a;
+    uint32_t Mg = 1;
+    while (Mg < len) Mg <<= 1;
+    for (uint32_t it = threadIdx.x; it < P.M * C; it += blockDim.x) {
+        const uint32_t c = it & (C - 1), d = it >> LOGC;
+        const uint32_t col = c0 + c;
+        const bool mine = phase ? (col < P.b) : (col >= P.b);
+        buf[it] = (mine && d < len) ? P.X[col + (uint64_t)d * W] : Word(0);
+    }
+    __syncthreads();
+    gitft(md, T, buf, LOGC, Mg, len, 0);
+    for (uint32_t it = threadIdx.x; it < len * C; it += blockDim.x) {
+        const uint32_t c = it & (C - 1), d = it >> LOGC;
+        const uint32_t col = c0 + c;
+        const bool mine = phase ? (col < P.b) : (col >= P.b);
+        if (mine) P.X[col + (uint64_t)d * W] = buf[it];
+    }
+    if (phase == 0 && P.b) {
+        __syncthreads();
+        dif_forward(md, T, buf, LOGC, P.M, P.a, P.a + 1, 0);
+        for (uint32_t c = threadIdx.x; c < C; c += blockDim.x)
+            if (c0 + c >= P.b) P.V[c0 + c] = buf[P.a * C + c];
+    }
+}
+
+// Inverse of the last row after its pieces were inverted by the row pass: the
+// b slots hold the pieces' coefficients and the W - b values V_c are the known
+// coefficients of the block; the remaining (elementwise) steps of the
 // truncated inverse recover the b column values P_c(w_a), c < b.
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_last_inv(Mod md, Tables<typename Mod::Word> T, typename Mod::Word* X,
-                                                       uint32_t logW, uint32_t a, uint32_t b,
-                                                       const typename Mod::Word* V) {
+__device__ void last_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
+                              const TwoPass<typename Mod::Word>& P) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
-    const uint32_t W = 1u << logW;
-    Word* row = X + (uint64_t)a * W;
-    for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = i < b ? row[i] : V[i];
+    const uint32_t W = 1u << P.logW;
+    Word* row = P.X + (uint64_t)P.a * W;
+    for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = i < P.b ? row[i] : P.V[i];
     __syncthreads();
-    gitft(md, T, buf, 0, W, b, a, /*skip_full=*/true);
-    for (uint32_t i = threadIdx.x; i < b; i += blockDim.x) row[i] = buf[i];
+    gitft(md, T, buf, 0, W, P.b, P.a, /*skip_full=*/true);
+    for (uint32_t i = threadIdx.x; i < P.b; i += blockDim.x) row[i] = buf[i];
+}
+
+// ---- single transform: one launch per pass, geometry by value
+template <class Mod, int LOGC>
+__global__ __launch_bounds__(kThreads) void k_col_fwd(Mod md, Tables<typename Mod::Word> T,
+                                                      TwoPass<typename Mod::Word> P, uint32_t tiles) {
+    col_fwd_body<Mod, LOGC>(md, T, P, xcd_remap(blockIdx.x, tiles));
+}
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_row_fwd(Mod md, Tables<typename Mod::Word> T,
+                                                      TwoPass<typename Mod::Word> P) {
+    row_fwd_body(md, T, P, blockIdx.x);
+}
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_row_inv(Mod md, Tables<typename Mod::Word> T,
+                                                      TwoPass<typename Mod::Word> P) {
+    row_inv_body(md, T, P, blockIdx.x);
+}
+template <class Mod, int LOGC>
+__global__ __launch_bounds__(kThreads) void k_col_inv(Mod md, Tables<typename Mod::Word> T,
+                                                      TwoPass<typename Mod::Word> P, int phase, uint32_t tile0,
+                                                      uint32_t tiles) {
+    col_inv_body<Mod, LOGC>(md, T, P, phase, tile0 + xcd_remap(blockIdx.x, tiles));
+}
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_last_inv(Mod md, Tables<typename Mod::Word> T,
+                                                       TwoPass<typename Mod::Word> P) {
+    last_inv_body(md, T, P);
+}
+
+// ---- batches: every workgroup takes one (record, index) item of a work list
+// for one pass; records are the geometries of the batch's transforms.
+struct Item {
+    uint32_t rec;
+    uint32_t idx;
+};
+template <class Mod, int LOGC>
+__global__ __launch_bounds__(kThreads) void k_col_fwd_list(Mod md, Tables<typename Mod::Word> T,
+                                                           const TwoPass<typename Mod::Word>* recs,
+                                                           const Item* items) {
+    const Item it = items[blockIdx.x];
+    col_fwd_body<Mod, LOGC>(md, T, recs[it.rec], it.idx);
+}
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_row_fwd_list(Mod md, Tables<typename Mod::Word> T,
+                                                           const TwoPass<typename Mod::Word>* recs,
+                                                           const Item* items) {
+    const Item it = items[blockIdx.x];
+    row_fwd_body(md, T, recs[it.rec], it.idx);
+}
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_row_inv_list(Mod md, Tables<typename Mod::Word> T,
+                                                           const TwoPass<typename Mod::Word>* recs,
+                                                           const Item* items) {
+    const Item it = items[blockIdx.x];
+    row_inv_body(md, T, recs[it.rec], it.idx);
+}
+template <class Mod, int LOGC>
+__global__ __launch_bounds__(kThreads) void k_col_inv_list(Mod md, Tables<typename Mod::Word> T,
+                                                           const TwoPass<typename Mod::Word>* recs,
+                                                           const Item* items, int phase) {
+    const Item it = items[blockIdx.x];
+    col_inv_body<Mod, LOGC>(md, T, recs[it.rec], phase, it.idx);
+}
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_last_inv_list(Mod md, Tables<typename Mod::Word> T,
+                                                            const TwoPass<typename Mod::Word>* recs,
+                                                            const Item* items) {
+    last_inv_body(md, T, recs[items[blockIdx.x].rec]);
+}
+
+// ---- batches of single-workgroup instances: a persistent kernel.  Each
+// workgroup repeatedly takes the next instance from an atomic counter (the
+// list is sorted by decreasing size, so the longest instances start first) and
+// runs it entirely in LDS: a product when B is set, else a forward transform.
+template <class Word>
+struct SmallJob {
+    const Word* A;
+    const Word* B;
+    Word* X;
+    uint32_t m, nb, M;
+};
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_small_list(Mod md, Tables<typename Mod::Word> T,
+                                                         const SmallJob<typename Mod::Word>* jobs, uint32_t count,
+                                                         uint32_t* counter) {
+    __shared__ uint32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t k = next;
+        __syncthreads();
+        if (k >= count) break;
+        const SmallJob<typename Mod::Word> J = jobs[k];
+        if (J.B)
+            small_mul_body(md, T, J.A, J.m, J.B, J.nb, J.X, J.M);
+        else
+            small_forward_body(md, T, J.X, J.m, J.M);
+        __syncthreads();
+    }
+}
+
+// Reset of the work counter, as a kernel so that a captured graph replays it.
+__global__ void k_reset_counter(uint32_t* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
 // ---------------------------------------------------------- elementwise
@@ -282,6 +397,49 @@ __global__ __launch_bounds__(kThreads) void k_copy_pad(Word* dst, uint64_t n_dst
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_dst;
          i += (uint64_t)gridDim.x * blockDim.x)
         dst[i] = i < n_src ? src[i] : Word(0);
+}
+
+// Signed integers to residues: dst[i] = src[i] mod p in [0, p).
+template <class Word>
+__global__ __launch_bounds__(kThreads) void k_from_signed(Word* dst, const int64_t* src, uint64_t n, uint64_t p) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const int64_t v = src[i];
+        uint64_t r;
+        if (v >= 0)
+            r = (uint64_t)v % p;
+        else
+            r = (p - ((uint64_t)(-(v + 1)) % p) - 1) % p;   // -(v+1) avoids overflow at INT64_MIN
+        dst[i] = (Word)r;
+    }
+}
+
+// Chinese remaindering of three residue vectors (Garner's mixed-radix form):
+// x = r1 + p1 t2 + p1 p2 t3 with t2 = (r2 - r1) p1^-1 mod p2 and
+// t3 = (r3 - (r1 + p1 t2)) (p1 p2)^-1 mod p3, so 0 <= x < M = p1 p2 p3; the
+// output is the signed representative in [-M/2, M/2), little-endian 128-bit.
+struct Crt3 {
+    uint64_t p1, p2, p3;
+    uint64_t inv_p1_mod_p2, inv_p1p2_mod_p3, p1p2_mod_p3;
+    unsigned __int128 M, half_M;
+};
+__device__ __forceinline__ uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t p) {
+    return (uint64_t)(((unsigned __int128)a * b) % p);
+}
+__global__ __launch_bounds__(kThreads) void k_crt3(Crt3 c, const uint32_t* r1, const uint32_t* r2, const uint32_t* r3,
+                                                  uint64_t* out, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t a1 = r1[i], a2 = r2[i], a3 = r3[i];
+        const uint64_t d2 = (a2 + c.p2 - a1 % c.p2) % c.p2;
+        const uint64_t t2 = mulmod64(d2, c.inv_p1_mod_p2, c.p2);
+        const uint64_t x12 = a1 + c.p1 * t2;                         // < p1 p2 < 2^62
+        const uint64_t x12m = x12 % c.p3;
+        const uint64_t d3 = (a3 + c.p3 - x12m) % c.p3;
+        const uint64_t t3 = mulmod64(d3, c.inv_p1p2_mod_p3, c.p3);
+        unsigned __int128 x = (unsigned __int128)x12 + (unsigned __int128)(c.p1 * c.p2) * t3;
+        if (x >= c.half_M) x -= c.M;                                 // two's complement wrap to signed
+        out[2 * i] = (uint64_t)x;
+        out[2 * i + 1] = (uint64_t)(x >> 64);
+    }
 }
 
 }  // namespace tft

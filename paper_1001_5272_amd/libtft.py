@@ -40,6 +40,14 @@ SIGNATURES = {
     "poly_mul_padded": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp, _vp, _vp]),
     "tft_plan_info": (_st, [_vp, _sz, _vp]),
     "tft_set_plan_override": (_st, [_vp, ctypes.c_uint]),
+    "tft_batch_create": (_st, [_vp, _vp, _sz, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "tft_batch_run": (_st, [_vp, _vp]),
+    "tft_batch_info": (_st, [_vp, _vp]),
+    "tft_batch_destroy": (None, [_vp]),
+    "poly_mul_batch": (_st, [_vp, _vp, _sz, _vp]),
+    "tft_forward_batch": (_st, [_vp, _vp, _vp, _sz, _vp]),
+    "tft_from_signed": (_st, [_vp, _vp, _sz, _vp, _vp]),
+    "tft_crt3": (_st, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "tft_timing_enable": (_st, [_vp, ctypes.c_int]),
     "tft_timing_read": (_st, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
     "tft_timing_reset": (_st, [_vp]),
@@ -48,13 +56,22 @@ SIGNATURES = {
 }
 
 KERNEL_NAMES = ["small_fwd", "small_inv", "small_mul", "col_fwd", "row_fwd", "row_inv", "col_inv_short",
-                "last_inv", "col_inv_long", "pointwise", "copy_pad"]
+                "last_inv", "col_inv_long", "pointwise", "copy_pad", "small_list", "crt3"]
 
 
 class TftError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
         super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+class MulDesc(ctypes.Structure):
+    _fields_ = [("a", _vp), ("la", _sz), ("b", _vp), ("lb", _sz), ("out", _vp), ("work", _vp)]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("count", _sz), ("single_workgroup", _sz), ("two_pass", _sz), ("device_bytes", _sz),
+                ("launches", ctypes.c_uint)]
 
 
 class PlanDesc(ctypes.Structure):
@@ -216,3 +233,96 @@ def tft_timing_read(ctx: Context) -> dict:
 
 def tft_kernel_name(i: int) -> str:
     return load().tft_kernel_name(i).decode()
+
+
+def _descs(ctx, jobs, products=True):
+    """jobs: list of (A, B, X, Y) tensors (Y may be None) for products, or of
+    X tensors for forward transforms."""
+    arr = (MulDesc * len(jobs))()
+    for i, j in enumerate(jobs):
+        if products:
+            A, B, X, Y = j
+            arr[i] = MulDesc(ctx._t(A, "A").value, A.numel(), ctx._t(B, "B").value, B.numel(), ctx._t(X, "X").value,
+                             ctx._t(Y, "Y").value if Y is not None else None)
+        else:
+            arr[i] = MulDesc(ctx._t(j, "X").value, j.numel(), None, 0, ctx._t(j, "X").value, None)
+    return arr
+
+
+class Batch:
+    """A planned batch (tft_batch_create); run() enqueues it (tft_batch_run)."""
+
+    def __init__(self, ctx: Context, jobs, products=True):
+        self.ctx = ctx
+        self._keep = list(jobs)
+        arr = _descs(ctx, jobs, products)
+        h = _vp()
+        _check(load().tft_batch_create(ctx.handle, arr, len(jobs), 1 if products else 0, ctypes.byref(h)),
+               "tft_batch_create")
+        self.handle = h
+
+    def run(self, stream=None):
+        _check(load().tft_batch_run(self.handle, _stream(stream)), "tft_batch_run")
+
+    def info(self) -> dict:
+        d = BatchDesc()
+        _check(load().tft_batch_info(self.handle, ctypes.byref(d)), "tft_batch_info")
+        return {f: getattr(d, f) for f, _ in BatchDesc._fields_}
+
+    def close(self):
+        if self.handle:
+            load().tft_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tft_batch_create(ctx: Context, jobs, products=True) -> Batch:
+    return Batch(ctx, jobs, products)
+
+
+def tft_batch_run(batch: Batch, stream=None):
+    batch.run(stream)
+
+
+def tft_batch_info(batch: Batch) -> dict:
+    return batch.info()
+
+
+def tft_batch_destroy(batch: Batch):
+    batch.close()
+
+
+def poly_mul_batch(ctx: Context, jobs, stream=None):
+    """jobs: list of (A, B, X, Y) tensors; Y may be None for short products."""
+    arr = _descs(ctx, jobs, True)
+    _check(load().poly_mul_batch(ctx.handle, arr, len(jobs), _stream(stream)), "poly_mul_batch")
+
+
+def tft_forward_batch(ctx: Context, xs, stream=None):
+    ptrs = (_vp * len(xs))(*[ctx._t(x, "X").value for x in xs])
+    ns = (_sz * len(xs))(*[x.numel() for x in xs])
+    _check(load().tft_forward_batch(ctx.handle, ptrs, ns, len(xs), _stream(stream)), "tft_forward_batch")
+
+
+def tft_from_signed(ctx: Context, src, dst, stream=None):
+    if src.dtype != torch.int64 or not src.is_cuda or not src.is_contiguous():
+        raise TypeError("src must be a contiguous int64 CUDA tensor")
+    _check(load().tft_from_signed(ctx.handle, _vp(src.data_ptr()), src.numel(), ctx._t(dst, "dst"), _stream(stream)),
+           "tft_from_signed")
+    return dst
+
+
+def tft_crt3(ctxs, r1, r2, r3, out, stream=None):
+    """out: int64 tensor of 2 n entries (little-endian 128-bit values)."""
+    hs = (_vp * 3)(*[c.handle.value for c in ctxs])
+    n = r1.numel()
+    if out.dtype != torch.int64 or out.numel() != 2 * n or not out.is_contiguous():
+        raise TypeError("out must be a contiguous int64 tensor of 2 n entries")
+    _check(load().tft_crt3(hs, ctxs[0]._t(r1, "r1"), ctxs[1]._t(r2, "r2"), ctxs[2]._t(r3, "r3"), n,
+                           _vp(out.data_ptr()), _stream(stream)), "tft_crt3")
+    return out

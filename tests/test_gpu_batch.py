@@ -1,0 +1,173 @@
+"""GPU parity for batched products and transforms, graph replay, and the
+three-prime exact integer product.  Bit-exact against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import PRIMES
+
+pytestmark = pytest.mark.gpu
+libtft = pytest.importorskip("paper_1001_5272_amd.libtft")
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx998():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = libtft.Context(*PRIMES["p998244353"])
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctxgl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = libtft.Context(*PRIMES["goldilocks"])
+    yield c
+    c.close()
+
+
+def make_jobs(ctx, p, lens, seed):
+    dt = np.uint32 if ctx.word_bytes == 4 else np.uint64
+    jobs, host = [], []
+    for i, (la, lb) in enumerate(lens):
+        A = synth.residues(p, la, seed + 2 * i)
+        B = synth.residues(p, lb, seed + 2 * i + 1)
+        r = la + lb - 1
+        dA = torch.from_numpy(A.astype(dt)).cuda()
+        dB = torch.from_numpy(B.astype(dt)).cuda()
+        X = torch.zeros(r, dtype=ctx.dtype, device="cuda")
+        Y = torch.zeros(r, dtype=ctx.dtype, device="cuda")
+        jobs.append((dA, dB, X, Y))
+        host.append((A, B))
+    return jobs, host
+
+
+def expected(p, g, A, B):
+    if len(A) * len(B) <= 2_000_000:
+        return oracle.mul_schoolbook(p, A, B)
+    return oracle.mul_padded(p, g, A, B)
+
+
+def seeded_lengths(n, lo, hi, seed):
+    la = synth.log_uniform_lengths(lo, hi, n, seed)
+    lb = synth.log_uniform_lengths(lo, hi, n, seed + 1)
+    return list(zip(la.tolist(), lb.tolist()))
+
+
+@pytest.mark.parametrize("which", ["p998244353", "goldilocks"])
+def test_batch_products_match_oracle_and_solo(ctx998, ctxgl, which):
+    ctx = ctx998 if which == "p998244353" else ctxgl
+    p, g = PRIMES[which]
+    lens = seeded_lengths(120, 1, 12000, 77) + [(1, 1), (1, 5), (7, 1), (4096, 4097), (9000, 9000), (1, 30000)]
+    print(f"[gpu] batch of {len(lens)} products, {which}", flush=True)
+    jobs, host = make_jobs(ctx, p, lens, 500)
+    b = libtft.Batch(ctx, jobs)
+    info = b.info()
+    assert info["single_workgroup"] > 0 and info["two_pass"] > 0, info
+    b.run()
+    torch.cuda.synchronize()
+    for (A, B), (_, _, X, _) in zip(host, jobs):
+        got = X.cpu().numpy().astype(np.uint64)
+        ref = expected(p, g, A, B)
+        assert (got == ref).all(), f"batch product {len(A)}x{len(B)} differs"
+    # the same instance alone gives the same words
+    for k in [0, 3, len(jobs) - 3, len(jobs) - 1]:
+        dA, dB, X, Y = jobs[k]
+        X2 = torch.empty_like(X)
+        Y2 = torch.empty_like(Y)
+        libtft.poly_mul(ctx, dA, dB, X2, Y2)
+        torch.cuda.synchronize()
+        assert torch.equal(X, X2)
+    b.close()
+
+
+def test_batch_graph_replay(ctx998):
+    p, g = PRIMES["p998244353"]
+    lens = seeded_lengths(40, 16, 20000, 91)
+    jobs, host = make_jobs(ctx998, p, lens, 900)
+    b = libtft.Batch(ctx998, jobs)
+    refs = [expected(p, g, A, B) for A, B in host]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run()                      # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.run()
+    for rep in range(4):
+        for (_, _, X, _) in jobs:
+            X.zero_()                # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for ref, (_, _, X, _) in zip(refs, jobs):
+            assert (X.cpu().numpy().astype(np.uint64) == ref).all(), f"replay {rep} differs"
+    b.close()
+
+
+def test_poly_mul_batch_convenience(ctxgl):
+    p, g = PRIMES["goldilocks"]
+    lens = seeded_lengths(30, 1, 9000, 31)
+    jobs, host = make_jobs(ctxgl, p, lens, 300)
+    libtft.poly_mul_batch(ctxgl, jobs)
+    torch.cuda.synchronize()
+    for (A, B), (_, _, X, _) in zip(host, jobs):
+        assert (X.cpu().numpy().astype(np.uint64) == expected(p, g, A, B)).all()
+
+
+@pytest.mark.parametrize("which", ["p998244353", "goldilocks"])
+def test_forward_batch(ctx998, ctxgl, which):
+    ctx = ctx998 if which == "p998244353" else ctxgl
+    p, g = PRIMES[which]
+    ns = [1, 2, 3, 100, 2499, 8191, 8193, 20000, 65537] + synth.log_uniform_lengths(1, 30000, 20, 5).tolist()
+    dt = np.uint32 if ctx.word_bytes == 4 else np.uint64
+    host = [synth.residues(p, n, 40 + i) for i, n in enumerate(ns)]
+    xs = [torch.from_numpy(h.astype(dt)).cuda() for h in host]
+    libtft.tft_forward_batch(ctx, xs)
+    torch.cuda.synchronize()
+    for F, X in zip(host, xs):
+        assert (X.cpu().numpy().astype(np.uint64) == oracle.fft_padded(p, g, F)).all(), len(F)
+
+
+def test_exact_integer_product_crt():
+    ctxs = [libtft.Context(p, g) for p, g in synth.CRT_PRIMES]
+    try:
+        for m, nb in [(1, 1), (5, 3), (200, 300), (3000, 5000), (20000, 12345)]:
+            print(f"[gpu] crt product {m}x{nb}", flush=True)
+            a = synth.signed24(m, 5001 + m)
+            b = synth.signed24(nb, 5002 + nb)
+            r = m + nb - 1
+            da = torch.from_numpy(a).cuda()
+            db = torch.from_numpy(b).cuda()
+            res = []
+            for c in ctxs:
+                A = torch.empty(m, dtype=torch.uint32, device="cuda")
+                B = torch.empty(nb, dtype=torch.uint32, device="cuda")
+                libtft.tft_from_signed(c, da, A)
+                libtft.tft_from_signed(c, db, B)
+                X = torch.empty(r, dtype=torch.uint32, device="cuda")
+                Y = torch.empty(r, dtype=torch.uint32, device="cuda")
+                libtft.poly_mul(c, A, B, X, Y)
+                res.append(X)
+            out = torch.empty(2 * r, dtype=torch.int64, device="cuda")
+            libtft.tft_crt3(ctxs, res[0], res[1], res[2], out)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy().view(np.uint64)
+            if m * nb <= 3_000_000:
+                ref = oracle.conv_i128(a, b, as_lohi=True)
+                assert (got == ref).all()
+            else:
+                for s in [0, 1, r // 3, r // 2, r - 2, r - 1]:
+                    v = (int(got[2 * s + 1]) << 64) | int(got[2 * s])
+                    if v >= 1 << 127:
+                        v -= 1 << 128
+                    assert v == oracle.conv_coeff_i128(a, b, s), s
+    finally:
+        for c in ctxs:
+            c.close()
