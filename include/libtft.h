@@ -140,6 +140,34 @@ void tft_batch_destroy(tft_batch* batch);
 tft_status poly_mul_batch(tft_ctx* ctx, const tft_mul_desc* d, size_t count, void* hip_stream);
 tft_status tft_forward_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t count, void* hip_stream);
 
+/* ---------------------------------------------------------------- serving
+ * A request queue with continuous batching.  tft_queue_create allocates a
+ * device pool of pool_words words and starts a worker thread.
+ * tft_queue_submit appends a product (a tft_mul_desc; its work field is
+ * ignored: workspace comes from the pool) and returns a ticket at once; the
+ * operands must stay valid and untouched until the ticket completes.
+ * Requests are admitted in arrival order while their workspace (r = la + lb - 1
+ * words, the in-place footprint -- not 2^ceil(lg r)) fits in the pool and
+ * fewer than max_inflight requests are on the device; each group admitted
+ * together runs as one batch, and consecutive batches run on two streams so
+ * that they overlap on the device.  Submit returns TFT_ERANGE for a request
+ * that could never fit and TFT_EAGAIN when the pending list is full
+ * (2^20 requests).  poll reports completion without blocking; wait blocks;
+ * completion_ns gives the steady-clock time (ns) at which the worker saw the
+ * request complete (0 while pending).  A request whose batch failed reports
+ * TFT_EDEVICE.  destroy waits for all submitted requests. */
+typedef struct tft_queue tft_queue;
+typedef struct {
+    uint64_t submitted, completed, batches, deferred, pending, inflight, pool_words, pool_used_max;
+} tft_queue_desc;
+tft_status tft_queue_create(tft_ctx* ctx, size_t pool_words, size_t max_inflight, tft_queue** out);
+tft_status tft_queue_submit(tft_queue* q, const tft_mul_desc* d, uint64_t* ticket);
+tft_status tft_queue_poll(tft_queue* q, uint64_t ticket, int* done);
+tft_status tft_queue_wait(tft_queue* q, uint64_t ticket);
+tft_status tft_queue_completion_ns(tft_queue* q, uint64_t ticket, uint64_t* ns);
+tft_status tft_queue_stats(tft_queue* q, tft_queue_desc* out);
+void tft_queue_destroy(tft_queue* q);
+
 /* ------------------------------------------------ exact integer products
  * tft_from_signed: dst[i] = src[i] mod p in [0, p) for n signed 64-bit inputs
  * (src on the device, dst n words of ctx's width).

@@ -8,6 +8,14 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "libtft.h"
@@ -704,6 +712,196 @@ tft_status batch_once(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pro
 
 }  // namespace
 
+// ================================================================= serving
+// A request queue with continuous batching.  submit() appends a product to a
+// pending FIFO and returns a ticket.  A worker thread admits pending requests
+// in order while their workspace (r words, the in-place footprint of B's
+// transform) fits in the queue's device pool and fewer than max_inflight
+// requests are on the device; each group of newly admitted requests becomes
+// one batch, launched on one of two streams in turn so that consecutive
+// batches overlap on the device.  The worker polls the batches' completion
+// events, releases their workspace, records completion times and admits more.
+namespace {
+
+struct QReq {
+    uint64_t ticket;
+    tft_mul_desc d;
+    uint64_t r;
+    uint64_t off;      // workspace offset in the pool (words), ~0 if none needed
+};
+
+struct QBatch {
+    tft_batch* B;
+    hipEvent_t done;
+    std::vector<QReq> reqs;
+};
+
+// First-fit allocator over word offsets of the pool, coalescing on free.
+struct PoolAlloc {
+    std::map<uint64_t, uint64_t> free_;   // offset -> length
+    uint64_t total = 0, used = 0;
+    void init(uint64_t words) {
+        free_.clear();
+        free_[0] = words;
+        total = words;
+        used = 0;
+    }
+    bool alloc(uint64_t n, uint64_t* off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const uint64_t rest = it->second - n, o = it->first + n;
+                free_.erase(it);
+                if (rest) free_[o] = rest;
+                used += n;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n) {
+        used -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace
+
+struct tft_queue {
+    tft_ctx* ctx;
+    void* pool;
+    size_t pool_words, max_inflight, max_pending, max_batch;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<QReq> pending;
+    std::deque<QBatch> inflight;
+    size_t inflight_reqs;
+    PoolAlloc alloc;
+    std::unordered_map<uint64_t, uint64_t> done_ns;   // ticket -> completion time (steady clock)
+    std::unordered_map<uint64_t, int> failed;
+    uint64_t next_ticket;
+    bool stop;
+    std::thread worker;
+    hipStream_t streams[2];
+    int next_stream;
+    uint64_t n_submitted, n_completed, n_batches, n_deferred, max_pool_used;
+    tft_status error;
+};
+
+namespace {
+
+void queue_worker(tft_queue* q) {
+    (void)hipSetDevice(q->ctx->device);
+    const unsigned w = q->ctx->wbytes;
+    std::unique_lock<std::mutex> lk(q->mu);
+    for (;;) {
+        bool progress = false;
+        // retire finished batches
+        for (auto it = q->inflight.begin(); it != q->inflight.end();) {
+            const hipError_t e = hipEventQuery(it->done);
+            if (e == hipErrorNotReady) {
+                ++it;
+                continue;
+            }
+            const uint64_t t = now_ns();
+            for (const QReq& rq : it->reqs) {
+                q->done_ns[rq.ticket] = t;
+                if (e != hipSuccess) q->failed[rq.ticket] = 1;
+                if (rq.off != ~0ull) q->alloc.release(rq.off, rq.r);
+            }
+            q->inflight_reqs -= it->reqs.size();
+            q->n_completed += it->reqs.size();
+            if (e != hipSuccess) q->error = TFT_EDEVICE;
+            (void)hipEventDestroy(it->done);
+            tft_batch_destroy(it->B);
+            it = q->inflight.erase(it);
+            progress = true;
+        }
+        if (progress) q->cv_done.notify_all();
+        // admit in arrival order and launch one batch (at most two batches in flight)
+        if (!q->pending.empty() && q->inflight.size() < 2) {
+            std::vector<QReq> group;
+            while (!q->pending.empty() && group.size() < q->max_batch && q->inflight_reqs + group.size() < q->max_inflight) {
+                QReq rq = q->pending.front();
+                const bool need_ws = rq.r > ((w == 4) ? 8192u : 4096u);
+                if (need_ws) {
+                    uint64_t off;
+                    if (!q->alloc.alloc(rq.r, &off)) {
+                        q->n_deferred++;
+                        break;   // keep FIFO order: wait for space
+                    }
+                    rq.off = off;
+                    rq.d.work = (char*)q->pool + off * w;
+                } else {
+                    rq.off = ~0ull;
+                    rq.d.work = nullptr;
+                }
+                q->pending.pop_front();
+                group.push_back(rq);
+            }
+            q->max_pool_used = std::max<uint64_t>(q->max_pool_used, q->alloc.used);
+            if (!group.empty()) {
+                q->inflight_reqs += group.size();
+                lk.unlock();
+                std::vector<tft_mul_desc> ds(group.size());
+                for (size_t i = 0; i < group.size(); i++) ds[i] = group[i].d;
+                tft_batch* B = nullptr;
+                hipEvent_t ev = nullptr;
+                const hipStream_t st = q->streams[q->next_stream];
+                q->next_stream ^= 1;
+                tft_status s = tft_batch_create(q->ctx, ds.data(), ds.size(), 1, &B);
+                if (s == TFT_OK) s = tft_batch_run(B, st);
+                if (s == TFT_OK && (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+                                    hipEventRecord(ev, st) != hipSuccess))
+                    s = TFT_EDEVICE;
+                lk.lock();
+                if (s != TFT_OK) {
+                    // fail the group now; its workspace is released immediately
+                    if (B) { (void)hipStreamSynchronize(st); tft_batch_destroy(B); }
+                    if (ev) (void)hipEventDestroy(ev);
+                    const uint64_t t = now_ns();
+                    for (const QReq& rq : group) {
+                        q->done_ns[rq.ticket] = t;
+                        q->failed[rq.ticket] = 1;
+                        if (rq.off != ~0ull) q->alloc.release(rq.off, rq.r);
+                    }
+                    q->inflight_reqs -= group.size();
+                    q->n_completed += group.size();
+                    q->error = s;
+                    q->cv_done.notify_all();
+                } else {
+                    q->inflight.push_back(QBatch{B, ev, std::move(group)});
+                    q->n_batches++;
+                }
+                continue;
+            }
+        }
+        if (q->stop && q->pending.empty() && q->inflight.empty()) break;
+        // nothing to do right now: sleep briefly (new work or completions wake us)
+        q->cv_work.wait_for(lk, std::chrono::microseconds(q->inflight.empty() ? 500 : 20));
+    }
+}
+
+}  // namespace
+
 // ============================================================== C entry points
 extern "C" {
 
@@ -991,6 +1189,110 @@ tft_status tft_crt3(tft_ctx* const ctxs[3], const void* r1, const void* r2, cons
     launch(ctx, TFT_K_CRT, tft::k_crt3, dim3((uint32_t)blocks), dim3(kThreads), 0, st, c, (const uint32_t*)r1,
            (const uint32_t*)r2, (const uint32_t*)r3, (uint64_t*)out, (uint64_t)n);
     return launch_status();
+}
+
+tft_status tft_queue_create(tft_ctx* ctx, size_t pool_words, size_t max_inflight, tft_queue** out) {
+    if (!ctx || !out || pool_words == 0 || max_inflight == 0) return TFT_EINVAL;
+    *out = nullptr;
+    DeviceGuard guard(ctx->device);
+    tft_queue* q = new (std::nothrow) tft_queue();
+    if (!q) return TFT_ENOMEM;
+    q->ctx = ctx;
+    q->pool_words = pool_words;
+    q->max_inflight = max_inflight;
+    q->max_pending = 1u << 20;
+    q->max_batch = 1024;
+    q->inflight_reqs = 0;
+    q->next_ticket = 1;
+    q->stop = false;
+    q->next_stream = 0;
+    q->n_submitted = q->n_completed = q->n_batches = q->n_deferred = q->max_pool_used = 0;
+    q->error = TFT_OK;
+    q->alloc.init(pool_words);
+    hipError_t e = hipMalloc(&q->pool, pool_words * ctx->wbytes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->streams[0], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->streams[1], hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (q->pool) (void)hipFree(q->pool);
+        delete q;
+        return e == hipErrorOutOfMemory ? TFT_ENOMEM : TFT_EDEVICE;
+    }
+    q->worker = std::thread(queue_worker, q);
+    *out = q;
+    return TFT_OK;
+}
+
+tft_status tft_queue_submit(tft_queue* q, const tft_mul_desc* d, uint64_t* ticket) {
+    if (!q || !d || !ticket || !d->a || !d->b || !d->out || d->la == 0 || d->lb == 0) return TFT_EINVAL;
+    const uint64_t r = d->la + d->lb - 1;
+    if (log2u(r) > q->ctx->v) return TFT_ERANGE;
+    if (r > q->pool_words) return TFT_ERANGE;   // could never be admitted
+    std::lock_guard<std::mutex> lk(q->mu);
+    if (q->pending.size() >= q->max_pending) return TFT_EAGAIN;
+    QReq rq;
+    rq.ticket = q->next_ticket++;
+    rq.d = *d;
+    rq.r = r;
+    rq.off = ~0ull;
+    q->pending.push_back(rq);
+    q->n_submitted++;
+    *ticket = rq.ticket;
+    q->cv_work.notify_one();
+    return TFT_OK;
+}
+
+tft_status tft_queue_poll(tft_queue* q, uint64_t ticket, int* done) {
+    if (!q || !done) return TFT_EINVAL;
+    std::lock_guard<std::mutex> lk(q->mu);
+    auto it = q->done_ns.find(ticket);
+    *done = it != q->done_ns.end();
+    if (*done && q->failed.count(ticket)) return TFT_EDEVICE;
+    return TFT_OK;
+}
+
+tft_status tft_queue_wait(tft_queue* q, uint64_t ticket) {
+    if (!q || ticket == 0) return TFT_EINVAL;
+    std::unique_lock<std::mutex> lk(q->mu);
+    if (ticket >= q->next_ticket) return TFT_EINVAL;
+    q->cv_done.wait(lk, [&] { return q->done_ns.count(ticket) != 0; });
+    return q->failed.count(ticket) ? TFT_EDEVICE : TFT_OK;
+}
+
+tft_status tft_queue_completion_ns(tft_queue* q, uint64_t ticket, uint64_t* ns) {
+    if (!q || !ns) return TFT_EINVAL;
+    std::lock_guard<std::mutex> lk(q->mu);
+    auto it = q->done_ns.find(ticket);
+    *ns = it == q->done_ns.end() ? 0 : it->second;
+    return TFT_OK;
+}
+
+tft_status tft_queue_stats(tft_queue* q, tft_queue_desc* out) {
+    if (!q || !out) return TFT_EINVAL;
+    std::lock_guard<std::mutex> lk(q->mu);
+    out->submitted = q->n_submitted;
+    out->completed = q->n_completed;
+    out->batches = q->n_batches;
+    out->deferred = q->n_deferred;
+    out->pending = q->pending.size();
+    out->inflight = q->inflight_reqs;
+    out->pool_words = q->pool_words;
+    out->pool_used_max = q->max_pool_used;
+    return q->error;
+}
+
+void tft_queue_destroy(tft_queue* q) {
+    if (!q) return;
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        q->stop = true;
+        q->cv_work.notify_one();
+    }
+    if (q->worker.joinable()) q->worker.join();
+    DeviceGuard guard(q->ctx->device);
+    (void)hipStreamDestroy(q->streams[0]);
+    (void)hipStreamDestroy(q->streams[1]);
+    (void)hipFree(q->pool);
+    delete q;
 }
 
 tft_status tft_timing_enable(tft_ctx* ctx, int on) {

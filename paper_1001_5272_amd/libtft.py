@@ -48,6 +48,13 @@ SIGNATURES = {
     "tft_forward_batch": (_st, [_vp, _vp, _vp, _sz, _vp]),
     "tft_from_signed": (_st, [_vp, _vp, _sz, _vp, _vp]),
     "tft_crt3": (_st, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
+    "tft_queue_create": (_st, [_vp, _sz, _sz, ctypes.POINTER(_vp)]),
+    "tft_queue_submit": (_st, [_vp, _vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "tft_queue_poll": (_st, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
+    "tft_queue_wait": (_st, [_vp, ctypes.c_uint64]),
+    "tft_queue_completion_ns": (_st, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+    "tft_queue_stats": (_st, [_vp, _vp]),
+    "tft_queue_destroy": (None, [_vp]),
     "tft_timing_enable": (_st, [_vp, ctypes.c_int]),
     "tft_timing_read": (_st, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
     "tft_timing_reset": (_st, [_vp]),
@@ -72,6 +79,11 @@ class MulDesc(ctypes.Structure):
 class BatchDesc(ctypes.Structure):
     _fields_ = [("count", _sz), ("single_workgroup", _sz), ("two_pass", _sz), ("device_bytes", _sz),
                 ("launches", ctypes.c_uint)]
+
+
+class QueueDesc(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "batches", "deferred", "pending",
+                                                 "inflight", "pool_words", "pool_used_max")]
 
 
 class PlanDesc(ctypes.Structure):
@@ -326,3 +338,77 @@ def tft_crt3(ctxs, r1, r2, r3, out, stream=None):
     _check(load().tft_crt3(hs, ctxs[0]._t(r1, "r1"), ctxs[1]._t(r2, "r2"), ctxs[2]._t(r3, "r3"), n,
                            _vp(out.data_ptr()), _stream(stream)), "tft_crt3")
     return out
+
+
+class Queue:
+    """Serving queue with continuous batching (tft_queue_*)."""
+
+    def __init__(self, ctx: Context, pool_words: int, max_inflight: int = 4096):
+        self.ctx = ctx
+        h = _vp()
+        _check(load().tft_queue_create(ctx.handle, pool_words, max_inflight, ctypes.byref(h)), "tft_queue_create")
+        self.handle = h
+
+    def submit(self, A, B, X) -> int:
+        d = MulDesc(self.ctx._t(A, "A").value, A.numel(), self.ctx._t(B, "B").value, B.numel(),
+                    self.ctx._t(X, "X").value, None)
+        t = ctypes.c_uint64()
+        _check(load().tft_queue_submit(self.handle, ctypes.byref(d), ctypes.byref(t)), "tft_queue_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int()
+        _check(load().tft_queue_poll(self.handle, ticket, ctypes.byref(done)), "tft_queue_poll")
+        return bool(done.value)
+
+    def wait(self, ticket: int):
+        _check(load().tft_queue_wait(self.handle, ticket), "tft_queue_wait")
+
+    def completion_ns(self, ticket: int) -> int:
+        ns = ctypes.c_uint64()
+        _check(load().tft_queue_completion_ns(self.handle, ticket, ctypes.byref(ns)), "tft_queue_completion_ns")
+        return int(ns.value)
+
+    def stats(self) -> dict:
+        d = QueueDesc()
+        _check(load().tft_queue_stats(self.handle, ctypes.byref(d)), "tft_queue_stats")
+        return {f: int(getattr(d, f)) for f, _ in QueueDesc._fields_}
+
+    def close(self):
+        if self.handle:
+            load().tft_queue_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tft_queue_create(ctx: Context, pool_words: int, max_inflight: int = 4096) -> Queue:
+    return Queue(ctx, pool_words, max_inflight)
+
+
+def tft_queue_submit(q: Queue, A, B, X) -> int:
+    return q.submit(A, B, X)
+
+
+def tft_queue_poll(q: Queue, ticket: int) -> bool:
+    return q.poll(ticket)
+
+
+def tft_queue_wait(q: Queue, ticket: int):
+    q.wait(ticket)
+
+
+def tft_queue_completion_ns(q: Queue, ticket: int) -> int:
+    return q.completion_ns(ticket)
+
+
+def tft_queue_stats(q: Queue) -> dict:
+    return q.stats()
+
+
+def tft_queue_destroy(q: Queue):
+    q.close()
