@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="only the timed step, roofline and baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the served Poisson stream")
+    ap.add_argument("--plain-seconds", type=float, default=1.0, help="length of the plain FIFO comparison")
+    ap.add_argument("--skip", default="", help="comma list of extras to skip: batched,served,crt,sweep")
     return ap.parse_args()
 
 
@@ -173,7 +176,16 @@ def main():
     }
 
     if not args.no_extras:
+        skip = set(x for x in args.skip.split(",") if x)
         result.update(extras(ctx, bufs, host, p))
+        if "sweep" not in skip:
+            result["sweep"] = length_sweep(ctx, p)
+        if "batched" not in skip:
+            result["batched"] = batched_c3()
+        if "served" not in skip:
+            result["served"] = served_c4(ctx, args.serve_seconds, args.plain_seconds)
+        if "crt" not in skip:
+            result["crt"] = crt_c5()
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(p, g, host)
@@ -261,6 +273,251 @@ def extras(ctx, bufs, host, p):
                        "tft_itft_roundtrip_us": round(rt * 1e3, 1)}
     c1.close()
     return out
+
+
+def length_sweep(ctx, p, per_octave=8):
+    """TFT+ITFT time at lengths spread through [2^21, 2^23] (the jump-free
+    curve) next to the padded comparator."""
+    import torch
+
+    import synth
+    from paper_1001_5272_amd import libtft
+    print("[bench] length sweep", file=sys.stderr, flush=True)
+    ns = sorted({int(round(2 ** (21 + i / per_octave))) for i in range(2 * per_octave + 1)} |
+                {(1 << 22) - 1, (1 << 22) + 1, (1 << 21) + 1})
+    pad = torch.empty(1 << 23, dtype=torch.uint64, device="cuda")
+    out = []
+    for n in ns:
+        X = torch.from_numpy(synth.residues(p, n, 7000 + n % 9973)).cuda()
+        t = event_time(lambda: (libtft.tft_forward(ctx, X), libtft.tft_inverse(ctx, X)), 5)
+        tp = event_time(lambda: (libtft.tft_padded_forward(ctx, X, pad), libtft.tft_padded_inverse(ctx, X, pad)), 5)
+        out.append({"n": n, "tft_itft_us": round(t * 1e3, 1), "padded_us": round(tp * 1e3, 1),
+                    "gbfly_s": round(2 * nominal_butterflies(n) / (t * 1e-3) / 1e9, 1)})
+        del X
+    return out
+
+
+def batched_c3():
+    """4096 independent products mod 998244353, operand lengths log-uniform in
+    [32, 32768]: one planned batch replayed as a HIP graph, against one plain
+    poly_mul launch sequence per instance on the same stream."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1001_5272_amd import libtft
+    print("[bench] batched 4096 products (998244353)", file=sys.stderr, flush=True)
+    p, g = synth.P998
+    ctx = libtft.Context(p, g, 0)
+    count = 4096
+    la = synth.log_uniform_lengths(32, 32768, count, 3001)
+    lb = synth.log_uniform_lengths(32, 32768, count, 3002)
+    total = int((la + lb - 1).sum())
+    # operands resident in HBM: one flat buffer per role, sliced per instance
+    Aall = torch.from_numpy(synth.residues_u32(p, int(la.sum()), 3003)).cuda()
+    Ball = torch.from_numpy(synth.residues_u32(p, int(lb.sum()), 3004)).cuda()
+    Xall = torch.zeros(total, dtype=torch.uint32, device="cuda")
+    Yall = torch.zeros(total, dtype=torch.uint32, device="cuda")
+    X2all = torch.zeros(total, dtype=torch.uint32, device="cuda")
+    jobs, plain = [], []
+    oa = ob = ox = 0
+    for i in range(count):
+        a, b = int(la[i]), int(lb[i])
+        r = a + b - 1
+        A, B = Aall[oa:oa + a], Ball[ob:ob + b]
+        jobs.append((A, B, Xall[ox:ox + r], Yall[ox:ox + r]))
+        plain.append((A, B, X2all[ox:ox + r], Yall[ox:ox + r]))
+        oa, ob, ox = oa + a, ob + b, ox + r
+    t0 = time.perf_counter()
+    batch = libtft.Batch(ctx, jobs)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = batch.info()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.run()
+    graph.replay()
+    torch.cuda.synchronize()
+    reps = 10
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        graph.replay()
+    ev1.record()
+    ev1.synchronize()
+    t_graph = ev0.elapsed_time(ev1) / reps
+    ev0.record()
+    for _ in range(3):
+        batch.run()
+    ev1.record()
+    ev1.synchronize()
+    t_run = ev0.elapsed_time(ev1) / 3
+
+    def run_plain():
+        for A, B, X, Y in plain:
+            libtft.poly_mul(ctx, A, B, X, Y)
+    run_plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) * 1e3
+    same = bool(torch.equal(Xall, X2all))
+    batch.close()
+    ctx.close()
+    return {"workload": "4096 products mod 998244353, la, lb log-uniform [32, 32768] (seeds 3001, 3002)",
+            "total_output_words": total, "batch": info, "plan_ms": round(plan_ms, 1),
+            "graph_ms": round(t_graph, 3), "run_ms": round(t_run, 3), "plain_ms": round(t_plain, 3),
+            "mults_per_s_graph": round(count / (t_graph * 1e-3), 0), "mults_per_s_plain": round(count / (t_plain * 1e-3), 0),
+            "speedup_vs_plain": round(t_plain / t_graph, 2), "batched_equals_plain": same}
+
+
+def served_c4(ctx, seconds, plain_seconds):
+    """Poisson stream (mean 20k requests/s) of products mod 2^64-2^32+1 with
+    product length r log-uniform in [2^8, 2^22]; operands resident in HBM; the
+    queue admits by in-place footprint.  Latency runs from the scheduled
+    arrival to the completion seen by the queue's worker.  The plain path
+    serves the same stream one request at a time (FIFO, poly_mul + wait)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1001_5272_amd import libtft
+    print(f"[bench] served stream {seconds} s", file=sys.stderr, flush=True)
+    p = synth.GOLDILOCKS[0]
+    K, SLOTS = 256, 4
+    rs = synth.log_uniform_lengths(1 << 8, 1 << 22, K, 4001)
+    pairs = []
+    for i, r in enumerate(rs.tolist()):
+        la = (r + 2) // 2
+        lb = r + 1 - la
+        A = torch.from_numpy(synth.residues(p, la, 4100 + 2 * i)).cuda()
+        B = torch.from_numpy(synth.residues(p, lb, 4101 + 2 * i)).cuda()
+        Xs = [torch.empty(r, dtype=torch.uint64, device="cuda") for _ in range(SLOTS)]
+        pairs.append((A, B, Xs))
+    arrivals = synth.poisson_arrivals(20000.0, seconds, 4002)
+    q = libtft.Queue(ctx, 1 << 27, 4096)
+    last = {}
+    tickets = []
+    torch.cuda.synchronize()
+    base = time.monotonic_ns() + 20_000_000
+    blocked = 0
+    for i, ta in enumerate(arrivals.tolist()):
+        k = i % K
+        slot = (i // K) % SLOTS
+        prev = last.get((k, slot))
+        if prev is not None and not q.poll(prev):
+            blocked += 1
+            q.wait(prev)
+        t_arr = base + int(ta * 1e9)
+        while time.monotonic_ns() < t_arr:
+            pass
+        A, B, Xs = pairs[k]
+        t = q.submit(A, B, Xs[slot])
+        last[(k, slot)] = t
+        tickets.append((t, t_arr, int(rs[k])))
+    for t, _, _ in tickets:
+        q.wait(t)
+    end = max(q.completion_ns(t) for t, _, _ in tickets)
+    lat = np.array([(q.completion_ns(t) - ta) / 1e3 for t, ta, _ in tickets])
+    st = q.stats()
+    q.close()
+    served = {"requests": len(tickets), "duration_s": round((end - base) / 1e9, 3),
+              "mults_per_s": round(len(tickets) / ((end - base) / 1e9), 1),
+              "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+              "mean_r": int(np.mean([r for _, _, r in tickets])), "batches": st["batches"],
+              "deferred": st["deferred"], "pool_words": st["pool_words"], "pool_used_max": st["pool_used_max"],
+              "submitter_waits": blocked}
+    # plain FIFO path on a prefix of the same stream
+    print(f"[bench] plain FIFO stream {plain_seconds} s", file=sys.stderr, flush=True)
+    sub = arrivals[arrivals < plain_seconds]
+    Y = torch.empty(1 << 22, dtype=torch.uint64, device="cuda")
+    torch.cuda.synchronize()
+    base = time.monotonic_ns() + 20_000_000
+    lat_p = []
+    for i, ta in enumerate(sub.tolist()):
+        k = i % K
+        A, B, Xs = pairs[k]
+        t_arr = base + int(ta * 1e9)
+        while time.monotonic_ns() < t_arr:
+            pass
+        libtft.poly_mul(ctx, A, B, Xs[0], Y[:Xs[0].numel()])
+        torch.cuda.synchronize()
+        lat_p.append((time.monotonic_ns() - t_arr) / 1e3)
+    end_p = time.monotonic_ns()
+    lat_p = np.array(lat_p)
+    plain = {"requests": len(sub), "duration_s": round((end_p - base) / 1e9, 3),
+             "mults_per_s": round(len(sub) / ((end_p - base) / 1e9), 1),
+             "p50_us": round(float(np.percentile(lat_p, 50)), 1), "p99_us": round(float(np.percentile(lat_p, 99)), 1)}
+    return {"workload": f"Poisson 20k req/s for {seconds} s, p=2^64-2^32+1, r log-uniform [2^8, 2^22] "
+                        f"({K} operand pairs reused round-robin)", "served": served, "plain_fifo": plain}
+
+
+def crt_c5():
+    """Exact product of two length-(2^24+12345) polynomials with signed 24-bit
+    coefficients through the primes 2013265921, 469762049, 1811939329 and CRT
+    to int128; timed per prime and for the CRT, with sampled exact checks."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_1001_5272_amd import libtft
+    print("[bench] exact integer product via 3 primes", file=sys.stderr, flush=True)
+    n = (1 << 24) + 12345
+    r = 2 * n - 1
+    a = synth.signed24(n, 5001)
+    b = synth.signed24(n, 5002)
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    ctxs = [libtft.Context(pp, gg) for pp, gg in synth.CRT_PRIMES]
+    A = torch.empty(n, dtype=torch.uint32, device="cuda")
+    B = torch.empty(n, dtype=torch.uint32, device="cuda")
+    Y = torch.empty(r, dtype=torch.uint32, device="cuda")
+    Xs = [torch.empty(r, dtype=torch.uint32, device="cuda") for _ in range(3)]
+    out = torch.empty(2 * r, dtype=torch.int64, device="cuda")
+
+    def run():
+        per = []
+        for c, X in zip(ctxs, Xs):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            libtft.tft_from_signed(c, da, A)
+            libtft.tft_from_signed(c, db, B)
+            libtft.poly_mul(c, A, B, X, Y)
+            e1.record()
+            per.append((e0, e1))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        libtft.tft_crt3(ctxs, Xs[0], Xs[1], Xs[2], out)
+        e1.record()
+        e1.synchronize()
+        return [s.elapsed_time(e) for s, e in per], e0.elapsed_time(e1)
+
+    run()
+    per, tcrt = run()
+    got = out.cpu().numpy().view(np.uint64)
+    checks = 0
+    for s in [0, 1, r // 3, r // 2, r - 2, r - 1]:
+        v = (int(got[2 * s + 1]) << 64) | int(got[2 * s])
+        if v >= 1 << 127:
+            v -= 1 << 128
+        assert v == oracle.conv_coeff_i128(a, b, s), s
+        checks += 1
+    for c in ctxs:
+        c.close()
+    total = sum(per) + tcrt
+    N = 1 << (r - 1).bit_length()
+    return {"workload": "signed 24-bit, both lengths 2^24+12345, primes 2013265921, 469762049, 1811939329 "
+                        "(1811939329 replaces 998244353, whose 2-adic order 23 is too small for r > 2^23)",
+            "r": r, "per_prime_ms": [round(x, 3) for x in per], "crt_ms": round(tcrt, 3), "total_ms": round(total, 3),
+            "coeffs_per_s": round(r / (total * 1e-3), 0),
+            "inplace_bytes_per_prime": 4 * (2 * n + 2 * r), "padded_bytes_per_prime": 4 * (2 * n + 2 * N),
+            "sampled_exact_checks": checks}
 
 
 def cpu_baseline(p, g, host):

@@ -1,0 +1,139 @@
+"""Parity at the benchmark's full sizes and launch configurations.
+
+- Goldilocks TFT at every length of the sweep: the whole output against the
+  oracle's padded FFT; the inverse restores the input.
+- Products at r = n: sampled exact coefficients and the evaluation identity
+  C(z) = A(z) B(z) at random points (a wrong coefficient survives one point
+  with probability at most r/p).
+- The 4096-product batch: a sample of instances against the oracle.
+- The three-prime exact product at length 2^24+12345: sampled exact int128
+  coefficients and C(z) = A(z) B(z) modulo 2^61-1.
+"""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+libtft = pytest.importorskip("paper_1001_5272_amd.libtft")
+torch = pytest.importorskip("torch")
+
+SWEEP = [1 << 22, (1 << 22) + 1, 3 << 21, (1 << 23) - 1, 1 << 23]
+
+
+@pytest.fixture(scope="module")
+def ctxgl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = libtft.Context(*synth.GOLDILOCKS)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("n", SWEEP)
+def test_sweep_lengths_full_output(ctxgl, n):
+    p, g = synth.GOLDILOCKS
+    print(f"[gpu] full-size TFT n={n} plan={libtft.tft_plan_info(ctxgl, n)}", flush=True)
+    F = synth.residues(p, n, 2000 + SWEEP.index(n))
+    X = torch.from_numpy(F).cuda()
+    libtft.tft_forward(ctxgl, X)
+    got = X.cpu().numpy()
+    ref = oracle.fft_padded(p, g, F)
+    bad = np.nonzero(got != ref)[0]
+    assert len(bad) == 0, f"{len(bad)} mismatches, first {bad[:5]}"
+    idx = [0, 1, n // 2, n - 1] + [random.Random(n).randrange(n) for _ in range(4)]
+    assert (oracle.tft_sample(p, g, F, idx) == got[idx]).all()
+    libtft.tft_inverse(ctxgl, X)
+    assert (X.cpu().numpy() == F).all()
+
+
+@pytest.mark.parametrize("r", [(1 << 22) + 1, (1 << 23) - 1])
+def test_products_at_full_size(ctxgl, r):
+    p, g = synth.GOLDILOCKS
+    la = (r + 2) // 2
+    lb = r + 1 - la
+    A = synth.residues(p, la, 3000 + r)
+    B = synth.residues(p, lb, 4000 + r)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    X = torch.empty(r, dtype=torch.uint64, device="cuda")
+    Y = torch.empty(r, dtype=torch.uint64, device="cuda")
+    libtft.poly_mul(ctxgl, dA, dB, X, Y)
+    C = X.cpu().numpy()
+    rng = random.Random(r)
+    for s in [0, 1, r // 2, r - 2, r - 1] + [rng.randrange(r) for _ in range(3)]:
+        assert int(C[s]) == oracle.mul_coeff(p, A, B, s), s
+    for _ in range(2):
+        z = rng.randrange(p)
+        assert oracle.evaluate(p, C, z) == oracle.evaluate(p, A, z) * oracle.evaluate(p, B, z) % p
+
+
+def test_batch_4096_sampled():
+    p, g = synth.P998
+    ctx = libtft.Context(p, g)
+    count = 4096
+    la = synth.log_uniform_lengths(32, 32768, count, 3001)
+    lb = synth.log_uniform_lengths(32, 32768, count, 3002)
+    jobs, host = [], []
+    for i in range(count):
+        A = synth.residues_u32(p, int(la[i]), 10_000 + 2 * i)
+        B = synth.residues_u32(p, int(lb[i]), 10_001 + 2 * i)
+        r = len(A) + len(B) - 1
+        jobs.append((torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
+                     torch.empty(r, dtype=torch.uint32, device="cuda"), torch.empty(r, dtype=torch.uint32, device="cuda")))
+        host.append((A, B))
+    b = libtft.Batch(ctx, jobs)
+    b.run()
+    torch.cuda.synchronize()
+    rng = random.Random(5)
+    sample = sorted(set([0, count - 1] + [rng.randrange(count) for _ in range(40)]))
+    big = max(range(count), key=lambda i: len(host[i][0]) + len(host[i][1]))
+    for i in sample + [big]:
+        A, B = host[i]
+        got = jobs[i][2].cpu().numpy().astype(np.uint64)
+        assert (got == oracle.mul_padded(p, g, A, B)).all(), i
+    b.close()
+    ctx.close()
+
+
+def test_exact_product_full_size():
+    P61 = (1 << 61) - 1
+    n = (1 << 24) + 12345
+    r = 2 * n - 1
+    a = synth.signed24(n, 5001)
+    b = synth.signed24(n, 5002)
+    ctxs = [libtft.Context(pp, gg) for pp, gg in synth.CRT_PRIMES]
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    res = []
+    for c in ctxs:
+        A = torch.empty(n, dtype=torch.uint32, device="cuda")
+        B = torch.empty(n, dtype=torch.uint32, device="cuda")
+        libtft.tft_from_signed(c, da, A)
+        libtft.tft_from_signed(c, db, B)
+        X = torch.empty(r, dtype=torch.uint32, device="cuda")
+        Y = torch.empty(r, dtype=torch.uint32, device="cuda")
+        libtft.poly_mul(c, A, B, X, Y)
+        res.append(X)
+        del A, B, Y
+    out = torch.empty(2 * r, dtype=torch.int64, device="cuda")
+    libtft.tft_crt3(ctxs, res[0], res[1], res[2], out)
+    o = out.cpu().numpy()
+    lo, hi = o[0::2].view(np.uint64), o[1::2]
+    for s in [0, 1, r // 2, r - 1, 12345, r - 7]:
+        v = (int(hi[s]) << 64) | int(lo[s])
+        if v >= 1 << 127:
+            v -= 1 << 128
+        assert v == oracle.conv_coeff_i128(a, b, s), s
+    # C(z) = A(z) B(z) mod 2^61 - 1, with C reduced from int128: 2^64 = 8 mod P61
+    M61 = np.uint64(P61)
+    lo_r = (lo >> np.uint64(61)) + (lo & M61)
+    hi_r = (hi % P61).astype(np.uint64)           # floor mod of the signed high word
+    Cr = (lo_r % M61 + (hi_r * np.uint64(8)) % M61) % M61
+    ar = (a % P61).astype(np.uint64)
+    br = (b % P61).astype(np.uint64)
+    for z in [123456789, 987654321987]:
+        assert oracle.evaluate(P61, Cr, z) == oracle.evaluate(P61, ar, z) * oracle.evaluate(P61, br, z) % P61
+    for c in ctxs:
+        c.close()
