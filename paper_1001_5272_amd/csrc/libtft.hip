@@ -29,7 +29,7 @@ namespace {
 constexpr uint64_t kGoldilocks = 0xFFFFFFFF00000001ull;
 constexpr unsigned kMaxLog2 = 28;               // longest transform supported by the tables
 constexpr size_t kScratchWords = size_t(1) << 16;   // V_c area: one word per column, W <= 2^16
-constexpr size_t kLdsSoft = 64 * 1024;          // preferred LDS per workgroup
+constexpr size_t kLdsSoft = 76 * 1024;          // preferred LDS per workgroup (two per CU)
 constexpr size_t kLdsHard = 160 * 1024;         // gfx950 LDS per workgroup
 constexpr size_t kLdsDynMax = 144 * 1024;       // dynamic LDS any launch may request
 
@@ -68,6 +68,7 @@ struct Plan {
     unsigned logW;
     uint64_t W, a, b;
     uint32_t Lout, M;    // column outputs and column LDS block (kind 1); LDS block (kind 0)
+    uint32_t split;      // kind 1: Lout = M + 1, the column block holds M words (see col_fwd_body)
     int logC;
     size_t lds_col, lds_row;
 };
@@ -150,7 +151,7 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
     if (log2u(n) <= small_max_log2(w) && !(ctx->override_logW && (1ull << ctx->override_logW) < n)) {
         P.kind = 0;
         P.M = (uint32_t)pow2ceil(n);
-        P.lds_row = (size_t)P.M * w;
+        P.lds_row = (size_t)P.M * w;                 // data; the kernels add M words of twiddles
         return P;
     }
     P.kind = 1;
@@ -162,7 +163,9 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
         P.b = n & (P.W - 1);
         P.Lout = (uint32_t)(P.a + (P.b ? 1 : 0));
         P.M = (uint32_t)pow2ceil(P.Lout);
-        P.lds_col = ((size_t)P.M << P.logC) * w;
+        P.split = (P.M >= 4 && P.Lout == P.M / 2 + 1) ? 1 : 0;
+        if (P.split) P.M /= 2;
+        P.lds_col = (((size_t)P.M << P.logC) + P.M) * w;   // tile + LDS twiddles
         P.lds_row = (size_t)P.W * w;
     };
     const unsigned logC = (unsigned)P.logC;
@@ -244,6 +247,7 @@ tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t
     G.b = (uint32_t)P.b;
     G.Lout = P.Lout;
     G.M = P.M;
+    G.split = P.split;
     return G;
 }
 
@@ -260,7 +264,7 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
         if (src != X) {
             launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3(1), dim3(kThreads), 0, st, X, n, src, n_src);
         }
-        launch(ctx, TFT_K_SMALL_FWD, tft::k_small_fwd<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, X, (uint32_t)n,
+        launch(ctx, TFT_K_SMALL_FWD, tft::k_small_fwd<Mod>, dim3(1), dim3(tft::kSmallThreads), 2 * P.lds_row, st, md, T, X, (uint32_t)n,
                            P.M);
         return launch_status();
     }
@@ -268,10 +272,10 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
     const auto G = two_pass_of<Word>(P, X, src, n_src, nullptr, V);
     const uint32_t tiles = (uint32_t)(P.W >> P.logC);
     if (P.logC == 3)
-        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(kThreads), P.lds_col, st, md, T, G, tiles);
+        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(tft::kColThreads), P.lds_col, st, md, T, G, tiles);
     else
-        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(kThreads), P.lds_col, st, md, T, G, tiles);
-    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(kThreads), P.lds_row,
+        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(tft::kColThreads), P.lds_col, st, md, T, G, tiles);
+    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(tft::kColThreads), P.lds_row,
            st, md, T, G);
     return launch_status();
 }
@@ -287,7 +291,7 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     if (P.kind < 0) return TFT_ERANGE;
     if (P.kind == 0) {
         if (Y) launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3(1), dim3(kThreads), 0, st, md, X, Y, n);
-        launch(ctx, TFT_K_SMALL_INV, tft::k_small_inv<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, X, (uint32_t)n,
+        launch(ctx, TFT_K_SMALL_INV, tft::k_small_inv<Mod>, dim3(1), dim3(tft::kSmallThreads), 2 * P.lds_row, st, md, T, X, (uint32_t)n,
                            P.M);
         return launch_status();
     }
@@ -296,17 +300,17 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     const uint32_t C = 1u << P.logC;
     const uint32_t tiles_all = (uint32_t)(P.W >> P.logC);
     const uint32_t nrows = tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
-    launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows), dim3(kThreads), P.lds_row, st, md, T, G);
+    launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows), dim3(tft::kRowThreads), P.lds_row, st, md, T, G);
     auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
     {   // columns c >= b
         const uint32_t t0 = (uint32_t)(P.b / C);
         const uint32_t nt = tiles_all - t0;
-        launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(kThreads), P.lds_col, st, md, T, G, 0, t0, nt);
+        launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 0, t0, nt);
     }
     if (P.b) {
-        launch(ctx, TFT_K_LAST_INV, tft::k_last_inv<Mod>, dim3(1), dim3(kThreads), P.lds_row, st, md, T, G);
+        launch(ctx, TFT_K_LAST_INV, tft::k_last_inv<Mod>, dim3(1), dim3(tft::kLastThreads), P.lds_row, st, md, T, G);
         const uint32_t nt = (uint32_t)((P.b + C - 1) / C);
-        launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(kThreads), P.lds_col, st, md, T, G, 1, 0u, nt);
+        launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 1, 0u, nt);
     }
     return launch_status();
 }
@@ -327,10 +331,10 @@ tft_status mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const
     const uint64_t r = m + nb - 1;
     const Plan P = make_plan(ctx, r);
     if (P.kind < 0) return TFT_ERANGE;
-    if (P.kind == 0 && 2 * P.lds_row <= kLdsHard - 32 * 1024) {
+    if (P.kind == 0 && 3 * P.lds_row <= kLdsHard - 32 * 1024) {
         const Mod& md = mod_of<Mod>(ctx);
         const auto T = tables_of<typename Mod::Word>(ctx);
-        launch(ctx, TFT_K_SMALL_MUL, tft::k_small_mul<Mod>, dim3(1), dim3(kThreads), 2 * P.lds_row, st, md, T, A, (uint32_t)m,
+        launch(ctx, TFT_K_SMALL_MUL, tft::k_small_mul<Mod>, dim3(1), dim3(tft::kSmallThreads), 3 * P.lds_row, st, md, T, A, (uint32_t)m,
                            B, (uint32_t)nb, X, P.M);
         return launch_status();
     }
@@ -508,7 +512,7 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
         if (log2u(r) > ctx->v) return TFT_ERANGE;
         const Plan P = make_plan(ctx, r);
         if (P.kind < 0) return TFT_ERANGE;
-        const size_t small_lds = (products ? 2 : 1) * (size_t)pow2ceil(r) * w;
+        const size_t small_lds = (products ? 3 : 2) * (size_t)pow2ceil(r) * w;   // data + LDS twiddles
         if (P.kind == 0 && small_lds <= small_lds_cap) {
             tft::SmallJob<Word> J;
             J.A = (const Word*)D.a;
@@ -628,24 +632,24 @@ tft_status batch_run(tft_batch* B, hipStream_t st) {
     const bool c3 = B->logC == 3;
     if (B->n_items[PH_COL_FWD])
         launch(ctx, TFT_K_COL_FWD, c3 ? tft::k_col_fwd_list<Mod, 3> : tft::k_col_fwd_list<Mod, 4>,
-               dim3(B->n_items[PH_COL_FWD]), dim3(kThreads), B->lds_col, st, md, T, recs,
+               dim3(B->n_items[PH_COL_FWD]), dim3(tft::kColThreads), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_FWD]);
     if (B->n_items[PH_ROW_FWD])
-        launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd_list<Mod>, dim3(B->n_items[PH_ROW_FWD]), dim3(kThreads), B->lds_row,
+        launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd_list<Mod>, dim3(B->n_items[PH_ROW_FWD]), dim3(tft::kRowThreads), B->lds_row,
                st, md, T, recs, (const tft::Item*)B->items[PH_ROW_FWD]);
     if (B->n_items[PH_ROW_INV])
-        launch(ctx, TFT_K_ROW_INV, tft::k_row_inv_list<Mod>, dim3(B->n_items[PH_ROW_INV]), dim3(kThreads), B->lds_row,
+        launch(ctx, TFT_K_ROW_INV, tft::k_row_inv_list<Mod>, dim3(B->n_items[PH_ROW_INV]), dim3(tft::kRowThreads), B->lds_row,
                st, md, T, recs, (const tft::Item*)B->items[PH_ROW_INV]);
     if (B->n_items[PH_COL_INV_SHORT])
         launch(ctx, TFT_K_COL_INV_SHORT, c3 ? tft::k_col_inv_list<Mod, 3> : tft::k_col_inv_list<Mod, 4>,
-               dim3(B->n_items[PH_COL_INV_SHORT]), dim3(kThreads), B->lds_col, st, md, T, recs,
+               dim3(B->n_items[PH_COL_INV_SHORT]), dim3(tft::kColThreads), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_INV_SHORT], 0);
     if (B->n_items[PH_LAST_INV])
-        launch(ctx, TFT_K_LAST_INV, tft::k_last_inv_list<Mod>, dim3(B->n_items[PH_LAST_INV]), dim3(kThreads),
+        launch(ctx, TFT_K_LAST_INV, tft::k_last_inv_list<Mod>, dim3(B->n_items[PH_LAST_INV]), dim3(tft::kLastThreads),
                B->lds_row, st, md, T, recs, (const tft::Item*)B->items[PH_LAST_INV]);
     if (B->n_items[PH_COL_INV_LONG])
         launch(ctx, TFT_K_COL_INV_LONG, c3 ? tft::k_col_inv_list<Mod, 3> : tft::k_col_inv_list<Mod, 4>,
-               dim3(B->n_items[PH_COL_INV_LONG]), dim3(kThreads), B->lds_col, st, md, T, recs,
+               dim3(B->n_items[PH_COL_INV_LONG]), dim3(tft::kColThreads), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_INV_LONG], 1);
     if (both) {
         if (hipEventRecord(B->join, B->side) != hipSuccess || hipStreamWaitEvent(st, B->join, 0) != hipSuccess)

@@ -34,6 +34,11 @@ struct Tables {
     const Word* f2;
     const Word* i1;
     const Word* i2;
+    // optional LDS copy of the small-index twiddles: lf[i] = w_{2i},
+    // li[i] = w_{2i}^-1 for i < nl (every twiddle of a block at global index 0)
+    const Word* lf = nullptr;
+    const Word* li = nullptr;
+    uint32_t nl = 0;
 };
 
 // ---------------------------------------------------------- 31-bit primes
@@ -70,6 +75,7 @@ struct ModU32 {
     // plain product of two residues
     __device__ __forceinline__ Word mul(Word a, Word b) const { return mont(mont(a, b), r2); }
     __device__ __forceinline__ Word half(Word x) const { return (x >> 1) + ((x & 1u) ? halfp1 : 0u); }
+    __device__ __forceinline__ Word one_tw() const { return mont(1u, r2); }   // 1 in twiddle (Montgomery) form
 };
 
 // ------------------------------------------------- p = 2^64 - 2^32 + 1
@@ -105,11 +111,13 @@ struct ModGL {
     __device__ __forceinline__ Word mul_tw(Word a, Word tw) const { return mul(a, tw); }
     __device__ __forceinline__ Word tw_mul_tw(Word t1, Word t2) const { return mul(t1, t2); }
     __device__ __forceinline__ Word half(Word x) const { return (x >> 1) + ((x & 1ull) ? HALF : 0ull); }
+    __device__ __forceinline__ Word one_tw() const { return 1ull; }
 };
 
 template <class Mod>
 __device__ __forceinline__ typename Mod::Word tw_fwd(const Mod& md, const Tables<typename Mod::Word>& T,
                                                       uint64_t s) {
+    if ((s >> 1) < T.nl && !(s & 1)) return T.lf[s >> 1];
     typename Mod::Word t = T.f1[s & kMask1];
     const uint64_t h = s >> kB1;
     if (h) t = md.tw_mul_tw(t, T.f2[h]);
@@ -119,10 +127,40 @@ __device__ __forceinline__ typename Mod::Word tw_fwd(const Mod& md, const Tables
 template <class Mod>
 __device__ __forceinline__ typename Mod::Word tw_inv(const Mod& md, const Tables<typename Mod::Word>& T,
                                                       uint64_t s) {
+    if ((s >> 1) < T.nl && !(s & 1)) return T.li[s >> 1];
     typename Mod::Word t = T.i1[s & kMask1];
     const uint64_t h = s >> kB1;
     if (h) t = md.tw_mul_tw(t, T.i2[h]);
     return t;
+}
+
+// Copy w_{2i} and w_{2i}^-1 (i < nl, 2 nl <= 2^B1) into LDS at dst (2 nl
+// words) and return tables that read them from there.  One coalesced pass
+// replaces a dependent global load at the start of every stage group.
+template <class Word>
+__device__ Tables<Word> local_tables(const Tables<Word>& T, Word* dst, uint32_t nl) {
+    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
+        dst[i] = T.f1[2 * i];
+        dst[nl + i] = T.i1[2 * i];
+    }
+    __syncthreads();
+    Tables<Word> L = T;
+    L.lf = dst;
+    L.li = dst + nl;
+    L.nl = nl;
+    return L;
+}
+
+// z^e for z in twiddle form (square and multiply).
+template <class Mod>
+__device__ __forceinline__ typename Mod::Word pow_tw(const Mod& md, typename Mod::Word z, uint32_t e) {
+    typename Mod::Word r = md.one_tw();
+    while (e) {
+        if (e & 1u) r = md.tw_mul_tw(r, z);
+        z = md.tw_mul_tw(z, z);
+        e >>= 1;
+    }
+    return r;
 }
 
 // ------------------------------------------------------- register units
@@ -230,6 +268,33 @@ __device__ __forceinline__ void dif_group(const Mod& md, const Tables<typename M
     __syncthreads();
 }
 
+// Evaluation at one point for every lane of a tile: res[c] = sum_{d < len}
+// buf[d C + c] z^d (z in twiddle form).  The blockDim / C threads of a lane
+// each run Horner over one chunk of d, scale by z^(chunk start) and the chunk
+// values are summed.  red is LDS scratch of blockDim words, res of C words.
+template <class Mod>
+__device__ void eval_lanes(const Mod& md, const typename Mod::Word* buf, int logC, uint32_t len, typename Mod::Word z,
+                           typename Mod::Word* red, typename Mod::Word* res) {
+    using Word = typename Mod::Word;
+    const uint32_t C = 1u << logC;
+    const uint32_t tpc = blockDim.x >> logC;
+    const uint32_t c = threadIdx.x & (C - 1), t = threadIdx.x >> logC;
+    const uint32_t chunk = (len + tpc - 1) / tpc;
+    const uint32_t lo = t * chunk;
+    const uint32_t hi = lo + chunk < len ? lo + chunk : len;
+    Word acc = 0;
+    for (uint32_t d = hi; d > lo; d--) acc = md.add(md.mul_tw(acc, z), buf[(d - 1) * C + c]);
+    if (lo > 0 && lo < hi) acc = md.mul_tw(acc, pow_tw(md, z, lo));
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        Word sum = 0;
+        for (uint32_t k = 0; k < tpc; k++) sum = md.add(sum, red[(k << logC) + threadIdx.x]);
+        res[threadIdx.x] = sum;
+    }
+    __syncthreads();
+}
+
 // Forward transform of the block of size M at global index g0 (the block is
 // F mod (x^M - w_{g0})); only blocks meeting [out_lo, out_hi) are computed, so
 // positions outside that range end with unspecified values.
@@ -316,6 +381,8 @@ __device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T,
 // The full inverses act on disjoint dyadic pieces of [0, m) and read only
 // known values, so a caller may run them beforehand (in parallel, elsewhere)
 // and pass skip_full = true.
+constexpr int kMaxLevels = 24;   // log2 of the largest LDS block, with room
+
 // Level d of gitft's descent along the truncation boundary: offset and half
 // size of the block met there, its global index, and whether the walk went to
 // the right child.  Recomputed on demand so that no per-level array is kept.
@@ -348,12 +415,32 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
     using Word = typename Mod::Word;
     const uint32_t C = 1u << logC;
     const uint32_t m0 = m;
+    // The walk visits at most log2 M levels; fetch each level's forward and
+    // inverse twiddle once, in parallel, instead of one dependent global load
+    // per level.
+    __shared__ Word lv_w[kMaxLevels], lv_wi[kMaxLevels];
+    int nlev = 0;
+    {
+        uint32_t mm = m, sz = M;
+        while (sz > 1 && mm > 0 && mm < sz) {
+            const uint32_t h = sz >> 1;
+            if (mm >= h) mm -= h;
+            sz = h;
+            nlev++;
+        }
+    }
+    if (threadIdx.x < (uint32_t)nlev) {
+        const Level L = gitft_level(M, m0, g0, (int)threadIdx.x);
+        lv_w[threadIdx.x] = tw_fwd(md, T, 2 * L.g);
+        lv_wi[threadIdx.x] = tw_inv(md, T, 2 * L.g);
+    }
+    __syncthreads();
     int depth = 0;
     uint32_t off = 0, size = M;
     uint64_t g = g0;
     while (size > 1 && m > 0 && m < size) {
         const uint32_t h = size >> 1;
-        const Word w = tw_fwd(md, T, 2 * g);
+        const Word w = lv_w[depth];
         if (m >= h) {
             if (!skip_full) full_inverse(md, T, buf, logC, off, h, 2 * g);
             // right child's known coefficients: C1_j = C0_j - 2 w hi_j, j in [m - h, h)
@@ -393,7 +480,7 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
         const uint32_t o = L.off, h = L.h;
         const uint32_t items = h * C;
         if (L.right) {
-            const Word wi = tw_inv(md, T, 2 * L.g);
+            const Word wi = lv_wi[d];
             for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
                 const uint32_t c = it & (C - 1);
                 const uint32_t j = it >> logC;
@@ -403,7 +490,7 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
                 buf[(o + h + j) * C + c] = md.mul_tw(md.half(md.sub(x, y)), wi);
             }
         } else {
-            const Word w = tw_fwd(md, T, 2 * L.g);
+            const Word w = lv_w[d];
             for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
                 const uint32_t c = it & (C - 1);
                 const uint32_t j = it >> logC;

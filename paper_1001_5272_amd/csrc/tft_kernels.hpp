@@ -32,7 +32,9 @@
 
 namespace tft {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;        // elementwise kernels and the persistent batch kernel
+constexpr int kColThreads = 512;     // column passes: 8 waves per workgroup (measured best)
+constexpr int kRowThreads = 1024;    // row passes: 16 waves per workgroup (measured best)
 
 template <class Word>
 __device__ __forceinline__ Word* lds_buf() {
@@ -49,64 +51,70 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t x, uint32_t tiles) {
 
 // ------------------------------------------------------ single workgroup
 template <class Mod>
-__device__ void small_forward_body(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* X,
+__device__ void small_forward_body(const Mod& md, const Tables<typename Mod::Word>& T0, typename Mod::Word* X,
                                    uint32_t n, uint32_t M) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
+    const Tables<Word> L = local_tables(T0, buf + M, M / 2);
     for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) buf[i] = i < n ? X[i] : Word(0);
     __syncthreads();
-    dif_forward(md, T, buf, 0, M, 0, n, 0);
+    dif_forward(md, L, buf, 0, M, 0, n, 0);
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) X[i] = buf[i];
 }
 
 template <class Mod>
-__device__ void small_inverse_body(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* X,
+__device__ void small_inverse_body(const Mod& md, const Tables<typename Mod::Word>& T0, typename Mod::Word* X,
                                    uint32_t n, uint32_t M) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
+    const Tables<Word> L = local_tables(T0, buf + M, M / 2);
     for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) buf[i] = i < n ? X[i] : Word(0);
     __syncthreads();
-    gitft(md, T, buf, 0, M, n, 0);
+    gitft(md, L, buf, 0, M, n, 0);
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) X[i] = buf[i];
 }
 
 // Whole product in one workgroup: both operands zero-extended to M words of
 // LDS, forward transforms truncated to r outputs, pointwise product, inverse.
 template <class Mod>
-__device__ void small_mul_body(const Mod& md, const Tables<typename Mod::Word>& T, const typename Mod::Word* A,
+__device__ void small_mul_body(const Mod& md, const Tables<typename Mod::Word>& T0, const typename Mod::Word* A,
                                uint32_t m, const typename Mod::Word* B, uint32_t nb, typename Mod::Word* X,
                                uint32_t M) {
     using Word = typename Mod::Word;
     Word* ba = lds_buf<Word>();
     Word* bb = ba + M;
+    const Tables<Word> L = local_tables(T0, ba + 2 * M, M / 2);
     const uint32_t r = m + nb - 1;
     for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
         ba[i] = i < m ? A[i] : Word(0);
         bb[i] = i < nb ? B[i] : Word(0);
     }
     __syncthreads();
-    dif_forward(md, T, ba, 0, M, 0, r, 0);
-    dif_forward(md, T, bb, 0, M, 0, r, 0);
+    dif_forward(md, L, ba, 0, M, 0, r, 0);
+    dif_forward(md, L, bb, 0, M, 0, r, 0);
     for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) ba[i] = i < r ? md.mul(ba[i], bb[i]) : Word(0);
     __syncthreads();
-    gitft(md, T, ba, 0, M, r, 0);
+    gitft(md, L, ba, 0, M, r, 0);
     for (uint32_t i = threadIdx.x; i < r; i += blockDim.x) X[i] = ba[i];
 }
 
+// Single-instance single-workgroup kernels are latency-bound: run 16 waves.
+constexpr int kSmallThreads = 1024;
+
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_small_fwd(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kSmallThreads) void k_small_fwd(Mod md, Tables<typename Mod::Word> T,
                                                         typename Mod::Word* X, uint32_t n, uint32_t M) {
     small_forward_body(md, T, X, n, M);
 }
 
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_small_inv(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kSmallThreads) void k_small_inv(Mod md, Tables<typename Mod::Word> T,
                                                         typename Mod::Word* X, uint32_t n, uint32_t M) {
     small_inverse_body(md, T, X, n, M);
 }
 
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_small_mul(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kSmallThreads) void k_small_mul(Mod md, Tables<typename Mod::Word> T,
                                                         const typename Mod::Word* A, uint32_t m,
                                                         const typename Mod::Word* B, uint32_t nb,
                                                         typename Mod::Word* X, uint32_t M) {
@@ -127,20 +135,59 @@ struct TwoPass {
     Word* V;
     uint64_t n_src, n;
     uint32_t logW, a, b, Lout, M;
+    uint32_t split;   // 1: Lout = M + 1 with M a power of two (see col_fwd_body)
 };
+
+constexpr int kMaxC = 16;   // widest column tile
 
 // Forward column pass over the tile of C columns starting at column tile*C:
 // evaluates each column polynomial at w_0..w_{Lout-1} (Lout = a + (b > 0)) in
 // an LDS block of M = 2^ceil(lg Lout) words per column, writes the outputs
 // that have a slot and the extra value P_c(w_a) of columns c >= b to V[c].
 template <class Mod, int LOGC>
-__device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T,
+__device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0,
                              const TwoPass<typename Mod::Word>& P, uint32_t tile) {
     using Word = typename Mod::Word;
     constexpr uint32_t C = 1u << LOGC;
+    __shared__ Word red[kColThreads];
+    __shared__ Word extra[kMaxC], hi0[kMaxC];
     Word* buf = lds_buf<Word>();
+    const Tables<Word> T = local_tables(T0, buf + (P.M << LOGC), P.M / 2);
     const uint32_t c0 = tile * C;
     const uint64_t W = 1ull << P.logW;
+    if (P.split) {
+        // Lout = H + 1 with H = P.M a power of two, and every column has at
+        // most H + 1 coefficients.  Outputs s < H are the H-point transform of
+        // P_c mod (x^H - 1) = lo + hi (hi is only the coefficient x_H); output
+        // H is P_c(w_H) = (lo - hi)(w_H) = (lo + hi)(w_H) - 2 x_H, one
+        // evaluation of the folded block taken before its transform.
+        const uint32_t H = P.M;
+        for (uint32_t c = threadIdx.x; c < C; c += blockDim.x) {
+            const uint64_t idx = (c0 + c) + (uint64_t)H * W;
+            hi0[c] = idx < P.n_src ? P.src[idx] : Word(0);
+        }
+        __syncthreads();
+        for (uint32_t it = threadIdx.x; it < H * C; it += blockDim.x) {
+            const uint32_t c = it & (C - 1), d = it >> LOGC;
+            const uint64_t idx = (c0 + c) + (uint64_t)d * W;
+            Word v = idx < P.n_src ? P.src[idx] : Word(0);
+            if (d == 0) v = md.add(v, hi0[c]);
+            buf[it] = v;
+        }
+        __syncthreads();
+        eval_lanes(md, buf, LOGC, H, tw_fwd(md, T, H), red, extra);
+        dif_forward(md, T, buf, LOGC, H, 0, H, 0);
+        for (uint32_t it = threadIdx.x; it < (H + 1) * C; it += blockDim.x) {
+            const uint32_t c = it & (C - 1), d = it >> LOGC;
+            const uint64_t idx = (c0 + c) + (uint64_t)d * W;
+            const Word v = d < H ? buf[it] : md.sub(md.sub(extra[c], hi0[c]), hi0[c]);
+            if (idx < P.n)
+                P.X[idx] = v;
+            else if (P.b && d == P.a)
+                P.V[c0 + c] = v;
+        }
+        return;
+    }
     for (uint32_t it = threadIdx.x; it < P.M * C; it += blockDim.x) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint64_t idx = (c0 + c) + (uint64_t)d * W;
@@ -229,35 +276,62 @@ __host__ __device__ inline uint32_t row_inv_items(uint32_t W, uint32_t a, uint32
 // restored coefficients; phase 1 handles c < b (length a + 1).  Columns of the
 // other class inside the tile are skipped.
 template <class Mod, int LOGC>
-__device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
+__device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0,
                              const TwoPass<typename Mod::Word>& P, int phase, uint32_t tile) {
     using Word = typename Mod::Word;
     constexpr uint32_t C = 1u << LOGC;
+    __shared__ Word red[kColThreads];
+    __shared__ Word extra[kMaxC], last[kMaxC];
     Word* buf = lds_buf<Word>();
+    const Tables<Word> T = local_tables(T0, buf + (P.M << LOGC), P.M / 2);
     const uint32_t c0 = tile * C;
     const uint64_t W = 1ull << P.logW;
     const uint32_t len = phase ? P.a + 1 : P.a;
     uint32_t Mg = 1;
     while (Mg < len) Mg <<= 1;
-    for (uint32_t it = threadIdx.x; it < P.M * C; it += blockDim.x) {
+    const bool top = P.split && len == P.M + 1;   // one coefficient above the H-point block
+    const uint32_t Mb = top ? P.M : Mg;            // block inverted in LDS
+    for (uint32_t it = threadIdx.x; it < Mb * C; it += blockDim.x) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint32_t col = c0 + c;
         const bool mine = phase ? (col < P.b) : (col >= P.b);
         buf[it] = (mine && d < len) ? P.X[col + (uint64_t)d * W] : Word(0);
     }
+    if (top) {
+        for (uint32_t c = threadIdx.x; c < C; c += blockDim.x) {
+            const uint32_t col = c0 + c;
+            const bool mine = phase ? (col < P.b) : (col >= P.b);
+            last[c] = mine ? P.X[col + (uint64_t)P.M * W] : Word(0);
+        }
+    }
     __syncthreads();
-    gitft(md, T, buf, LOGC, Mg, len, 0);
+    if (top) {
+        // outputs 0..H-1 are the transform of C0 = lo + hi, output H is
+        // C0(w_H) - 2 x_H (see col_fwd_body): invert the H-point block, then
+        // x_H = (C0(w_H) - y_H) / 2 and x_0 = C0_0 - x_H
+        const uint32_t H = P.M;
+        full_inverse(md, T, buf, LOGC, 0, H, 0);
+        eval_lanes(md, buf, LOGC, H, tw_fwd(md, T, H), red, extra);
+        if (threadIdx.x < C) {
+            const Word xh = md.half(md.sub(extra[threadIdx.x], last[threadIdx.x]));
+            last[threadIdx.x] = xh;
+            buf[threadIdx.x] = md.sub(buf[threadIdx.x], xh);
+        }
+        __syncthreads();
+    } else {
+        gitft(md, T, buf, LOGC, Mg, len, 0);
+    }
     for (uint32_t it = threadIdx.x; it < len * C; it += blockDim.x) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint32_t col = c0 + c;
         const bool mine = phase ? (col < P.b) : (col >= P.b);
-        if (mine) P.X[col + (uint64_t)d * W] = buf[it];
+        if (mine) P.X[col + (uint64_t)d * W] = d < Mb ? buf[it] : last[c];
     }
     if (phase == 0 && P.b) {
-        __syncthreads();
-        dif_forward(md, T, buf, LOGC, P.M, P.a, P.a + 1, 0);
+        // the extra value V_c = P_c(w_a) of the restored column
+        eval_lanes(md, buf, LOGC, P.a, tw_fwd(md, T, P.a), red, extra);
         for (uint32_t c = threadIdx.x; c < C; c += blockDim.x)
-            if (c0 + c >= P.b) P.V[c0 + c] = buf[P.a * C + c];
+            if (c0 + c >= P.b) P.V[c0 + c] = extra[c];
     }
 }
 
@@ -280,29 +354,30 @@ __device__ void last_inv_body(const Mod& md, const Tables<typename Mod::Word>& T
 
 // ---- single transform: one launch per pass, geometry by value
 template <class Mod, int LOGC>
-__global__ __launch_bounds__(kThreads) void k_col_fwd(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kColThreads) void k_col_fwd(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P, uint32_t tiles) {
     col_fwd_body<Mod, LOGC>(md, T, P, xcd_remap(blockIdx.x, tiles));
 }
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_row_fwd(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kRowThreads) void k_row_fwd(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P) {
     row_fwd_body(md, T, P, blockIdx.x);
 }
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_row_inv(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kRowThreads) void k_row_inv(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P) {
     row_inv_body(md, T, P, blockIdx.x);
 }
 template <class Mod, int LOGC>
-__global__ __launch_bounds__(kThreads) void k_col_inv(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kColThreads) void k_col_inv(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P, int phase, uint32_t tile0,
                                                       uint32_t tiles) {
     col_inv_body<Mod, LOGC>(md, T, P, phase, tile0 + xcd_remap(blockIdx.x, tiles));
 }
+constexpr int kLastThreads = 1024;   // the last-row inverse is one workgroup: give it many waves
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_last_inv(Mod md, Tables<typename Mod::Word> T,
-                                                       TwoPass<typename Mod::Word> P) {
+__global__ __launch_bounds__(kLastThreads) void k_last_inv(Mod md, Tables<typename Mod::Word> T,
+                                                           TwoPass<typename Mod::Word> P) {
     last_inv_body(md, T, P);
 }
 
@@ -313,35 +388,35 @@ struct Item {
     uint32_t idx;
 };
 template <class Mod, int LOGC>
-__global__ __launch_bounds__(kThreads) void k_col_fwd_list(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kColThreads) void k_col_fwd_list(Mod md, Tables<typename Mod::Word> T,
                                                            const TwoPass<typename Mod::Word>* recs,
                                                            const Item* items) {
     const Item it = items[blockIdx.x];
     col_fwd_body<Mod, LOGC>(md, T, recs[it.rec], it.idx);
 }
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_row_fwd_list(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kRowThreads) void k_row_fwd_list(Mod md, Tables<typename Mod::Word> T,
                                                            const TwoPass<typename Mod::Word>* recs,
                                                            const Item* items) {
     const Item it = items[blockIdx.x];
     row_fwd_body(md, T, recs[it.rec], it.idx);
 }
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_row_inv_list(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kRowThreads) void k_row_inv_list(Mod md, Tables<typename Mod::Word> T,
                                                            const TwoPass<typename Mod::Word>* recs,
                                                            const Item* items) {
     const Item it = items[blockIdx.x];
     row_inv_body(md, T, recs[it.rec], it.idx);
 }
 template <class Mod, int LOGC>
-__global__ __launch_bounds__(kThreads) void k_col_inv_list(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kColThreads) void k_col_inv_list(Mod md, Tables<typename Mod::Word> T,
                                                            const TwoPass<typename Mod::Word>* recs,
                                                            const Item* items, int phase) {
     const Item it = items[blockIdx.x];
     col_inv_body<Mod, LOGC>(md, T, recs[it.rec], phase, it.idx);
 }
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_last_inv_list(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kLastThreads) void k_last_inv_list(Mod md, Tables<typename Mod::Word> T,
                                                             const TwoPass<typename Mod::Word>* recs,
                                                             const Item* items) {
     last_inv_body(md, T, recs[items[blockIdx.x].rec]);
