@@ -32,6 +32,7 @@ constexpr size_t kScratchWords = size_t(1) << 16;   // V_c area: one word per co
 constexpr size_t kLdsSoft = 76 * 1024;          // preferred LDS per workgroup (two per CU)
 constexpr size_t kLdsHard = 160 * 1024;         // gfx950 LDS per workgroup
 constexpr size_t kLdsDynMax = 144 * 1024;       // dynamic LDS any launch may request
+constexpr uint64_t kFewColumns = 16;            // column classes up to this size run one column per workgroup
 
 typedef unsigned __int128 u128;
 
@@ -151,7 +152,7 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
     if (log2u(n) <= small_max_log2(w) && !(ctx->override_logW && (1ull << ctx->override_logW) < n)) {
         P.kind = 0;
         P.M = (uint32_t)pow2ceil(n);
-        P.lds_row = (size_t)P.M * w;                 // data; the kernels add M words of twiddles
+        P.lds_row = (size_t)tft::padded_words(P.M) * w;   // data tile; the kernels add M words of twiddles
         return P;
     }
     P.kind = 1;
@@ -165,8 +166,8 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
         P.M = (uint32_t)pow2ceil(P.Lout);
         P.split = (P.M >= 4 && P.Lout == P.M / 2 + 1) ? 1 : 0;
         if (P.split) P.M /= 2;
-        P.lds_col = (((size_t)P.M << P.logC) + P.M) * w;   // tile + LDS twiddles
-        P.lds_row = (size_t)P.W * w;
+        P.lds_col = ((size_t)tft::padded_words(P.M << P.logC) + P.M) * w;   // tile + LDS twiddles
+        P.lds_row = (size_t)tft::padded_words((uint32_t)P.W) * w;
     };
     const unsigned logC = (unsigned)P.logC;
     if (ctx->override_logW) {
@@ -177,7 +178,7 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
     // balanced split: W close to sqrt(n), within the LDS budget (preferred
     // budget first, then the larger one)
     const unsigned k = log2u(n);
-    for (size_t lim : {kLdsSoft, kLdsHard - 32 * 1024}) {
+    for (size_t lim : {kLdsSoft, kLdsDynMax}) {
         int best = -1;
         for (unsigned logW = logC; logW <= 16 && (1ull << logW) < n; logW++) {
             fill(logW);
@@ -221,6 +222,7 @@ bool set_lds_limits() {
         (const void*)tft::k_small_mul<Mod>,       (const void*)tft::k_small_list<Mod>,
         (const void*)tft::k_col_fwd<Mod, 3>,      (const void*)tft::k_col_fwd<Mod, 4>,
         (const void*)tft::k_col_inv<Mod, 3>,      (const void*)tft::k_col_inv<Mod, 4>,
+        (const void*)tft::k_col_inv<Mod, 0>,
         (const void*)tft::k_row_fwd<Mod>,         (const void*)tft::k_row_inv<Mod>,
         (const void*)tft::k_last_inv<Mod>,        (const void*)tft::k_col_fwd_list<Mod, 3>,
         (const void*)tft::k_col_fwd_list<Mod, 4>, (const void*)tft::k_col_inv_list<Mod, 3>,
@@ -264,7 +266,7 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
         if (src != X) {
             launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3(1), dim3(kThreads), 0, st, X, n, src, n_src);
         }
-        launch(ctx, TFT_K_SMALL_FWD, tft::k_small_fwd<Mod>, dim3(1), dim3(tft::kSmallThreads), 2 * P.lds_row, st, md, T, X, (uint32_t)n,
+        launch(ctx, TFT_K_SMALL_FWD, tft::k_small_fwd<Mod>, dim3(1), dim3(tft::kSmallThreads), P.lds_row + (size_t)P.M * ctx->wbytes, st, md, T, X, (uint32_t)n,
                            P.M);
         return launch_status();
     }
@@ -275,7 +277,7 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
         launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(tft::kColThreads), P.lds_col, st, md, T, G, tiles);
     else
         launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(tft::kColThreads), P.lds_col, st, md, T, G, tiles);
-    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(tft::kColThreads), P.lds_row,
+    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(tft::kRowThreads), P.lds_row,
            st, md, T, G);
     return launch_status();
 }
@@ -291,7 +293,7 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     if (P.kind < 0) return TFT_ERANGE;
     if (P.kind == 0) {
         if (Y) launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3(1), dim3(kThreads), 0, st, md, X, Y, n);
-        launch(ctx, TFT_K_SMALL_INV, tft::k_small_inv<Mod>, dim3(1), dim3(tft::kSmallThreads), 2 * P.lds_row, st, md, T, X, (uint32_t)n,
+        launch(ctx, TFT_K_SMALL_INV, tft::k_small_inv<Mod>, dim3(1), dim3(tft::kSmallThreads), P.lds_row + (size_t)P.M * ctx->wbytes, st, md, T, X, (uint32_t)n,
                            P.M);
         return launch_status();
     }
@@ -302,15 +304,29 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     const uint32_t nrows = tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
     launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows), dim3(tft::kRowThreads), P.lds_row, st, md, T, G);
     auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
+    // A class with only a few columns runs one column per workgroup, so that a
+    // tile does not transform C - 1 skipped columns on one CU.
+    const size_t lds_one = ((size_t)tft::padded_words(P.M) + P.M) * ctx->wbytes;
     {   // columns c >= b
-        const uint32_t t0 = (uint32_t)(P.b / C);
-        const uint32_t nt = tiles_all - t0;
-        launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 0, t0, nt);
+        const uint64_t ncols = P.W - P.b;
+        if (ncols <= kFewColumns) {
+            launch(ctx, TFT_K_COL_INV_SHORT, tft::k_col_inv<Mod, 0>, dim3((uint32_t)ncols), dim3(tft::kColThreads),
+                   lds_one, st, md, T, G, 0, (uint32_t)P.b, (uint32_t)ncols);
+        } else {
+            const uint32_t t0 = (uint32_t)(P.b / C);
+            const uint32_t nt = tiles_all - t0;
+            launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 0, t0, nt);
+        }
     }
     if (P.b) {
         launch(ctx, TFT_K_LAST_INV, tft::k_last_inv<Mod>, dim3(1), dim3(tft::kLastThreads), P.lds_row, st, md, T, G);
-        const uint32_t nt = (uint32_t)((P.b + C - 1) / C);
-        launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 1, 0u, nt);
+        if (P.b <= kFewColumns) {
+            launch(ctx, TFT_K_COL_INV_LONG, tft::k_col_inv<Mod, 0>, dim3((uint32_t)P.b), dim3(tft::kColThreads),
+                   lds_one, st, md, T, G, 1, 0u, (uint32_t)P.b);
+        } else {
+            const uint32_t nt = (uint32_t)((P.b + C - 1) / C);
+            launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 1, 0u, nt);
+        }
     }
     return launch_status();
 }
@@ -331,10 +347,11 @@ tft_status mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const
     const uint64_t r = m + nb - 1;
     const Plan P = make_plan(ctx, r);
     if (P.kind < 0) return TFT_ERANGE;
-    if (P.kind == 0 && 3 * P.lds_row <= kLdsHard - 32 * 1024) {
+    const size_t mul_lds = 2 * P.lds_row + (size_t)P.M * ctx->wbytes;
+    if (P.kind == 0 && mul_lds <= kLdsHard - 32 * 1024) {
         const Mod& md = mod_of<Mod>(ctx);
         const auto T = tables_of<typename Mod::Word>(ctx);
-        launch(ctx, TFT_K_SMALL_MUL, tft::k_small_mul<Mod>, dim3(1), dim3(tft::kSmallThreads), 3 * P.lds_row, st, md, T, A, (uint32_t)m,
+        launch(ctx, TFT_K_SMALL_MUL, tft::k_small_mul<Mod>, dim3(1), dim3(tft::kSmallThreads), mul_lds, st, md, T, A, (uint32_t)m,
                            B, (uint32_t)nb, X, P.M);
         return launch_status();
     }
@@ -512,7 +529,8 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
         if (log2u(r) > ctx->v) return TFT_ERANGE;
         const Plan P = make_plan(ctx, r);
         if (P.kind < 0) return TFT_ERANGE;
-        const size_t small_lds = (products ? 3 : 2) * (size_t)pow2ceil(r) * w;   // data + LDS twiddles
+        const size_t Mr = pow2ceil(r);
+        const size_t small_lds = ((products ? 2 : 1) * (size_t)tft::padded_words((uint32_t)Mr) + Mr) * w;   // data + twiddles
         if (P.kind == 0 && small_lds <= small_lds_cap) {
             tft::SmallJob<Word> J;
             J.A = (const Word*)D.a;

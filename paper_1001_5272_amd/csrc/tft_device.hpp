@@ -41,6 +41,12 @@ struct Tables {
     uint32_t nl = 0;
 };
 
+// Threads in the workgroup.  Every launch here has uniform workgroups, so the
+// size comes from the kernel's hidden arguments through one scalar load;
+// blockDim.x also allows for a partial last workgroup and compiles to a
+// vector load of the dispatch data that is repeated after every barrier.
+__device__ __forceinline__ uint32_t nthreads() { return __builtin_amdgcn_workgroup_size_x(); }
+
 // ---------------------------------------------------------- 31-bit primes
 // Residues in [0, p), p < 2^31 odd.  Twiddles are kept in Montgomery form
 // (w 2^32 mod p) so that mul_tw(x, w 2^32) = x w mod p.
@@ -139,7 +145,7 @@ __device__ __forceinline__ typename Mod::Word tw_inv(const Mod& md, const Tables
 // replaces a dependent global load at the start of every stage group.
 template <class Word>
 __device__ Tables<Word> local_tables(const Tables<Word>& T, Word* dst, uint32_t nl) {
-    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
+    for (uint32_t i = threadIdx.x; i < nl; i += nthreads()) {
         dst[i] = T.f1[2 * i];
         dst[nl + i] = T.i1[2 * i];
     }
@@ -231,6 +237,13 @@ struct Unit {
 };
 
 // ------------------------------------------------------- LDS block views
+// LDS data tiles are addressed through pad(): one unused word after every 32,
+// which spreads the strided accesses of the radix-8 units over the banks (a
+// row tile without it meets 16-way bank conflicts in its lowest stages).
+__host__ __device__ __forceinline__ uint32_t pad(uint32_t x) { return x + (x >> 5); }
+// words of LDS a padded tile of n words occupies
+__host__ __device__ __forceinline__ uint32_t padded_words(uint32_t n) { return n + (n >> 5) + 1; }
+
 // A tile in LDS holds C interleaved vectors ("lanes"): element d of lane c is
 // buf[d * C + c].  Rows use C = 1.  All routines are called by every thread of
 // the workgroup and end with a barrier.
@@ -251,7 +264,7 @@ __device__ __forceinline__ void dif_group(const Mod& md, const Tables<typename M
     const uint32_t items = ((i_hi - i_lo + 1) << logq) << logC;
     const uint64_t gbase = g0 * (uint64_t)(M / two_h);
     Unit<Mod, S> un;
-    for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+    for (uint32_t it = threadIdx.x; it < items; it += nthreads()) {
         const uint32_t c = it & (C - 1);
         const uint32_t u = it >> logC;
         const uint32_t i = i_lo + (u >> logq);
@@ -259,37 +272,52 @@ __device__ __forceinline__ void dif_group(const Mod& md, const Tables<typename M
         const uint32_t base = i * two_h + j;
         Word x[R];
 #pragma unroll
-        for (int t = 0; t < R; t++) x[t] = buf[(base + t * q) * C + c];
+        for (int t = 0; t < R; t++) x[t] = buf[pad((base + t * q) * C + c)];
         un.load_fwd(md, T, gbase + i);
         un.forward(md, x);
 #pragma unroll
-        for (int t = 0; t < R; t++) buf[(base + t * q) * C + c] = x[t];
+        for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
     }
     __syncthreads();
 }
 
+// Lane exchange of one word across the wavefront (64-bit words as two halves).
+template <class Word>
+__device__ __forceinline__ Word shfl_xor_word(Word v, int mask) {
+    if constexpr (sizeof(Word) == 8) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, mask), hi = __shfl_xor((uint32_t)(v >> 32), mask);
+        return ((uint64_t)hi << 32) | lo;
+    } else {
+        return __shfl_xor(v, mask);
+    }
+}
+
 // Evaluation at one point for every lane of a tile: res[c] = sum_{d < len}
-// buf[d C + c] z^d (z in twiddle form).  The blockDim / C threads of a lane
-// each run Horner over one chunk of d, scale by z^(chunk start) and the chunk
-// values are summed.  red is LDS scratch of blockDim words, res of C words.
+// buf[d C + c] z^d (z in twiddle form).  The nthreads() / C threads of a lane
+// each run Horner over one chunk of d and scale by z^(chunk start); the chunk
+// values are summed across each wavefront by lane exchanges (threads of one
+// lane sit C apart), then across wavefronts.  red is LDS scratch of
+// (nthreads() / 64) C words, res of C words; C <= 64.
 template <class Mod>
 __device__ void eval_lanes(const Mod& md, const typename Mod::Word* buf, int logC, uint32_t len, typename Mod::Word z,
                            typename Mod::Word* red, typename Mod::Word* res) {
     using Word = typename Mod::Word;
     const uint32_t C = 1u << logC;
-    const uint32_t tpc = blockDim.x >> logC;
+    const uint32_t tpc = nthreads() >> logC;
     const uint32_t c = threadIdx.x & (C - 1), t = threadIdx.x >> logC;
     const uint32_t chunk = (len + tpc - 1) / tpc;
     const uint32_t lo = t * chunk;
     const uint32_t hi = lo + chunk < len ? lo + chunk : len;
     Word acc = 0;
-    for (uint32_t d = hi; d > lo; d--) acc = md.add(md.mul_tw(acc, z), buf[(d - 1) * C + c]);
+    for (uint32_t d = hi; d > lo; d--) acc = md.add(md.mul_tw(acc, z), buf[pad((d - 1) * C + c)]);
     if (lo > 0 && lo < hi) acc = md.mul_tw(acc, pow_tw(md, z, lo));
-    red[threadIdx.x] = acc;
+    for (uint32_t o = C; o < 64; o <<= 1) acc = md.add(acc, shfl_xor_word(acc, (int)o));
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < C) red[wave * C + lane] = acc;
     __syncthreads();
     if (threadIdx.x < C) {
         Word sum = 0;
-        for (uint32_t k = 0; k < tpc; k++) sum = md.add(sum, red[(k << logC) + threadIdx.x]);
+        for (uint32_t k = 0; k < (nthreads() >> 6); k++) sum = md.add(sum, red[k * C + threadIdx.x]);
         res[threadIdx.x] = sum;
     }
     __syncthreads();
@@ -312,7 +340,7 @@ __device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, 
 
 // One group of S inverse stages ending at half-size h (stages h/2^(S-1) .. h)
 // over every block of size 2h inside [off, off + Sz).
-template <class Mod, int S>
+template <class Mod, int S, bool SYNC = true>
 __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
                                           int logC, uint32_t off, uint32_t Sz, uint32_t h, uint64_t g) {
     using Word = typename Mod::Word;
@@ -324,7 +352,7 @@ __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename M
     const uint32_t items = (Sz >> S) << logC;   // one unit per R elements
     const uint64_t gbase = g * (uint64_t)(Sz / two_h);
     Unit<Mod, S> un;
-    for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+    for (uint32_t it = threadIdx.x; it < items; it += nthreads()) {
         const uint32_t c = it & (C - 1);
         const uint32_t u = it >> logC;
         const uint32_t i = u >> logq;
@@ -332,13 +360,13 @@ __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename M
         const uint32_t base = off + i * two_h + j;
         Word x[R];
 #pragma unroll
-        for (int t = 0; t < R; t++) x[t] = buf[(base + t * q) * C + c];
+        for (int t = 0; t < R; t++) x[t] = buf[pad((base + t * q) * C + c)];
         un.load_inv(md, T, gbase + i);
         un.inverse(md, x);
 #pragma unroll
-        for (int t = 0; t < R; t++) buf[(base + t * q) * C + c] = x[t];
+        for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
     }
-    __syncthreads();
+    if (SYNC) __syncthreads();
 }
 
 // Full inverse of the forward stages on the block of size Sz at offset off with
@@ -378,16 +406,20 @@ __device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T,
 //   m <  h: for j >= m both lo_j and hi_j are known, so C0_j = lo_j + w hi_j is
 //           a known coefficient of the left child, which is solved
 //           recursively; then lo_j = C0_j - w hi_j.
-// The full inverses act on disjoint dyadic pieces of [0, m) and read only
-// known values, so a caller may run them beforehand (in parallel, elsewhere)
-// and pass skip_full = true.
+// The schedule here is not recursive.  The full inverses act on the dyadic
+// pieces of [0, m) and read only given values, so they all run first
+// (pieces_inverse).  The downward steps then touch only positions >= m, and
+// the upward steps follow; both are taken three levels at a time in
+// registers (walk_group), so a block of size 2^L needs about L barriers in all
+// rather than one per level.  A caller that has already inverted the pieces
+// (elsewhere, in parallel) passes skip_full = true.
 constexpr int kMaxLevels = 24;   // log2 of the largest LDS block, with room
 
-// Level d of gitft's descent along the truncation boundary: offset and half
-// size of the block met there, its global index, and whether the walk went to
-// the right child.  Recomputed on demand so that no per-level array is kept.
+// Level d of gitft's walk along the truncation boundary: offset, half size
+// and global index of the block met there, the number m of transform values
+// it holds, and whether the walk goes on to its right child.
 struct Level {
-    uint32_t off, h;
+    uint32_t off, h, m;
     uint64_t g;
     bool right;
 };
@@ -397,7 +429,7 @@ __device__ __forceinline__ Level gitft_level(uint32_t M, uint32_t m, uint64_t g0
     for (int i = 0;; i++) {
         const uint32_t h = size >> 1;
         const bool right = m >= h;
-        if (i == d) return Level{off, h, g, right};
+        if (i == d) return Level{off, h, m, g, right};
         if (right) {
             off += h;
             g = 2 * g + 1;
@@ -409,96 +441,209 @@ __device__ __forceinline__ Level gitft_level(uint32_t M, uint32_t m, uint64_t g0
     }
 }
 
+// Number of levels of the walk (blocks with 0 < m < size).
+__host__ __device__ __forceinline__ int gitft_depth(uint32_t M, uint32_t m) {
+    int d = 0;
+    while (M > 1 && m > 0 && m < M) {
+        M >>= 1;
+        if (m >= M) m -= M;
+        d++;
+    }
+    return d;
+}
+
+// The full inverses of all pieces of [0, m) inside the block (size M, global
+// index g0).  The pieces are the dyadic blocks given by the set bits of m (bit
+// e: the block of size 2^e at offset m with bits 0..e cleared).  Stage group
+// s0 = 0, 3, 6, ... applies stages 2^s0 .. 2^(s0+2): the pieces of size at
+// least 2^(s0+3) are unions of aligned blocks of that size, which together
+// fill [0, m8) (m rounded down to a multiple of 2^(s0+3)) and take radix-8
+// units, while the pieces for bits s0+2 and s0+1 of m take their last two or
+// one stages here.  One barrier per stage group.
+template <class Mod>
+__device__ void pieces_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+                               uint32_t M, uint32_t m, uint64_t g0) {
+    using Word = typename Mod::Word;
+    const uint32_t C = 1u << logC;
+    const uint32_t logM = __builtin_ctz(M);
+    const uint64_t gbase = g0 << logM;   // global position of the block's first word
+    for (uint32_t s0 = 0; (m >> (s0 + 1)) != 0; s0 += 3) {
+        const uint32_t q = 1u << s0;
+        const uint32_t m8 = (m >> (s0 + 3)) << (s0 + 3);
+        const uint32_t n8 = m8 >> 3;
+        const uint32_t n4 = ((m >> (s0 + 2)) & 1u) << s0;
+        const uint32_t n2 = ((m >> (s0 + 1)) & 1u) << s0;
+        const uint32_t off4 = m8, off2 = m8 + (n4 << 2);
+        const uint32_t items = (n8 + n4 + n2) << logC;
+        Unit<Mod, 3> u8;
+        Unit<Mod, 2> u4;
+        Unit<Mod, 1> u2;
+        for (uint32_t it = threadIdx.x; it < items; it += nthreads()) {
+            const uint32_t c = it & (C - 1);
+            const uint32_t u = it >> logC;
+            if (u < n8) {
+                const uint32_t i = u >> s0, j = u & (q - 1);
+                const uint32_t base = (i << (s0 + 3)) + j;
+                Word x[8];
+#pragma unroll
+                for (int t = 0; t < 8; t++) x[t] = buf[pad((base + t * q) * C + c)];
+                u8.load_inv(md, T, (gbase >> (s0 + 3)) + i);
+                u8.inverse(md, x);
+#pragma unroll
+                for (int t = 0; t < 8; t++) buf[pad((base + t * q) * C + c)] = x[t];
+            } else if (u < n8 + n4) {
+                const uint32_t base = off4 + (u - n8);
+                Word x[4];
+#pragma unroll
+                for (int t = 0; t < 4; t++) x[t] = buf[pad((base + t * q) * C + c)];
+                u4.load_inv(md, T, (gbase + off4) >> (s0 + 2));
+                u4.inverse(md, x);
+#pragma unroll
+                for (int t = 0; t < 4; t++) buf[pad((base + t * q) * C + c)] = x[t];
+            } else {
+                const uint32_t base = off2 + (u - n8 - n4);
+                Word x[2];
+#pragma unroll
+                for (int t = 0; t < 2; t++) x[t] = buf[pad((base + t * q) * C + c)];
+                u2.load_inv(md, T, (gbase + off2) >> (s0 + 1));
+                u2.inverse(md, x);
+#pragma unroll
+                for (int t = 0; t < 2; t++) buf[pad((base + t * q) * C + c)] = x[t];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Per-level data of gitft's walk, filled once per call (one thread per level)
+// so that the passes below read it from LDS instead of re-walking the tree in
+// every wave.
+template <class Word>
+struct WalkTable {
+    uint32_t off[kMaxLevels];   // block offset
+    uint32_t h[kMaxLevels];     // half size
+    uint32_t lb[kMaxLevels];    // first j of the downward step's range, top bit = walk goes right
+    Word w[kMaxLevels], wi[kMaxLevels];
+};
+constexpr uint32_t kRightBit = 1u << 31;
+
+// S consecutive levels d0 .. d0+S-1 of gitft's walk in one pass.  With u the
+// half size of the deepest of them, the values at positions j + t u (t < 2^S)
+// of the level-d0 block contain every pair that the S levels combine, so one
+// unit per j < u does all S levels in registers.  Slot k of the unit holds
+// position t = k ^ rmask (rmask = the S walk directions, level d0 in the top
+// bit): at level d0+s the unit's part of the current block is slots
+// k < 2^(S-s), its child half slots k < 2^(S-s-1) and the sibling half the
+// rest, whatever the directions.
+//   down = true: the known-coefficient steps (C1_j = C0_j - 2 w hi_j on the
+//     right, C0_j = lo_j + w hi_j on the left) for j in the level's range;
+//   down = false: the upward steps, deepest level first.
+template <class Mod, int S>
+__device__ void walk_group(const Mod& md, typename Mod::Word* buf, int logC, int d0,
+                           const WalkTable<typename Mod::Word>& L, bool down) {
+    using Word = typename Mod::Word;
+    constexpr int R = 1 << S;
+    const uint32_t C = 1u << logC;
+    uint32_t lb[S];
+    bool rt[S];
+    Word w[S], wi[S];
+    uint32_t rmask = 0;
+    const uint32_t off = L.off[d0];
+    const uint32_t u = L.h[d0 + S - 1];
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        const uint32_t v = L.lb[d0 + s];
+        rt[s] = (v & kRightBit) != 0;
+        lb[s] = v & ~kRightBit;
+        rmask |= (rt[s] ? 1u : 0u) << (S - 1 - s);
+        w[s] = L.w[d0 + s];
+        wi[s] = L.wi[d0 + s];
+    }
+    const uint32_t items = u << logC;
+    for (uint32_t it = threadIdx.x; it < items; it += nthreads()) {
+        const uint32_t c = it & (C - 1);
+        const uint32_t j = it >> logC;
+        if (down) {
+            // a unit with no position in range at any level has nothing to do
+            bool any = false;
+#pragma unroll
+            for (int s = 0; s < S; s++) any |= j + ((R >> (s + 1)) - 1) * u >= lb[s];
+            if (!any) continue;
+        }
+        Word x[R];
+#pragma unroll
+        for (int k = 0; k < R; k++) x[k] = buf[pad((off + j + (k ^ rmask) * u) * C + c)];
+        if (down) {
+#pragma unroll
+            for (int s = 0; s < S; s++) {
+                const int half = R >> (s + 1);
+#pragma unroll
+                for (int k = 0; k < half; k++) {
+                    const uint32_t jj = j + ((k ^ rmask) & (half - 1)) * u;
+                    if (jj >= lb[s]) {
+                        const Word child = x[k], other = x[k + half];
+                        if (rt[s]) {
+                            const Word t = md.mul_tw(child, w[s]);
+                            x[k] = md.sub(md.sub(other, t), t);
+                        } else {
+                            x[k] = md.add(child, md.mul_tw(other, w[s]));
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < R / 2; k++) buf[pad((off + j + (k ^ rmask) * u) * C + c)] = x[k];
+        } else {
+#pragma unroll
+            for (int s = S - 1; s >= 0; s--) {
+                const int half = R >> (s + 1);
+#pragma unroll
+                for (int k = 0; k < half; k++) {
+                    const Word child = x[k], other = x[k + half];
+                    if (rt[s]) {   // lo = other, hi = child
+                        x[k + half] = md.half(md.add(other, child));
+                        x[k] = md.mul_tw(md.half(md.sub(other, child)), wi[s]);
+                    } else {       // lo = child, hi = other
+                        x[k] = md.sub(child, md.mul_tw(other, w[s]));
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < R; k++) buf[pad((off + j + (k ^ rmask) * u) * C + c)] = x[k];
+        }
+    }
+    __syncthreads();
+}
+
+template <class Mod>
+__device__ void walk_levels(const Mod& md, typename Mod::Word* buf, int logC, int d0, int S,
+                            const WalkTable<typename Mod::Word>& L, bool down) {
+    if (S == 3) walk_group<Mod, 3>(md, buf, logC, d0, L, down);
+    else if (S == 2) walk_group<Mod, 2>(md, buf, logC, d0, L, down);
+    else walk_group<Mod, 1>(md, buf, logC, d0, L, down);
+}
+
 template <class Mod>
 __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                       uint32_t M, uint32_t m, uint64_t g0, bool skip_full = false) {
     using Word = typename Mod::Word;
-    const uint32_t C = 1u << logC;
-    const uint32_t m0 = m;
-    // The walk visits at most log2 M levels; fetch each level's forward and
-    // inverse twiddle once, in parallel, instead of one dependent global load
-    // per level.
-    __shared__ Word lv_w[kMaxLevels], lv_wi[kMaxLevels];
-    int nlev = 0;
-    {
-        uint32_t mm = m, sz = M;
-        while (sz > 1 && mm > 0 && mm < sz) {
-            const uint32_t h = sz >> 1;
-            if (mm >= h) mm -= h;
-            sz = h;
-            nlev++;
-        }
+    __shared__ WalkTable<Word> L;
+    const int depth = gitft_depth(M, m);
+    if (threadIdx.x < (uint32_t)depth) {
+        const int d = (int)threadIdx.x;
+        const Level v = gitft_level(M, m, g0, d);
+        L.off[d] = v.off;
+        L.h[d] = v.h;
+        L.lb[d] = v.right ? (v.m - v.h) | kRightBit : v.m;
+        L.w[d] = tw_fwd(md, T, 2 * v.g);
+        L.wi[d] = tw_inv(md, T, 2 * v.g);
     }
-    if (threadIdx.x < (uint32_t)nlev) {
-        const Level L = gitft_level(M, m0, g0, (int)threadIdx.x);
-        lv_w[threadIdx.x] = tw_fwd(md, T, 2 * L.g);
-        lv_wi[threadIdx.x] = tw_inv(md, T, 2 * L.g);
-    }
-    __syncthreads();
-    int depth = 0;
-    uint32_t off = 0, size = M;
-    uint64_t g = g0;
-    while (size > 1 && m > 0 && m < size) {
-        const uint32_t h = size >> 1;
-        const Word w = lv_w[depth];
-        if (m >= h) {
-            if (!skip_full) full_inverse(md, T, buf, logC, off, h, 2 * g);
-            // right child's known coefficients: C1_j = C0_j - 2 w hi_j, j in [m - h, h)
-            const uint32_t j0 = m - h;
-            const uint32_t items = (h - j0) * C;
-            for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
-                const uint32_t c = it & (C - 1);
-                const uint32_t j = j0 + (it >> logC);
-                const Word c0 = buf[(off + j) * C + c];
-                const Word t = md.mul_tw(buf[(off + h + j) * C + c], w);
-                buf[(off + h + j) * C + c] = md.sub(md.sub(c0, t), t);
-            }
-            __syncthreads();
-            off += h;
-            g = 2 * g + 1;
-            m -= h;
-        } else {
-            // left child's known coefficients: C0_j = lo_j + w hi_j, j in [m, h)
-            const uint32_t items = (h - m) * C;
-            for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
-                const uint32_t c = it & (C - 1);
-                const uint32_t j = m + (it >> logC);
-                const Word lo = buf[(off + j) * C + c];
-                const Word t = md.mul_tw(buf[(off + h + j) * C + c], w);
-                buf[(off + j) * C + c] = md.add(lo, t);
-            }
-            __syncthreads();
-            g = 2 * g;
-        }
-        size = h;
-        depth++;
-    }
-    if (size > 1 && m == size && !skip_full) full_inverse(md, T, buf, logC, off, size, g);
-    // ascend
-    for (int d = depth - 1; d >= 0; d--) {
-        const Level L = gitft_level(M, m0, g0, d);
-        const uint32_t o = L.off, h = L.h;
-        const uint32_t items = h * C;
-        if (L.right) {
-            const Word wi = lv_wi[d];
-            for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
-                const uint32_t c = it & (C - 1);
-                const uint32_t j = it >> logC;
-                const Word x = buf[(o + j) * C + c];
-                const Word y = buf[(o + h + j) * C + c];
-                buf[(o + j) * C + c] = md.half(md.add(x, y));
-                buf[(o + h + j) * C + c] = md.mul_tw(md.half(md.sub(x, y)), wi);
-            }
-        } else {
-            const Word w = lv_w[d];
-            for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
-                const uint32_t c = it & (C - 1);
-                const uint32_t j = it >> logC;
-                const Word t = md.mul_tw(buf[(o + h + j) * C + c], w);
-                buf[(o + j) * C + c] = md.sub(buf[(o + j) * C + c], t);
-            }
-        }
-        __syncthreads();
+    if (!skip_full && (m >> 1) != 0) pieces_inverse(md, T, buf, logC, M, m, g0);   // ends with a barrier
+    else __syncthreads();
+    for (int d = 0; d < depth; d += 3) walk_levels(md, buf, logC, d, depth - d < 3 ? depth - d : 3, L, true);
+    for (int e = depth; e > 0; e -= 3) {
+        const int S = e < 3 ? e : 3;
+        walk_levels(md, buf, logC, e - S, S, L, false);
     }
 }
 

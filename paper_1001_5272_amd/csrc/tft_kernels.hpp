@@ -55,11 +55,11 @@ __device__ void small_forward_body(const Mod& md, const Tables<typename Mod::Wor
                                    uint32_t n, uint32_t M) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
-    const Tables<Word> L = local_tables(T0, buf + M, M / 2);
-    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) buf[i] = i < n ? X[i] : Word(0);
+    const Tables<Word> L = local_tables(T0, buf + padded_words(M), M / 2);
+    for (uint32_t i = threadIdx.x; i < M; i += nthreads()) buf[pad(i)] = i < n ? X[i] : Word(0);
     __syncthreads();
     dif_forward(md, L, buf, 0, M, 0, n, 0);
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) X[i] = buf[i];
+    for (uint32_t i = threadIdx.x; i < n; i += nthreads()) X[i] = buf[pad(i)];
 }
 
 template <class Mod>
@@ -67,11 +67,11 @@ __device__ void small_inverse_body(const Mod& md, const Tables<typename Mod::Wor
                                    uint32_t n, uint32_t M) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
-    const Tables<Word> L = local_tables(T0, buf + M, M / 2);
-    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) buf[i] = i < n ? X[i] : Word(0);
+    const Tables<Word> L = local_tables(T0, buf + padded_words(M), M / 2);
+    for (uint32_t i = threadIdx.x; i < M; i += nthreads()) buf[pad(i)] = i < n ? X[i] : Word(0);
     __syncthreads();
     gitft(md, L, buf, 0, M, n, 0);
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) X[i] = buf[i];
+    for (uint32_t i = threadIdx.x; i < n; i += nthreads()) X[i] = buf[pad(i)];
 }
 
 // Whole product in one workgroup: both operands zero-extended to M words of
@@ -82,20 +82,20 @@ __device__ void small_mul_body(const Mod& md, const Tables<typename Mod::Word>& 
                                uint32_t M) {
     using Word = typename Mod::Word;
     Word* ba = lds_buf<Word>();
-    Word* bb = ba + M;
-    const Tables<Word> L = local_tables(T0, ba + 2 * M, M / 2);
+    Word* bb = ba + padded_words(M);
+    const Tables<Word> L = local_tables(T0, ba + 2 * padded_words(M), M / 2);
     const uint32_t r = m + nb - 1;
-    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
-        ba[i] = i < m ? A[i] : Word(0);
-        bb[i] = i < nb ? B[i] : Word(0);
+    for (uint32_t i = threadIdx.x; i < M; i += nthreads()) {
+        ba[pad(i)] = i < m ? A[i] : Word(0);
+        bb[pad(i)] = i < nb ? B[i] : Word(0);
     }
     __syncthreads();
     dif_forward(md, L, ba, 0, M, 0, r, 0);
     dif_forward(md, L, bb, 0, M, 0, r, 0);
-    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) ba[i] = i < r ? md.mul(ba[i], bb[i]) : Word(0);
+    for (uint32_t i = threadIdx.x; i < M; i += nthreads()) ba[pad(i)] = i < r ? md.mul(ba[pad(i)], bb[pad(i)]) : Word(0);
     __syncthreads();
     gitft(md, L, ba, 0, M, r, 0);
-    for (uint32_t i = threadIdx.x; i < r; i += blockDim.x) X[i] = ba[i];
+    for (uint32_t i = threadIdx.x; i < r; i += nthreads()) X[i] = ba[pad(i)];
 }
 
 // Single-instance single-workgroup kernels are latency-bound: run 16 waves.
@@ -149,10 +149,10 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
                              const TwoPass<typename Mod::Word>& P, uint32_t tile) {
     using Word = typename Mod::Word;
     constexpr uint32_t C = 1u << LOGC;
-    __shared__ Word red[kColThreads];
+    __shared__ Word red[(kColThreads / 64) * kMaxC];
     __shared__ Word extra[kMaxC], hi0[kMaxC];
     Word* buf = lds_buf<Word>();
-    const Tables<Word> T = local_tables(T0, buf + (P.M << LOGC), P.M / 2);
+    const Tables<Word> T = local_tables(T0, buf + padded_words(P.M << LOGC), P.M / 2);
     const uint32_t c0 = tile * C;
     const uint64_t W = 1ull << P.logW;
     if (P.split) {
@@ -162,25 +162,25 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
         // H is P_c(w_H) = (lo - hi)(w_H) = (lo + hi)(w_H) - 2 x_H, one
         // evaluation of the folded block taken before its transform.
         const uint32_t H = P.M;
-        for (uint32_t c = threadIdx.x; c < C; c += blockDim.x) {
+        for (uint32_t c = threadIdx.x; c < C; c += nthreads()) {
             const uint64_t idx = (c0 + c) + (uint64_t)H * W;
             hi0[c] = idx < P.n_src ? P.src[idx] : Word(0);
         }
         __syncthreads();
-        for (uint32_t it = threadIdx.x; it < H * C; it += blockDim.x) {
+        for (uint32_t it = threadIdx.x; it < H * C; it += nthreads()) {
             const uint32_t c = it & (C - 1), d = it >> LOGC;
             const uint64_t idx = (c0 + c) + (uint64_t)d * W;
             Word v = idx < P.n_src ? P.src[idx] : Word(0);
             if (d == 0) v = md.add(v, hi0[c]);
-            buf[it] = v;
+            buf[pad(it)] = v;
         }
         __syncthreads();
         eval_lanes(md, buf, LOGC, H, tw_fwd(md, T, H), red, extra);
         dif_forward(md, T, buf, LOGC, H, 0, H, 0);
-        for (uint32_t it = threadIdx.x; it < (H + 1) * C; it += blockDim.x) {
+        for (uint32_t it = threadIdx.x; it < (H + 1) * C; it += nthreads()) {
             const uint32_t c = it & (C - 1), d = it >> LOGC;
             const uint64_t idx = (c0 + c) + (uint64_t)d * W;
-            const Word v = d < H ? buf[it] : md.sub(md.sub(extra[c], hi0[c]), hi0[c]);
+            const Word v = d < H ? buf[pad(it)] : md.sub(md.sub(extra[c], hi0[c]), hi0[c]);
             if (idx < P.n)
                 P.X[idx] = v;
             else if (P.b && d == P.a)
@@ -188,20 +188,20 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
         }
         return;
     }
-    for (uint32_t it = threadIdx.x; it < P.M * C; it += blockDim.x) {
+    for (uint32_t it = threadIdx.x; it < P.M * C; it += nthreads()) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint64_t idx = (c0 + c) + (uint64_t)d * W;
-        buf[it] = (d < P.Lout && idx < P.n_src) ? P.src[idx] : Word(0);
+        buf[pad(it)] = (d < P.Lout && idx < P.n_src) ? P.src[idx] : Word(0);
     }
     __syncthreads();
     dif_forward(md, T, buf, LOGC, P.M, 0, P.Lout, 0);
-    for (uint32_t it = threadIdx.x; it < P.Lout * C; it += blockDim.x) {
+    for (uint32_t it = threadIdx.x; it < P.Lout * C; it += nthreads()) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint64_t idx = (c0 + c) + (uint64_t)d * W;
         if (idx < P.n)
-            P.X[idx] = buf[it];
+            P.X[idx] = buf[pad(it)];
         else if (P.b && d == P.a)
-            P.V[c0 + c] = buf[it];
+            P.V[c0 + c] = buf[pad(it)];
     }
 }
 
@@ -216,15 +216,15 @@ __device__ void row_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T,
     const uint32_t W = 1u << P.logW;
     Word* row = P.X + (uint64_t)j * W;
     if (j < P.a) {
-        for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = row[i];
+        for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = row[i];
         __syncthreads();
         dif_forward(md, T, buf, 0, W, 0, W, j);
-        for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) row[i] = buf[i];
+        for (uint32_t i = threadIdx.x; i < W; i += nthreads()) row[i] = buf[pad(i)];
     } else {
-        for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = i < P.b ? row[i] : P.V[i];
+        for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = i < P.b ? row[i] : P.V[i];
         __syncthreads();
         dif_forward(md, T, buf, 0, W, 0, P.b, P.a);
-        for (uint32_t i = threadIdx.x; i < P.b; i += blockDim.x) row[i] = buf[i];
+        for (uint32_t i = threadIdx.x; i < P.b; i += nthreads()) row[i] = buf[pad(i)];
     }
 }
 
@@ -255,13 +255,13 @@ __device__ void row_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
     Word* row = P.X + start;
     if (P.Y) {
         const Word* yr = P.Y + start;
-        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) buf[i] = md.mul(row[i], yr[i]);
+        for (uint32_t i = threadIdx.x; i < len; i += nthreads()) buf[pad(i)] = md.mul(row[i], yr[i]);
     } else {
-        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) buf[i] = row[i];
+        for (uint32_t i = threadIdx.x; i < len; i += nthreads()) buf[pad(i)] = row[i];
     }
     __syncthreads();
     full_inverse(md, T, buf, 0, 0, len, g);
-    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) row[i] = buf[i];
+    for (uint32_t i = threadIdx.x; i < len; i += nthreads()) row[i] = buf[pad(i)];
 }
 
 // Number of inverse-row items: a rows plus the last row's pieces.
@@ -280,10 +280,10 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
                              const TwoPass<typename Mod::Word>& P, int phase, uint32_t tile) {
     using Word = typename Mod::Word;
     constexpr uint32_t C = 1u << LOGC;
-    __shared__ Word red[kColThreads];
+    __shared__ Word red[(kColThreads / 64) * kMaxC];
     __shared__ Word extra[kMaxC], last[kMaxC];
     Word* buf = lds_buf<Word>();
-    const Tables<Word> T = local_tables(T0, buf + (P.M << LOGC), P.M / 2);
+    const Tables<Word> T = local_tables(T0, buf + padded_words(P.M << LOGC), P.M / 2);
     const uint32_t c0 = tile * C;
     const uint64_t W = 1ull << P.logW;
     const uint32_t len = phase ? P.a + 1 : P.a;
@@ -291,14 +291,14 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
     while (Mg < len) Mg <<= 1;
     const bool top = P.split && len == P.M + 1;   // one coefficient above the H-point block
     const uint32_t Mb = top ? P.M : Mg;            // block inverted in LDS
-    for (uint32_t it = threadIdx.x; it < Mb * C; it += blockDim.x) {
+    for (uint32_t it = threadIdx.x; it < Mb * C; it += nthreads()) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint32_t col = c0 + c;
         const bool mine = phase ? (col < P.b) : (col >= P.b);
-        buf[it] = (mine && d < len) ? P.X[col + (uint64_t)d * W] : Word(0);
+        buf[pad(it)] = (mine && d < len) ? P.X[col + (uint64_t)d * W] : Word(0);
     }
     if (top) {
-        for (uint32_t c = threadIdx.x; c < C; c += blockDim.x) {
+        for (uint32_t c = threadIdx.x; c < C; c += nthreads()) {
             const uint32_t col = c0 + c;
             const bool mine = phase ? (col < P.b) : (col >= P.b);
             last[c] = mine ? P.X[col + (uint64_t)P.M * W] : Word(0);
@@ -315,22 +315,22 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
         if (threadIdx.x < C) {
             const Word xh = md.half(md.sub(extra[threadIdx.x], last[threadIdx.x]));
             last[threadIdx.x] = xh;
-            buf[threadIdx.x] = md.sub(buf[threadIdx.x], xh);
+            buf[pad(threadIdx.x)] = md.sub(buf[pad(threadIdx.x)], xh);
         }
         __syncthreads();
     } else {
         gitft(md, T, buf, LOGC, Mg, len, 0);
     }
-    for (uint32_t it = threadIdx.x; it < len * C; it += blockDim.x) {
+    for (uint32_t it = threadIdx.x; it < len * C; it += nthreads()) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint32_t col = c0 + c;
         const bool mine = phase ? (col < P.b) : (col >= P.b);
-        if (mine) P.X[col + (uint64_t)d * W] = d < Mb ? buf[it] : last[c];
+        if (mine) P.X[col + (uint64_t)d * W] = d < Mb ? buf[pad(it)] : last[c];
     }
     if (phase == 0 && P.b) {
         // the extra value V_c = P_c(w_a) of the restored column
         eval_lanes(md, buf, LOGC, P.a, tw_fwd(md, T, P.a), red, extra);
-        for (uint32_t c = threadIdx.x; c < C; c += blockDim.x)
+        for (uint32_t c = threadIdx.x; c < C; c += nthreads())
             if (c0 + c >= P.b) P.V[c0 + c] = extra[c];
     }
 }
@@ -346,10 +346,10 @@ __device__ void last_inv_body(const Mod& md, const Tables<typename Mod::Word>& T
     Word* buf = lds_buf<Word>();
     const uint32_t W = 1u << P.logW;
     Word* row = P.X + (uint64_t)P.a * W;
-    for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) buf[i] = i < P.b ? row[i] : P.V[i];
+    for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = i < P.b ? row[i] : P.V[i];
     __syncthreads();
     gitft(md, T, buf, 0, W, P.b, P.a, /*skip_full=*/true);
-    for (uint32_t i = threadIdx.x; i < P.b; i += blockDim.x) row[i] = buf[i];
+    for (uint32_t i = threadIdx.x; i < P.b; i += nthreads()) row[i] = buf[pad(i)];
 }
 
 // ---- single transform: one launch per pass, geometry by value
@@ -462,22 +462,22 @@ __global__ void k_reset_counter(uint32_t* counter) {
 template <class Mod>
 __global__ __launch_bounds__(kThreads) void k_pointwise(Mod md, typename Mod::Word* X, const typename Mod::Word* Y,
                                                         uint64_t n) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    for (uint64_t i = blockIdx.x * (uint64_t)nthreads() + threadIdx.x; i < n; i += (uint64_t)gridDim.x * nthreads())
         X[i] = md.mul(X[i], Y[i]);
 }
 
 // dst[i] = i < n_src ? src[i] : 0 for i < n_dst
 template <class Word>
 __global__ __launch_bounds__(kThreads) void k_copy_pad(Word* dst, uint64_t n_dst, const Word* src, uint64_t n_src) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_dst;
-         i += (uint64_t)gridDim.x * blockDim.x)
+    for (uint64_t i = blockIdx.x * (uint64_t)nthreads() + threadIdx.x; i < n_dst;
+         i += (uint64_t)gridDim.x * nthreads())
         dst[i] = i < n_src ? src[i] : Word(0);
 }
 
 // Signed integers to residues: dst[i] = src[i] mod p in [0, p).
 template <class Word>
 __global__ __launch_bounds__(kThreads) void k_from_signed(Word* dst, const int64_t* src, uint64_t n, uint64_t p) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = blockIdx.x * (uint64_t)nthreads() + threadIdx.x; i < n; i += (uint64_t)gridDim.x * nthreads()) {
         const int64_t v = src[i];
         uint64_t r;
         if (v >= 0)
@@ -502,7 +502,7 @@ __device__ __forceinline__ uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t p)
 }
 __global__ __launch_bounds__(kThreads) void k_crt3(Crt3 c, const uint32_t* r1, const uint32_t* r2, const uint32_t* r3,
                                                   uint64_t* out, uint64_t n) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = blockIdx.x * (uint64_t)nthreads() + threadIdx.x; i < n; i += (uint64_t)gridDim.x * nthreads()) {
         const uint64_t a1 = r1[i], a2 = r2[i], a3 = r3[i];
         const uint64_t d2 = (a2 + c.p2 - a1 % c.p2) % c.p2;
         const uint64_t t2 = mulmod64(d2, c.inv_p1_mod_p2, c.p2);
