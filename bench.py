@@ -35,12 +35,55 @@ sys.path.insert(0, ROOT)
 METRIC = "TFT+ITFT Gbutterfly/s & HBM GB/s; batched mults/s + p99 latency vs plain"
 SWEEP = [1 << 22, (1 << 22) + 1, 3 << 21, (1 << 23) - 1, 1 << 23]
 HBM_PEAK_GBS = 8000.0
-# VALU: 256 CUs x 4 SIMDs x 16 lanes = 64 lanes/CU/clk at 2.4 GHz
+# VALU: 256 CUs x 4 SIMDs x 16 lanes = 64 32-bit lane operations per CU per
+# clock at 2.4 GHz
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# 32-bit VALU operations of one butterfly mod 2^64 - 2^32 + 1 (64 x 64-bit
+# product as four 32 x 32 + 64 multiply-adds, folding with 2^64 = 2^32 - 1 and
+# 2^96 = -1, modular add and subtract), register moves not counted
+OPS_PER_BUTTERFLY = 33
+ROW_KERNELS = ("row_fwd", "row_inv")
+COL_KERNELS = ("col_fwd", "col_inv_short", "col_inv_long")
 
 
 def nominal_butterflies(n: int) -> float:
     return (n / 2.0) * math.log2(n)
+
+
+def pass_butterflies(kernel: str, n: int, plan: dict) -> float:
+    """Nominal butterflies of one pass of the two-pass transform of length n:
+    the rows take log2 W of the log2 n levels, the columns the rest; the two
+    classes of inverse columns split the column share by their word counts."""
+    if plan["kind"] != 1:
+        return nominal_butterflies(n) if kernel.startswith("small") else 0.0
+    lw = plan["logW"]
+    total_levels = math.log2(n)
+    if kernel in ROW_KERNELS:
+        return (n / 2.0) * lw
+    if kernel in COL_KERNELS:
+        col = (n / 2.0) * max(total_levels - lw, 0.0)
+        if kernel == "col_fwd":
+            return col
+        W, a, b = plan["W"], plan["a"], plan["b"]
+        share = ((W - b) * a if kernel == "col_inv_short" else b * (a + 1)) / float(n)
+        return col * share
+    return 0.0
+
+
+def pass_words(kernel: str, n: int, plan: dict) -> float:
+    """Words one pass reads (and writes) once."""
+    if plan["kind"] != 1:
+        return float(n) if kernel.startswith("small") else 0.0
+    if kernel in ROW_KERNELS or kernel == "col_fwd":
+        return float(n)
+    W, a, b = plan["W"], plan["a"], plan["b"]
+    if kernel == "col_inv_short":
+        return float((W - b) * a)
+    if kernel == "col_inv_long":
+        return float(b * (a + 1))
+    if kernel == "last_inv":
+        return float(W)
+    return 0.0
 
 
 def parse():
@@ -52,7 +95,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the served Poisson stream")
     ap.add_argument("--plain-seconds", type=float, default=1.0, help="length of the plain FIFO comparison")
-    ap.add_argument("--skip", default="", help="comma list of extras to skip: batched,served,crt,sweep")
+    ap.add_argument("--skip", default="", help="comma list of extras to skip: products,small,sweep,batched,served,crt")
     return ap.parse_args()
 
 
@@ -120,6 +163,7 @@ def main():
     kstats = libtft.tft_timing_read(ctx)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     bfly = sum(2 * nominal_butterflies(n) for n in SWEEP)
+    words_per_step = sum(SWEEP)
     value = bfly / (ms_per_step * 1e-3) / 1e9
     # the round trip must restore the inputs exactly
     ok = all(np.array_equal(bufs[n].cpu().numpy(), host[n]) for n in SWEEP)
@@ -131,18 +175,24 @@ def main():
     dom = max(kstats.items(), key=lambda kv: kv[1][1])
     dname, (dcount, dms) = dom
     avg_ms = dms / dcount
-    # every column/row kernel is one HBM pass: it reads and writes each of the
-    # words it covers once.  Per timed step the sweep's words are covered once
-    # by each pass, so bytes per launch = 2 * 8 * (sum n) / launches per step.
-    words_per_step = sum(SWEEP)
     launches_per_step = dcount / args.steps
-    alg_bytes = 2 * 8 * words_per_step / launches_per_step
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    plans = {n: libtft.tft_plan_info(ctx, n) for n in SWEEP}
+    # Algorithmic work of one launch: the butterflies of the pass it runs
+    # (the nominal count split between the passes by their tree depth) and
+    # the words it must read and write once, averaged over the step.
+    bf_step = sum(pass_butterflies(dname, n, plans[n]) for n in SWEEP)
+    words_step = sum(pass_words(dname, n, plans[n]) for n in SWEEP)
+    bf_launch = bf_step / launches_per_step
+    alu_achieved = bf_launch * OPS_PER_BUTTERFLY / (avg_ms * 1e-3) / 1e12
+    hbm_bytes = 2 * 8 * words_step / launches_per_step
+    hbm_achieved = hbm_bytes / (avg_ms * 1e-3) / 1e9
     roofline = {
-        "kernel": dname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": dname, "bound": "alu", "achieved": round(alu_achieved, 2), "peak": round(VALU_PEAK_TOPS, 1),
+        "unit": "Tops/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+        "ops_per_butterfly": OPS_PER_BUTTERFLY, "butterflies_per_launch": int(bf_launch),
         "avg_launch_us": round(avg_ms * 1e3, 2), "launches": dcount,
-        "alg_bytes_per_launch": int(alg_bytes),
+        "hbm": {"achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(hbm_bytes)},
     }
     pmc_path = os.path.join(ROOT, "profiles", f"pmc_{dname}_goldilocks_sweep.json")
     if os.path.exists(pmc_path):
@@ -177,7 +227,7 @@ def main():
 
     if not args.no_extras:
         skip = set(x for x in args.skip.split(",") if x)
-        result.update(extras(ctx, bufs, host, p))
+        result.update(extras(ctx, bufs, host, p, skip))
         if "sweep" not in skip:
             result["sweep"] = length_sweep(ctx, p)
         if "batched" not in skip:
@@ -194,7 +244,7 @@ def main():
     ctx.close()
 
 
-def extras(ctx, bufs, host, p):
+def extras(ctx, bufs, host, p, skip=frozenset()):
     import numpy as np
     import torch
 
@@ -228,6 +278,19 @@ def extras(ctx, bufs, host, p):
     out["jump"] = {"tft_ratio_2^22+1_over_2^22": round(t[SWEEP[1]] / t[SWEEP[0]], 3),
                    "padded_ratio_2^22+1_over_2^22": round(tp[SWEEP[1]] / tp[SWEEP[0]], 3)}
 
+    if "products" not in skip:
+        out["poly_mul"] = products(ctx, p, dev)
+    if "small" not in skip:
+        out["small_c1"] = small_c1(dev)
+    return out
+
+
+def products(ctx, p, dev):
+    """poly_mul at product lengths r of the sweep against the padded product."""
+    import torch
+
+    import synth
+    from paper_1001_5272_amd import libtft
     print("[bench] products", file=sys.stderr, flush=True)
     prods = []
     for r in SWEEP:
@@ -247,9 +310,15 @@ def extras(ctx, bufs, host, p):
         prods.append({"r": r, "poly_mul_us": round(tm * 1e3, 1), "padded_mul_us": round(tpm * 1e3, 1),
                       "mults_per_s": round(1e3 / tm, 1), "same_as_padded": same})
         del Ap, Bp, X2
-    out["poly_mul"] = prods
+    return prods
 
-    # configuration 1: the small 998244353 product, launch-bound
+
+def small_c1(dev):
+    """Configuration 1: the 998244353 product 1000 x 1500 (launch-bound)."""
+    import torch
+
+    import synth
+    from paper_1001_5272_amd import libtft
     print("[bench] small product latency", file=sys.stderr, flush=True)
     p1, g1 = synth.P998
     c1 = libtft.Context(p1, g1, 0)
@@ -268,11 +337,11 @@ def extras(ctx, bufs, host, p):
     lat.sort()
     F = torch.from_numpy(synth.residues_u32(p1, 2499, 1)).to(dev)
     rt = event_time(lambda: (libtft.tft_forward(c1, F), libtft.tft_inverse(c1, F)), 21)
-    out["small_c1"] = {"workload": "998244353, 1000 x 1500 -> r=2499", "poly_mul_p50_us": round(lat[len(lat) // 2], 1),
-                       "poly_mul_p99_us": round(lat[int(len(lat) * 0.99) - 1], 1),
-                       "tft_itft_roundtrip_us": round(rt * 1e3, 1)}
+    res = {"workload": "998244353, 1000 x 1500 -> r=2499", "poly_mul_p50_us": round(lat[len(lat) // 2], 1),
+           "poly_mul_p99_us": round(lat[int(len(lat) * 0.99) - 1], 1),
+           "tft_itft_roundtrip_us": round(rt * 1e3, 1)}
     c1.close()
-    return out
+    return res
 
 
 def length_sweep(ctx, p, per_octave=8):
