@@ -32,7 +32,7 @@ constexpr size_t kScratchWords = size_t(1) << 16;   // V_c area: one word per co
 constexpr size_t kLdsSoft = 76 * 1024;          // preferred LDS per workgroup (two per CU)
 constexpr size_t kLdsHard = 160 * 1024;         // gfx950 LDS per workgroup
 constexpr size_t kLdsDynMax = 144 * 1024;       // dynamic LDS any launch may request
-constexpr uint64_t kFewColumns = 16;            // column classes up to this size run one column per workgroup
+constexpr uint64_t kFewColumns = 128;   // classes this narrow run one column per workgroup
 
 typedef unsigned __int128 u128;
 
@@ -250,6 +250,7 @@ tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t
     G.Lout = P.Lout;
     G.M = P.M;
     G.split = P.split;
+    G.early = 0;
     return G;
 }
 
@@ -298,34 +299,41 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
         return launch_status();
     }
     Word* V = reinterpret_cast<Word*>(ctx->scratch);
-    const auto G = two_pass_of<Word>(P, X, X, n, Y, V);
+    auto G = two_pass_of<Word>(P, X, X, n, Y, V);
+    // In split mode the columns c < b need the last row only for their top
+    // coefficient: they run with the columns c >= b, and the last-row inverse
+    // finishes them (early mode).
+    G.early = (P.split && P.b) ? 1u : 0u;
     const uint32_t C = 1u << P.logC;
     const uint32_t tiles_all = (uint32_t)(P.W >> P.logC);
     const uint32_t nrows = tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
     launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows), dim3(tft::kRowThreads), P.lds_row, st, md, T, G);
     auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
+    const uint32_t tiles_long = (uint32_t)((P.b + C - 1) / C);   // tiles holding columns c < b
     // A class with only a few columns runs one column per workgroup, so that a
     // tile does not transform C - 1 skipped columns on one CU.
     const size_t lds_one = ((size_t)tft::padded_words(P.M) + P.M) * ctx->wbytes;
-    {   // columns c >= b
-        const uint64_t ncols = P.W - P.b;
+    {   // columns c >= b (early mode: every column)
+        const uint64_t ncols = G.early ? P.W : P.W - P.b;
+        const uint32_t t0 = G.early ? 0u : (uint32_t)(P.b / C);
         if (ncols <= kFewColumns) {
             launch(ctx, TFT_K_COL_INV_SHORT, tft::k_col_inv<Mod, 0>, dim3((uint32_t)ncols), dim3(tft::kColThreads),
-                   lds_one, st, md, T, G, 0, (uint32_t)P.b, (uint32_t)ncols);
+                   lds_one, st, md, T, G, 0, (uint32_t)(P.W - ncols), (uint32_t)ncols);
         } else {
-            const uint32_t t0 = (uint32_t)(P.b / C);
             const uint32_t nt = tiles_all - t0;
             launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 0, t0, nt);
         }
     }
     if (P.b) {
         launch(ctx, TFT_K_LAST_INV, tft::k_last_inv<Mod>, dim3(1), dim3(tft::kLastThreads), P.lds_row, st, md, T, G);
-        if (P.b <= kFewColumns) {
+        if (G.early) {
+            // done: the last-row inverse completed the columns c < b
+        } else if (P.b <= kFewColumns) {
             launch(ctx, TFT_K_COL_INV_LONG, tft::k_col_inv<Mod, 0>, dim3((uint32_t)P.b), dim3(tft::kColThreads),
                    lds_one, st, md, T, G, 1, 0u, (uint32_t)P.b);
         } else {
-            const uint32_t nt = (uint32_t)((P.b + C - 1) / C);
-            launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 1, 0u, nt);
+            launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(tiles_long), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 1,
+                   0u, tiles_long);
         }
     }
     return launch_status();

@@ -323,19 +323,32 @@ __device__ void eval_lanes(const Mod& md, const typename Mod::Word* buf, int log
     __syncthreads();
 }
 
+// Stages per LDS round trip (1..3, at most `left`) for a pass over `words`
+// words.  Radix-8 units do the least work per butterfly, but a unit is a long
+// dependent chain for one lane: when the radix-8 units would leave more than
+// half of the workgroup idle (a block that alone occupies the CU), smaller
+// units give more lanes shorter chains.
+__device__ __forceinline__ int group_stages(uint32_t words, int left) {
+    const uint32_t half = nthreads() >> 1;
+    int S = 3;
+    while (S > 1 && (words >> S) < half) S--;
+    return S < left ? S : left;
+}
+
 // Forward transform of the block of size M at global index g0 (the block is
 // F mod (x^M - w_{g0})); only blocks meeting [out_lo, out_hi) are computed, so
 // positions outside that range end with unspecified values.
 template <class Mod>
 __device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                             uint32_t M, uint32_t out_lo, uint32_t out_hi, uint64_t g0) {
-    uint32_t h = M >> 1;
-    while (h >= 4) {
-        dif_group<Mod, 3>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
-        h >>= 3;
+    const uint32_t words = M << logC;
+    for (uint32_t h = M >> 1; h >= 1;) {
+        const int S = group_stages(words, __builtin_ctz(h) + 1);
+        if (S == 3) dif_group<Mod, 3>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
+        else if (S == 2) dif_group<Mod, 2>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
+        else dif_group<Mod, 1>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
+        h >>= S;
     }
-    if (h == 2) dif_group<Mod, 2>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
-    if (h == 1) dif_group<Mod, 1>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
 }
 
 // One group of S inverse stages ending at half-size h (stages h/2^(S-1) .. h)
@@ -375,14 +388,15 @@ template <class Mod>
 __device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                              uint32_t off, uint32_t Sz, uint64_t g) {
     if (Sz < 2) return;
-    const uint32_t L = __builtin_ctz(Sz);     // number of stages
-    uint32_t done = 0;                         // stages 2^0 .. 2^(done-1) finished
-    const uint32_t first = L % 3;              // leading short group so that the rest are radix-8
-    if (first == 1) { dit_group<Mod, 1>(md, T, buf, logC, off, Sz, 1, g); done = 1; }
-    if (first == 2) { dit_group<Mod, 2>(md, T, buf, logC, off, Sz, 2, g); done = 2; }
-    while (done < L) {
-        dit_group<Mod, 3>(md, T, buf, logC, off, Sz, 1u << (done + 2), g);
-        done += 3;
+    const int L = __builtin_ctz(Sz);     // number of stages
+    const uint32_t words = Sz << logC;
+    for (int done = 0; done < L;) {      // stages 2^0 .. 2^(done-1) finished
+        const int S = group_stages(words, L - done);
+        const uint32_t h = 1u << (done + S - 1);
+        if (S == 3) dit_group<Mod, 3>(md, T, buf, logC, off, Sz, h, g);
+        else if (S == 2) dit_group<Mod, 2>(md, T, buf, logC, off, Sz, h, g);
+        else dit_group<Mod, 1>(md, T, buf, logC, off, Sz, h, g);
+        done += S;
     }
 }
 
@@ -454,64 +468,76 @@ __host__ __device__ __forceinline__ int gitft_depth(uint32_t M, uint32_t m) {
 
 // The full inverses of all pieces of [0, m) inside the block (size M, global
 // index g0).  The pieces are the dyadic blocks given by the set bits of m (bit
-// e: the block of size 2^e at offset m with bits 0..e cleared).  Stage group
-// s0 = 0, 3, 6, ... applies stages 2^s0 .. 2^(s0+2): the pieces of size at
-// least 2^(s0+3) are unions of aligned blocks of that size, which together
-// fill [0, m8) (m rounded down to a multiple of 2^(s0+3)) and take radix-8
-// units, while the pieces for bits s0+2 and s0+1 of m take their last two or
-// one stages here.  One barrier per stage group.
+// e: the block of size 2^e at offset m with bits 0..e cleared).  A pass takes
+// stages 2^s0 .. 2^(s0+S-1) (S from group_stages): the pieces of size at least
+// 2^(s0+S) are unions of aligned blocks of that size, which together fill
+// [0, mS) (m rounded down to a multiple of 2^(s0+S)) and take radix-2^S
+// units, while the pieces for bits s0+2 and s0+1 of m (below s0+S) take their
+// last two or one stages here.  One barrier per pass.
+template <class Mod, int S>
+__device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename Mod::Word>& T,
+                                            typename Mod::Word* buf, int logC, uint32_t m, uint64_t gbase,
+                                            uint32_t s0) {
+    using Word = typename Mod::Word;
+    constexpr int R = 1 << S;
+    const uint32_t C = 1u << logC;
+    const uint32_t q = 1u << s0;
+    const uint32_t mS = (m >> (s0 + S)) << (s0 + S);
+    const uint32_t nS = mS >> S;
+    const uint32_t n4 = S == 3 ? ((m >> (s0 + 2)) & 1u) << s0 : 0u;
+    const uint32_t n2 = S >= 2 ? ((m >> (s0 + 1)) & 1u) << s0 : 0u;
+    const uint32_t off4 = mS, off2 = mS + (n4 << 2);
+    const uint32_t items = (nS + n4 + n2) << logC;
+    Unit<Mod, S> uS;
+    Unit<Mod, 2> u4;
+    Unit<Mod, 1> u2;
+    for (uint32_t it = threadIdx.x; it < items; it += nthreads()) {
+        const uint32_t c = it & (C - 1);
+        const uint32_t u = it >> logC;
+        if (u < nS) {
+            const uint32_t i = u >> s0, j = u & (q - 1);
+            const uint32_t base = (i << (s0 + S)) + j;
+            Word x[R];
+#pragma unroll
+            for (int t = 0; t < R; t++) x[t] = buf[pad((base + t * q) * C + c)];
+            uS.load_inv(md, T, (gbase >> (s0 + S)) + i);
+            uS.inverse(md, x);
+#pragma unroll
+            for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
+        } else if (u < nS + n4) {
+            const uint32_t base = off4 + (u - nS);
+            Word x[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) x[t] = buf[pad((base + t * q) * C + c)];
+            u4.load_inv(md, T, (gbase + off4) >> (s0 + 2));
+            u4.inverse(md, x);
+#pragma unroll
+            for (int t = 0; t < 4; t++) buf[pad((base + t * q) * C + c)] = x[t];
+        } else {
+            const uint32_t base = off2 + (u - nS - n4);
+            Word x[2];
+#pragma unroll
+            for (int t = 0; t < 2; t++) x[t] = buf[pad((base + t * q) * C + c)];
+            u2.load_inv(md, T, (gbase + off2) >> (s0 + 1));
+            u2.inverse(md, x);
+#pragma unroll
+            for (int t = 0; t < 2; t++) buf[pad((base + t * q) * C + c)] = x[t];
+        }
+    }
+    __syncthreads();
+}
+
 template <class Mod>
 __device__ void pieces_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                                uint32_t M, uint32_t m, uint64_t g0) {
-    using Word = typename Mod::Word;
-    const uint32_t C = 1u << logC;
-    const uint32_t logM = __builtin_ctz(M);
-    const uint64_t gbase = g0 << logM;   // global position of the block's first word
-    for (uint32_t s0 = 0; (m >> (s0 + 1)) != 0; s0 += 3) {
-        const uint32_t q = 1u << s0;
-        const uint32_t m8 = (m >> (s0 + 3)) << (s0 + 3);
-        const uint32_t n8 = m8 >> 3;
-        const uint32_t n4 = ((m >> (s0 + 2)) & 1u) << s0;
-        const uint32_t n2 = ((m >> (s0 + 1)) & 1u) << s0;
-        const uint32_t off4 = m8, off2 = m8 + (n4 << 2);
-        const uint32_t items = (n8 + n4 + n2) << logC;
-        Unit<Mod, 3> u8;
-        Unit<Mod, 2> u4;
-        Unit<Mod, 1> u2;
-        for (uint32_t it = threadIdx.x; it < items; it += nthreads()) {
-            const uint32_t c = it & (C - 1);
-            const uint32_t u = it >> logC;
-            if (u < n8) {
-                const uint32_t i = u >> s0, j = u & (q - 1);
-                const uint32_t base = (i << (s0 + 3)) + j;
-                Word x[8];
-#pragma unroll
-                for (int t = 0; t < 8; t++) x[t] = buf[pad((base + t * q) * C + c)];
-                u8.load_inv(md, T, (gbase >> (s0 + 3)) + i);
-                u8.inverse(md, x);
-#pragma unroll
-                for (int t = 0; t < 8; t++) buf[pad((base + t * q) * C + c)] = x[t];
-            } else if (u < n8 + n4) {
-                const uint32_t base = off4 + (u - n8);
-                Word x[4];
-#pragma unroll
-                for (int t = 0; t < 4; t++) x[t] = buf[pad((base + t * q) * C + c)];
-                u4.load_inv(md, T, (gbase + off4) >> (s0 + 2));
-                u4.inverse(md, x);
-#pragma unroll
-                for (int t = 0; t < 4; t++) buf[pad((base + t * q) * C + c)] = x[t];
-            } else {
-                const uint32_t base = off2 + (u - n8 - n4);
-                Word x[2];
-#pragma unroll
-                for (int t = 0; t < 2; t++) x[t] = buf[pad((base + t * q) * C + c)];
-                u2.load_inv(md, T, (gbase + off2) >> (s0 + 1));
-                u2.inverse(md, x);
-#pragma unroll
-                for (int t = 0; t < 2; t++) buf[pad((base + t * q) * C + c)] = x[t];
-            }
-        }
-        __syncthreads();
+    const uint64_t gbase = g0 << __builtin_ctz(M);   // global position of the block's first word
+    const int top = 31 - __builtin_clz(m);            // largest piece: 2^top
+    for (int s0 = 0; s0 < top;) {
+        const int S = group_stages(m << logC, top - s0);
+        if (S == 3) pieces_pass<Mod, 3>(md, T, buf, logC, m, gbase, (uint32_t)s0);
+        else if (S == 2) pieces_pass<Mod, 2>(md, T, buf, logC, m, gbase, (uint32_t)s0);
+        else pieces_pass<Mod, 1>(md, T, buf, logC, m, gbase, (uint32_t)s0);
+        s0 += S;
     }
 }
 

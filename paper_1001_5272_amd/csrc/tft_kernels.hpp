@@ -136,9 +136,11 @@ struct TwoPass {
     uint64_t n_src, n;
     uint32_t logW, a, b, Lout, M;
     uint32_t split;   // 1: Lout = M + 1 with M a power of two (see col_fwd_body)
+    uint32_t early;   // inverse, split and b > 0: columns c < b run with phase 0 (see col_inv_body)
 };
 
 constexpr int kMaxC = 16;   // widest column tile
+constexpr int kLastThreads = 1024;   // the last-row inverse is one workgroup: give it many waves
 
 // Forward column pass over the tile of C columns starting at column tile*C:
 // evaluates each column polynomial at w_0..w_{Lout-1} (Lout = a + (b > 0)) in
@@ -291,17 +293,20 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
     while (Mg < len) Mg <<= 1;
     const bool top = P.split && len == P.M + 1;   // one coefficient above the H-point block
     const uint32_t Mb = top ? P.M : Mg;            // block inverted in LDS
+    // the columns of the tile in this class; in early mode (split, b > 0)
+    // phase 0 takes every column: the columns c < b need only their first H = a
+    // values here, and the last-row inverse finishes them
+    const bool every = P.early && phase == 0;
+    auto mine_col = [&](uint32_t col) { return every || (phase ? (col < P.b) : (col >= P.b)); };
     for (uint32_t it = threadIdx.x; it < Mb * C; it += nthreads()) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint32_t col = c0 + c;
-        const bool mine = phase ? (col < P.b) : (col >= P.b);
-        buf[pad(it)] = (mine && d < len) ? P.X[col + (uint64_t)d * W] : Word(0);
+        buf[pad(it)] = (mine_col(col) && d < len) ? P.X[col + (uint64_t)d * W] : Word(0);
     }
     if (top) {
         for (uint32_t c = threadIdx.x; c < C; c += nthreads()) {
             const uint32_t col = c0 + c;
-            const bool mine = phase ? (col < P.b) : (col >= P.b);
-            last[c] = mine ? P.X[col + (uint64_t)P.M * W] : Word(0);
+            last[c] = mine_col(col) ? P.X[col + (uint64_t)P.M * W] : Word(0);
         }
     }
     __syncthreads();
@@ -324,32 +329,54 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
     for (uint32_t it = threadIdx.x; it < len * C; it += nthreads()) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint32_t col = c0 + c;
-        const bool mine = phase ? (col < P.b) : (col >= P.b);
-        if (mine) P.X[col + (uint64_t)d * W] = d < Mb ? buf[pad(it)] : last[c];
+        if (mine_col(col)) P.X[col + (uint64_t)d * W] = d < Mb ? buf[pad(it)] : last[c];
     }
     if (phase == 0 && P.b) {
-        // the extra value V_c = P_c(w_a) of the restored column
+        // the extra value V_c = P_c(w_a) of the restored column (early mode:
+        // for c < b the same evaluation gives C0(w_H), H = a)
         eval_lanes(md, buf, LOGC, P.a, tw_fwd(md, T, P.a), red, extra);
         for (uint32_t c = threadIdx.x; c < C; c += nthreads())
-            if (c0 + c >= P.b) P.V[c0 + c] = extra[c];
+            if (mine_col(c0 + c)) P.V[c0 + c] = extra[c];
     }
 }
 
 // Inverse of the last row after its pieces were inverted by the row pass: the
 // b slots hold the pieces' coefficients and the W - b values V_c are the known
 // coefficients of the block; the remaining (elementwise) steps of the
-// truncated inverse recover the b column values P_c(w_a), c < b.
+// truncated inverse recover the b column values P_c(w_a), c < b.  With one
+// unknown (b = 1) the slot holds the value of the row polynomial at w_{aW},
+// so P_0(w_a) is that value minus sum_{c >= 1} V_c w_{aW}^c: one evaluation.
+// With P.early the columns c < b were inverted before (split mode, see
+// col_inv_body): their top coefficient is x_H = (C0(w_H) - P_c(w_a)) / 2, with
+// C0(w_H) left in V[c], and x_0 = C0_0 - x_H.
 template <class Mod>
 __device__ void last_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
                               const TwoPass<typename Mod::Word>& P) {
     using Word = typename Mod::Word;
+    __shared__ Word red[kLastThreads / 64], val[1];
     Word* buf = lds_buf<Word>();
     const uint32_t W = 1u << P.logW;
     Word* row = P.X + (uint64_t)P.a * W;
-    for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = i < P.b ? row[i] : P.V[i];
-    __syncthreads();
-    gitft(md, T, buf, 0, W, P.b, P.a, /*skip_full=*/true);
-    for (uint32_t i = threadIdx.x; i < P.b; i += nthreads()) row[i] = buf[pad(i)];
+    if (P.b == 1) {
+        for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = i == 0 ? Word(0) : P.V[i];
+        __syncthreads();
+        eval_lanes(md, buf, 0, W, tw_fwd(md, T, (uint64_t)P.a * W), red, val);
+        if (threadIdx.x == 0) buf[pad(0)] = md.sub(row[0], val[0]);
+        __syncthreads();
+    } else {
+        for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = i < P.b ? row[i] : P.V[i];
+        __syncthreads();
+        gitft(md, T, buf, 0, W, P.b, P.a, /*skip_full=*/true);
+    }
+    for (uint32_t i = threadIdx.x; i < P.b; i += nthreads()) {
+        if (P.early) {
+            const Word xh = md.half(md.sub(P.V[i], buf[pad(i)]));
+            row[i] = xh;
+            P.X[i] = md.sub(P.X[i], xh);
+        } else {
+            row[i] = buf[pad(i)];
+        }
+    }
 }
 
 // ---- single transform: one launch per pass, geometry by value
@@ -374,7 +401,6 @@ __global__ __launch_bounds__(kColThreads) void k_col_inv(Mod md, Tables<typename
                                                       uint32_t tiles) {
     col_inv_body<Mod, LOGC>(md, T, P, phase, tile0 + xcd_remap(blockIdx.x, tiles));
 }
-constexpr int kLastThreads = 1024;   // the last-row inverse is one workgroup: give it many waves
 template <class Mod>
 __global__ __launch_bounds__(kLastThreads) void k_last_inv(Mod md, Tables<typename Mod::Word> T,
                                                            TwoPass<typename Mod::Word> P) {
