@@ -215,13 +215,15 @@ typedef enum {
     TFT_K_COL_FWD,         /* forward column pass (large-stride layers) */
     TFT_K_ROW_FWD,         /* forward row pass (small-stride layers) and last row */
     TFT_K_ROW_INV,         /* inverse row pass */
-    TFT_K_COL_INV_SHORT,   /* inverse columns c >= b, re-deriving the extra evaluations */
+    TFT_K_COL_INV_SHORT,   /* inverse columns c >= b (single transforms with b > 0: every column on
+                              its first a values), re-deriving the extra evaluations */
     TFT_K_LAST_INV,        /* inverse of the partial last row */
-    TFT_K_COL_INV_LONG,    /* inverse columns c < b */
+    TFT_K_COL_INV_LONG,    /* inverse columns c < b (batches) */
     TFT_K_POINTWISE,       /* pointwise product */
     TFT_K_COPY,            /* zero-extending copy, counter reset, signed-to-residue */
     TFT_K_SMALL_LIST,      /* persistent single-workgroup jobs of a batch */
     TFT_K_CRT,             /* three-prime Chinese remaindering */
+    TFT_K_COL_FIX,         /* inverse: rank-one completion of the columns c < b */
     TFT_K_COUNT
 } tft_kernel_id;
 tft_status tft_timing_enable(tft_ctx* ctx, int on);

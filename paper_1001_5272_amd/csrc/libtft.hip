@@ -28,7 +28,10 @@ namespace {
 
 constexpr uint64_t kGoldilocks = 0xFFFFFFFF00000001ull;
 constexpr unsigned kMaxLog2 = 28;               // longest transform supported by the tables
-constexpr size_t kScratchWords = size_t(1) << 16;   // V_c area: one word per column, W <= 2^16
+constexpr size_t kVWords = size_t(1) << 16;          // V_c area: one word per column, W <= 2^16
+// V_c area, then the column polynomial Q of the general last-row step (two
+// buffers of kQStride words and 1 / Q(w_a))
+constexpr size_t kScratchWords = kVWords + 2 * size_t(tft::kQStride) + 64;
 constexpr size_t kLdsSoft = 76 * 1024;          // preferred LDS per workgroup (two per CU)
 constexpr size_t kLdsHard = 160 * 1024;         // gfx950 LDS per workgroup
 constexpr size_t kLdsDynMax = 144 * 1024;       // dynamic LDS any launch may request
@@ -86,7 +89,7 @@ struct tft_ctx {
     tft::ModGL m64;
     void* tables;        // f1 | f2 | i1 | i2
     size_t n1, n2;       // entries per level
-    void* scratch;       // V_c area
+    void* scratch;       // V_c area and column polynomial (kScratchWords words)
     // measurement mode (tft_timing_*): events bracketing each launch
     bool timing;
     struct Rec { int kid; hipEvent_t e0, e1; };
@@ -251,6 +254,7 @@ tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t
     G.M = P.M;
     G.split = P.split;
     G.early = 0;
+    G.Q = nullptr;
     return G;
 }
 
@@ -300,20 +304,25 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     }
     Word* V = reinterpret_cast<Word*>(ctx->scratch);
     auto G = two_pass_of<Word>(P, X, X, n, Y, V);
-    // In split mode the columns c < b need the last row only for their top
-    // coefficient: they run with the columns c >= b, and the last-row inverse
-    // finishes them (early mode).
-    G.early = (P.split && P.b) ? 1u : 0u;
+    // With b > 0 the columns c < b (a + 1 values) run with the columns c >= b on
+    // their first a values and are finished after the last row: in split mode
+    // by the last-row inverse alone (two coefficients change), otherwise by a
+    // rank-one update with the column polynomial Q (k_col_fix).  When a + 1 is
+    // a power of two the columns c < b are full inverses and the columns c >= b
+    // the truncated ones, so the two classes keep their own passes.
+    const bool full_long = P.b && ((P.a + 1) & P.a) == 0;
+    G.early = (P.b && !full_long) ? (P.split ? 1u : 2u) : 0u;
+    G.Q = V + kVWords;
     const uint32_t C = 1u << P.logC;
     const uint32_t tiles_all = (uint32_t)(P.W >> P.logC);
     const uint32_t nrows = tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
-    launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows), dim3(tft::kRowThreads), P.lds_row, st, md, T, G);
+    launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows + (G.early == 2 ? 1u : 0u)), dim3(tft::kRowThreads),
+           P.lds_row, st, md, T, G, ctx->p);
     auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
-    const uint32_t tiles_long = (uint32_t)((P.b + C - 1) / C);   // tiles holding columns c < b
     // A class with only a few columns runs one column per workgroup, so that a
     // tile does not transform C - 1 skipped columns on one CU.
     const size_t lds_one = ((size_t)tft::padded_words(P.M) + P.M) * ctx->wbytes;
-    {   // columns c >= b (early mode: every column)
+    {   // columns c >= b (early modes: every column)
         const uint64_t ncols = G.early ? P.W : P.W - P.b;
         const uint32_t t0 = G.early ? 0u : (uint32_t)(P.b / C);
         if (ncols <= kFewColumns) {
@@ -326,14 +335,19 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     }
     if (P.b) {
         launch(ctx, TFT_K_LAST_INV, tft::k_last_inv<Mod>, dim3(1), dim3(tft::kLastThreads), P.lds_row, st, md, T, G);
-        if (G.early) {
-            // done: the last-row inverse completed the columns c < b
-        } else if (P.b <= kFewColumns) {
-            launch(ctx, TFT_K_COL_INV_LONG, tft::k_col_inv<Mod, 0>, dim3((uint32_t)P.b), dim3(tft::kColThreads),
-                   lds_one, st, md, T, G, 1, 0u, (uint32_t)P.b);
-        } else {
-            launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(tiles_long), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 1,
-                   0u, tiles_long);
+        if (G.early == 2) {
+            const uint32_t gx = (uint32_t)((P.b + kThreads - 1) / kThreads);
+            const uint32_t gy = (uint32_t)std::min<uint64_t>(P.a, std::max<uint64_t>(1, 4096 / gx));
+            launch(ctx, TFT_K_COL_FIX, tft::k_col_fix<Mod>, dim3(gx, gy), dim3(kThreads), 0, st, md, G);
+        } else if (!G.early) {   // columns c < b, after the last row
+            if (P.b <= kFewColumns) {
+                launch(ctx, TFT_K_COL_INV_LONG, tft::k_col_inv<Mod, 0>, dim3((uint32_t)P.b), dim3(tft::kColThreads),
+                       lds_one, st, md, T, G, 1, 0u, (uint32_t)P.b);
+            } else {
+                const uint32_t nt = (uint32_t)((P.b + C - 1) / C);
+                launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 1,
+                       0u, nt);
+            }
         }
     }
     return launch_status();
@@ -1366,7 +1380,7 @@ tft_status tft_timing_reset(tft_ctx* ctx) {
 const char* tft_kernel_name(int id) {
     static const char* names[TFT_K_COUNT] = {"small_fwd", "small_inv", "small_mul", "col_fwd", "row_fwd",
                                              "row_inv", "col_inv_short", "last_inv", "col_inv_long",
-                                             "pointwise", "copy_pad", "small_list", "crt3"};
+                                             "pointwise", "copy_pad", "small_list", "crt3", "col_fix"};
     return (id >= 0 && id < TFT_K_COUNT) ? names[id] : "unknown";
 }
 

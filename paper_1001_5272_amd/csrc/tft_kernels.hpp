@@ -136,8 +136,11 @@ struct TwoPass {
     uint64_t n_src, n;
     uint32_t logW, a, b, Lout, M;
     uint32_t split;   // 1: Lout = M + 1 with M a power of two (see col_fwd_body)
-    uint32_t early;   // inverse, split and b > 0: columns c < b run with phase 0 (see col_inv_body)
+    uint32_t early;   // inverse with b > 0: 0 columns c < b after the last row; 1 split mode, 2 general
+                      // (columns c < b run with phase 0, see col_inv_body and last_inv_body)
+    Word* Q;          // early == 2: Q_0..Q_a at Q, scratch at Q + kQStride, 1 / Q(w_a) at Q[2 kQStride]
 };
+constexpr uint32_t kQStride = (1u << 16) + 64;
 
 constexpr int kMaxC = 16;   // widest column tile
 constexpr int kLastThreads = 1024;   // the last-row inverse is one workgroup: give it many waves
@@ -293,9 +296,9 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
     while (Mg < len) Mg <<= 1;
     const bool top = P.split && len == P.M + 1;   // one coefficient above the H-point block
     const uint32_t Mb = top ? P.M : Mg;            // block inverted in LDS
-    // the columns of the tile in this class; in early mode (split, b > 0)
-    // phase 0 takes every column: the columns c < b need only their first H = a
-    // values here, and the last-row inverse finishes them
+    // the columns of the tile in this class; in early modes phase 0 takes
+    // every column with its first a values, and the last-row inverse (and, in
+    // general, k_col_fix) finishes the columns c < b
     const bool every = P.early && phase == 0;
     auto mine_col = [&](uint32_t col) { return every || (phase ? (col < P.b) : (col >= P.b)); };
     for (uint32_t it = threadIdx.x; it < Mb * C; it += nthreads()) {
@@ -369,13 +372,76 @@ __device__ void last_inv_body(const Mod& md, const Tables<typename Mod::Word>& T
         gitft(md, T, buf, 0, W, P.b, P.a, /*skip_full=*/true);
     }
     for (uint32_t i = threadIdx.x; i < P.b; i += nthreads()) {
-        if (P.early) {
+        if (P.early == 1) {
             const Word xh = md.half(md.sub(P.V[i], buf[pad(i)]));
             row[i] = xh;
             P.X[i] = md.sub(P.X[i], xh);
+        } else if (P.early == 2) {
+            // the column's top coefficient t_c = (P_c(w_a) - P'_c(w_a)) / Q(w_a)
+            row[i] = md.mul(md.sub(buf[pad(i)], P.V[i]), P.Q[2 * kQStride]);
         } else {
             row[i] = buf[pad(i)];
         }
+    }
+}
+
+// The columns c < b hold a + 1 transform values; the column pass inverted only
+// the first a of them, giving the polynomial P'_c of degree < a through those
+// values and P'_c(w_a) (in V[c]).  The true column is P_c = P'_c + t_c Q with
+// Q = prod_{i < a} (x - w_i) (monic, degree a) and t_c = (P_c(w_a) -
+// P'_c(w_a)) / Q(w_a), P_c(w_a) being the last-row value.  The points w_0 ..
+// w_{a-1} are the dyadic pieces of [0, a) (one per set bit e of a: the roots of
+// x^(2^e) - w_{o_e / 2^e}, o_e = a with bits 0..e cleared), so Q is a product of
+// popcount(a) binomials; Q(w_a) = prod_e (w_{a >> e} - w_{o_e / 2^e}) since
+// w_s^(2^e) = w_{s >> e}.  One workgroup builds Q in the scratch area beside
+// the row pass.
+template <class Mod>
+__device__ typename Mod::Word pow_normal(const Mod& md, typename Mod::Word x, uint64_t e) {
+    typename Mod::Word r = 1;
+    while (e) {
+        if (e & 1) r = md.mul(r, x);
+        x = md.mul(x, x);
+        e >>= 1;
+    }
+    return r;
+}
+
+template <class Mod>
+__device__ void col_poly_body(const Mod& md, const Tables<typename Mod::Word>& T,
+                              const TwoPass<typename Mod::Word>& P, uint64_t p) {
+    using Word = typename Mod::Word;
+    const uint32_t a = P.a;
+    Word* cur = (__builtin_popcount(a) & 1) ? P.Q + kQStride : P.Q;   // ends in P.Q
+    Word* nxt = cur == P.Q ? P.Q + kQStride : P.Q;
+    if (threadIdx.x == 0) cur[0] = 1;
+    __syncthreads();
+    uint32_t deg = 0;
+    for (int e = 31; e >= 0; e--) {
+        if (!((a >> e) & 1u)) continue;
+        const uint32_t s = 1u << e;
+        const uint32_t o = (a >> (e + 1)) << (e + 1);
+        const Word ce = md.mul_tw(Word(1), tw_fwd(md, T, o >> e));
+        for (uint32_t d = threadIdx.x; d <= deg + s; d += nthreads()) {
+            Word v = d >= s ? cur[d - s] : Word(0);
+            if (d <= deg) v = md.sub(v, md.mul(ce, cur[d]));
+            nxt[d] = v;
+        }
+        __syncthreads();
+        Word* t = cur;
+        cur = nxt;
+        nxt = t;
+        deg += s;
+    }
+    if (threadIdx.x == 0) {
+        Word q = 1;
+        for (int e = 31; e >= 0; e--) {
+            if (!((a >> e) & 1u)) continue;
+            const uint32_t o = (a >> (e + 1)) << (e + 1);
+            const Word ce = md.mul_tw(Word(1), tw_fwd(md, T, o >> e));
+            const Word we = md.mul_tw(Word(1), tw_fwd(md, T, a >> e));
+            q = md.mul(q, md.sub(we, ce));
+        }
+        P.Q[2 * kQStride] = pow_normal(md, q, p - 2);
     }
 }
 
@@ -390,10 +456,17 @@ __global__ __launch_bounds__(kRowThreads) void k_row_fwd(Mod md, Tables<typename
                                                       TwoPass<typename Mod::Word> P) {
     row_fwd_body(md, T, P, blockIdx.x);
 }
+// With P.early == 2 workgroup 0 builds Q (col_poly_body; dispatched first, it
+// runs beside the rows) and workgroup k + 1 takes row item k.
 template <class Mod>
 __global__ __launch_bounds__(kRowThreads) void k_row_inv(Mod md, Tables<typename Mod::Word> T,
-                                                      TwoPass<typename Mod::Word> P) {
-    row_inv_body(md, T, P, blockIdx.x);
+                                                      TwoPass<typename Mod::Word> P, uint64_t p) {
+    const bool q = P.early == 2;
+    if (q && blockIdx.x == 0) {
+        col_poly_body(md, T, P, p);
+        return;
+    }
+    row_inv_body(md, T, P, blockIdx.x - (q ? 1u : 0u));
 }
 template <class Mod, int LOGC>
 __global__ __launch_bounds__(kColThreads) void k_col_inv(Mod md, Tables<typename Mod::Word> T,
@@ -405,6 +478,20 @@ template <class Mod>
 __global__ __launch_bounds__(kLastThreads) void k_last_inv(Mod md, Tables<typename Mod::Word> T,
                                                            TwoPass<typename Mod::Word> P) {
     last_inv_body(md, T, P);
+}
+// X[c + d W] += t_c Q_d for c < b, d < a (t_c in the last-row slot of column c);
+// grid: x over columns (kThreads each), y over strided rows d.
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_col_fix(Mod md, TwoPass<typename Mod::Word> P) {
+    using Word = typename Mod::Word;
+    const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= P.b) return;
+    const uint64_t W = 1ull << P.logW;
+    const Word t = P.X[(uint64_t)P.a * W + c];
+    for (uint32_t d = blockIdx.y; d < P.a; d += gridDim.y) {
+        Word* x = P.X + c + (uint64_t)d * W;
+        *x = md.add(*x, md.mul(t, P.Q[d]));
+    }
 }
 
 // ---- batches: every workgroup takes one (record, index) item of a work list

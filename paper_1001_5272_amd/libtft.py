@@ -63,7 +63,7 @@ SIGNATURES = {
 }
 
 KERNEL_NAMES = ["small_fwd", "small_inv", "small_mul", "col_fwd", "row_fwd", "row_inv", "col_inv_short",
-                "last_inv", "col_inv_long", "pointwise", "copy_pad", "small_list", "crt3"]
+                "last_inv", "col_inv_long", "pointwise", "copy_pad", "small_list", "crt3", "col_fix"]
 
 
 class TftError(RuntimeError):
