@@ -238,6 +238,12 @@ bool set_lds_limits() {
     return true;
 }
 
+// Threads of a row workgroup: one radix-8 unit per thread (W / 8), so that
+// the idle half of a wider workgroup does not hold wave slots of the CU.
+uint32_t row_threads(const Plan& P) {
+    return (uint32_t)std::min<uint64_t>(tft::kRowThreads, std::max<uint64_t>(256, P.W >> 3));
+}
+
 template <class Word>
 tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t n_src, const Word* Y, Word* V) {
     tft::TwoPass<Word> G;
@@ -282,7 +288,7 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
         launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(tft::kColThreads), P.lds_col, st, md, T, G, tiles);
     else
         launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(tft::kColThreads), P.lds_col, st, md, T, G, tiles);
-    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(tft::kRowThreads), P.lds_row,
+    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(row_threads(P)), P.lds_row,
            st, md, T, G);
     return launch_status();
 }
@@ -316,7 +322,7 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     const uint32_t C = 1u << P.logC;
     const uint32_t tiles_all = (uint32_t)(P.W >> P.logC);
     const uint32_t nrows = tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
-    launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows + (G.early == 2 ? 1u : 0u)), dim3(tft::kRowThreads),
+    launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows + (G.early == 2 ? 1u : 0u)), dim3(row_threads(P)),
            P.lds_row, st, md, T, G, ctx->p);
     auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
     // A class with only a few columns runs one column per workgroup, so that a
