@@ -93,6 +93,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="only the timed step, roofline and baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--no-autotune", action="store_true", help="plan with the built-in planner only")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the served Poisson stream")
     ap.add_argument("--plain-seconds", type=float, default=1.0, help="length of the plain FIFO comparison")
     ap.add_argument("--skip", default="", help="comma list of extras to skip: products,small,sweep,batched,served,crt")
@@ -142,6 +143,14 @@ def main():
     host = {n: synth.residues(p, n, 2000 + i) for i, n in enumerate(SWEEP)}
     bufs = {n: torch.from_numpy(host[n]).to(dev) for n in SWEEP}
     torch.cuda.synchronize()
+
+    # autotune each length (outside the timed steps): the plan cache then holds
+    # the fastest column width per ceil(lg n)
+    tuned = {}
+    if not args.no_autotune:
+        print("[bench] autotune", file=sys.stderr, flush=True)
+        for n in SWEEP:
+            tuned[n] = libtft.tft_autotune(ctx, n)["logW"]
 
     def step():
         for n in SWEEP:
@@ -194,6 +203,16 @@ def main():
         "hbm": {"achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(hbm_bytes)},
     }
+    # the same device's register-only and copy-only ceilings (outside the timed steps)
+    try:
+        cal = libtft.tft_calibrate(ctx)
+        bf_rate = bf_launch / (avg_ms * 1e-3) / 1e9
+        roofline["device_measured"] = {k: round(v, 2) for k, v in cal.items()}
+        roofline["achieved_gbutterfly_s"] = round(bf_rate, 1)
+        roofline["frac_of_register_butterflies"] = round(bf_rate / cal["butterflies_g"], 4)
+        roofline["hbm"]["frac_of_copy"] = round(hbm_achieved / cal["copy_gbs"], 4)
+    except Exception as ex:   # calibration is reported, never required
+        roofline["device_measured"] = {"error": str(ex)}
     pmc_path = os.path.join(ROOT, "profiles", f"pmc_{dname}_goldilocks_sweep.json")
     if os.path.exists(pmc_path):
         try:
@@ -220,7 +239,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "inplace TFT+ITFT sweep, p=2^64-2^32+1, n in {2^22, 2^22+1, 3*2^21, 2^23-1, 2^23}",
                    "prime": p, "generator": g, "lengths": SWEEP, "word_bytes": 8,
-                   "algorithmic_hbm_gbs": round(4 * 8 * words_per_step / (ms_per_step * 1e-3) / 1e9, 1)},
+                   "algorithmic_hbm_gbs": round(4 * 8 * words_per_step / (ms_per_step * 1e-3) / 1e9, 1),
+                   "plans": {str(n): libtft.tft_plan_info(ctx, n)["logW"] for n in SWEEP},
+                   "autotuned": not args.no_autotune},
         "roofline": roofline,
         "kernels": per_kernel,
     }

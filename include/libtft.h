@@ -201,6 +201,23 @@ tft_status tft_plan_info(tft_ctx* ctx, size_t n, tft_plan_desc* out);
  * Lengths whose tiles would not fit in LDS then return TFT_ERANGE. */
 tft_status tft_set_plan_override(tft_ctx* ctx, unsigned logW);
 
+/* Autotuner.  Times forward + inverse round trips of length n on the device
+ * (on a buffer of n words the call allocates and frees, filled with i mod p;
+ * synchronous) for each valid two-pass column width 2^logW within two of the
+ * planner's choice, and records the fastest in the context's plan cache for
+ * every length in the same bucket, floor(4 lg n) (quarter octaves).  Later
+ * calls of every entry point (single, batched, served) plan with the cached
+ * width; any width gives the same results.  Lengths the planner runs in one
+ * workgroup are left to the planner (cache entry 0).  `chosen` (may be NULL)
+ * receives the resulting plan.  The cache is plain data: tft_plan_cache_get /
+ * set read and write the entry of a bucket (0 = the planner's choice), so that
+ * a caller can store tuned plans and load them into a new context;
+ * tft_plan_bucket gives the bucket of a length. */
+tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen);
+tft_status tft_plan_cache_get(tft_ctx* ctx, unsigned bucket, unsigned* logW);
+tft_status tft_plan_cache_set(tft_ctx* ctx, unsigned bucket, unsigned logW);
+unsigned tft_plan_bucket(size_t n);
+
 /* Measurement mode.  While enabled, each kernel a context launches is
  * bracketed by two HIP events recorded on the caller's stream, so that a
  * benchmark can report per-kernel durations measured live (the events are
@@ -230,6 +247,23 @@ tft_status tft_timing_enable(tft_ctx* ctx, int on);
 tft_status tft_timing_read(tft_ctx* ctx, int id, uint64_t* launches, double* total_ms);
 tft_status tft_timing_reset(tft_ctx* ctx);
 const char* tft_kernel_name(int id);
+
+/* Roofline denominators measured on the context's device.  Not an operation
+ * of the paper: the peaks that benchmarks report the transform kernels
+ * against, each from a register-only or copy-only kernel timed with HIP
+ * events (the call allocates and frees its own buffers, about 0.5 GiB, and
+ * waits for the device; a few tens of milliseconds):
+ *   valu_tops      32-bit integer VALU operations per second / 10^12
+ *                  (chains of v_xad_u32);
+ *   mad64_tops     32 x 32 + 64 -> 64 multiply-adds per second / 10^12;
+ *   butterflies_g  butterflies per second / 10^9 with the context's modular
+ *                  arithmetic, in registers (radix-8 units, no memory traffic);
+ *   copy_gbs       HBM copy bandwidth, bytes read + written per second / 10^9.
+ * Returns TFT_EDEVICE if a kernel or allocation fails. */
+typedef struct {
+    double valu_tops, mad64_tops, butterflies_g, copy_gbs;
+} tft_calibration;
+tft_status tft_calibrate(tft_ctx* ctx, tft_calibration* out);
 
 /* Human-readable name of a status code. */
 const char* tft_strerror(tft_status s);

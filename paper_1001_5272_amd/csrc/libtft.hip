@@ -20,6 +20,7 @@
 
 #include "libtft.h"
 #include "tft_kernels.hpp"
+#include "tft_calib.hpp"
 
 using tft::kB1;
 using tft::kThreads;
@@ -28,6 +29,7 @@ namespace {
 
 constexpr uint64_t kGoldilocks = 0xFFFFFFFF00000001ull;
 constexpr unsigned kMaxLog2 = 28;               // longest transform supported by the tables
+constexpr unsigned kPlanBuckets = 4 * kMaxLog2 + 4;   // plan cache: quarter octaves of n
 constexpr size_t kVWords = size_t(1) << 16;          // V_c area: one word per column, W <= 2^16
 // V_c area, then the column polynomial Q of the general last-row step (two
 // buffers of kQStride words and 1 / Q(w_a))
@@ -85,6 +87,7 @@ struct tft_ctx {
     unsigned v;          // usable log2 length
     unsigned wbytes;     // 4 or 8
     unsigned override_logW;
+    unsigned tuned_logW[kPlanBuckets];   // plan cache by floor(4 lg n): 0 = planner's choice
     tft::ModU32 m32;
     tft::ModGL m64;
     void* tables;        // f1 | f2 | i1 | i2
@@ -148,6 +151,15 @@ void launch(tft_ctx* ctx, int kid, Kernel kernel, dim3 grid, dim3 block, size_t 
 
 unsigned small_max_log2(unsigned wbytes) { return wbytes == 4 ? 13 : 12; }
 
+// Plan-cache bucket of a length: floor(4 lg n) (quarter octaves), exactly.
+unsigned plan_bucket(uint64_t n) {
+    const unsigned e = 63u - (unsigned)__builtin_clzll(n);
+    const u128 n4 = (u128)n * n * n * n;
+    unsigned j = 0;
+    while (j < 3 && n4 >= ((u128)1 << (4 * e + j + 1))) j++;
+    return 4 * e + j;
+}
+
 Plan make_plan(const tft_ctx* ctx, uint64_t n) {
     Plan P{};
     P.n = n;
@@ -178,9 +190,14 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
         if (P.W < (1ull << logC) || P.a < 1 || P.lds_col > kLdsDynMax || P.lds_row > kLdsDynMax) P.kind = -1;
         return P;
     }
+    const unsigned k = log2u(n);
+    const unsigned bk = plan_bucket(n);
+    if (bk < kPlanBuckets && ctx->tuned_logW[bk] && (1ull << ctx->tuned_logW[bk]) < n) {   // tft_autotune
+        fill(ctx->tuned_logW[bk]);
+        if (P.W >= (1ull << logC) && P.a >= 1 && P.lds_col <= kLdsDynMax && P.lds_row <= kLdsDynMax) return P;
+    }
     // balanced split: W close to sqrt(n), within the LDS budget (preferred
     // budget first, then the larger one)
-    const unsigned k = log2u(n);
     for (size_t lim : {kLdsSoft, kLdsDynMax}) {
         int best = -1;
         for (unsigned logW = logC; logW <= 16 && (1ull << logW) < n; logW++) {
@@ -986,6 +1003,7 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
     c->v = v < kMaxLog2 ? v : kMaxLog2;
     c->wbytes = wide ? 8 : 4;
     c->override_logW = 0;
+    for (unsigned i = 0; i < kPlanBuckets; i++) c->tuned_logW[i] = 0;
     c->timing = false;
     c->last_batch = nullptr;
     c->last_done = nullptr;
@@ -1381,6 +1399,145 @@ tft_status tft_timing_reset(tft_ctx* ctx) {
     tft_status s = timing_collect(ctx);
     for (int i = 0; i < TFT_K_COUNT; i++) { ctx->launches[i] = 0; ctx->total_ms[i] = 0.0; }
     return s;
+}
+
+tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen) {
+    if (!ctx || n == 0) return TFT_EINVAL;
+    if (n > (1ull << ctx->v)) return TFT_ERANGE;
+    DeviceGuard dg(ctx->device);
+    const unsigned k = plan_bucket(n);
+    const unsigned saved_override = ctx->override_logW, saved_tuned = ctx->tuned_logW[k];
+    ctx->override_logW = 0;
+    ctx->tuned_logW[k] = 0;
+    const Plan base = make_plan(ctx, n);
+    tft_status st = TFT_OK;
+    unsigned best = 0;
+    if (base.kind == 1) {
+        void* X = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipMalloc(&X, n * ctx->wbytes) != hipSuccess) st = TFT_ENOMEM;
+        if (st == TFT_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = TFT_EDEVICE;
+        // canonical residues (i mod p), so that the timed kernels see real data
+        if (st == TFT_OK) {
+            if (ctx->wbytes == 8)
+                tft::k_fill_index<uint64_t><<<1024, kThreads>>>((uint64_t*)X, n, ctx->p);
+            else
+                tft::k_fill_index<uint32_t><<<1024, kThreads>>>((uint32_t*)X, n, ctx->p);
+            if (hipGetLastError() != hipSuccess) st = TFT_EDEVICE;
+        }
+        float best_ms = 0.f;
+        const int lo = std::max<int>((int)base.logW - 2, (int)base.logC), hi = std::min<int>((int)base.logW + 2, 16);
+        for (int lw = lo; lw <= hi && st == TFT_OK; lw++) {
+            if ((1ull << lw) >= n) break;
+            ctx->override_logW = (unsigned)lw;
+            if (make_plan(ctx, n).kind != 1) continue;
+            auto round_trip = [&]() {
+                tft_status a = tft_forward(ctx, X, n, nullptr);
+                tft_status b = tft_inverse(ctx, X, n, nullptr);
+                return a != TFT_OK ? a : b;
+            };
+            float ms_min = 0.f;
+            for (int rep = 0; rep < 4 && st == TFT_OK; rep++) {
+                if (hipEventRecord(e0, nullptr) != hipSuccess) { st = TFT_EDEVICE; break; }
+                const tft_status r = round_trip();
+                if (r != TFT_OK) { st = r; break; }
+                if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    st = TFT_EDEVICE;
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0 && (ms_min == 0.f || ms < ms_min)) ms_min = ms;   // first run warms up
+            }
+            if (st == TFT_OK && ms_min > 0.f && (best == 0 || ms_min < best_ms)) {
+                best = (unsigned)lw;
+                best_ms = ms_min;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (X) (void)hipFree(X);
+    }
+    ctx->override_logW = saved_override;
+    ctx->tuned_logW[k] = st == TFT_OK ? best : saved_tuned;
+    if (st == TFT_OK && chosen) st = tft_plan_info(ctx, n, chosen);
+    return st;
+}
+
+tft_status tft_plan_cache_get(tft_ctx* ctx, unsigned bucket, unsigned* logW) {
+    if (!ctx || !logW || bucket >= kPlanBuckets) return TFT_EINVAL;
+    *logW = ctx->tuned_logW[bucket];
+    return TFT_OK;
+}
+
+tft_status tft_plan_cache_set(tft_ctx* ctx, unsigned bucket, unsigned logW) {
+    if (!ctx || bucket >= kPlanBuckets || logW > 16) return TFT_EINVAL;
+    ctx->tuned_logW[bucket] = logW;
+    return TFT_OK;
+}
+
+unsigned tft_plan_bucket(size_t n) { return n ? plan_bucket(n) : 0u; }
+
+tft_status tft_calibrate(tft_ctx* ctx, tft_calibration* out) {
+    if (!ctx || !out) return TFT_EINVAL;
+    DeviceGuard dg(ctx->device);
+    const uint32_t blocks = 8192;
+    const size_t lanes = (size_t)blocks * tft::kCalThreads;
+    const uint64_t copy_words = uint64_t(1) << 24;   // 256 MiB each way in 16-byte words
+    void *o = nullptr, *x = nullptr, *tw = nullptr, *src = nullptr, *dst = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    tft_status st = TFT_OK;
+    auto ok = [&](hipError_t e) { if (e != hipSuccess && st == TFT_OK) st = TFT_EDEVICE; return st == TFT_OK; };
+    ok(hipMalloc(&o, lanes * 4));
+    ok(hipMalloc(&x, lanes * 8 * ctx->wbytes));
+    ok(hipMalloc(&tw, 8 * ctx->wbytes));
+    ok(hipMalloc(&src, copy_words * 16));
+    ok(hipMalloc(&dst, copy_words * 16));
+    ok(hipEventCreate(&e0));
+    ok(hipEventCreate(&e1));
+    if (st == TFT_OK) {
+        ok(hipMemset(x, 1, lanes * 8 * ctx->wbytes));   // residues 0x0101.. < p for both word sizes
+        ok(hipMemset(tw, 3, 8 * ctx->wbytes));
+        ok(hipMemset(src, 7, copy_words * 16));
+    }
+    // time one launch (after one warm-up launch of the same kernel)
+    auto timed = [&](auto&& run) -> double {
+        if (st != TFT_OK) return 0.0;
+        run();
+        ok(hipEventRecord(e0, nullptr));
+        run();
+        ok(hipEventRecord(e1, nullptr));
+        ok(hipEventSynchronize(e1));
+        float ms = 0.f;
+        ok(hipEventElapsedTime(&ms, e0, e1));
+        ok(hipGetLastError());
+        return ms > 0.f ? ms * 1e-3 : 0.0;
+    };
+    const int it_alu = 4000, it_bf = 400;
+    const double t_valu = timed([&] { tft::k_cal_valu<<<blocks, tft::kCalThreads>>>((uint32_t*)o, 3u, it_alu); });
+    const double t_mad = timed([&] { tft::k_cal_mad64<<<blocks, tft::kCalThreads>>>((uint32_t*)o, 3u, it_alu); });
+    const double t_bf = timed([&] {
+        if (ctx->wbytes == 8)
+            tft::k_cal_bfly<tft::ModGL><<<blocks, tft::kCalThreads>>>(ctx->m64, (uint64_t*)x, (const uint64_t*)tw, it_bf);
+        else
+            tft::k_cal_bfly<tft::ModU32><<<blocks, tft::kCalThreads>>>(ctx->m32, (uint32_t*)x, (const uint32_t*)tw, it_bf);
+    });
+    const double t_copy = timed([&] {
+        tft::k_cal_copy<<<2048, tft::kCalThreads>>>((uint4*)dst, (const uint4*)src, copy_words);
+    });
+    if (st == TFT_OK && t_valu > 0 && t_mad > 0 && t_bf > 0 && t_copy > 0) {
+        out->valu_tops = (double)lanes * it_alu * 8 / t_valu / 1e12;
+        out->mad64_tops = (double)lanes * it_alu * 8 / t_mad / 1e12;
+        out->butterflies_g = (double)lanes * it_bf * 12 / t_bf / 1e9;
+        out->copy_gbs = 2.0 * 16.0 * (double)copy_words / t_copy / 1e9;
+    } else if (st == TFT_OK) {
+        st = TFT_EDEVICE;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (void* q : {o, x, tw, src, dst})
+        if (q) (void)hipFree(q);
+    return st;
 }
 
 const char* tft_kernel_name(int id) {

@@ -454,10 +454,13 @@ __global__ __launch_bounds__(kColThreads) void k_col_fwd(Mod md, Tables<typename
 template <class Mod>
 __global__ __launch_bounds__(kRowThreads) void k_row_fwd(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P) {
-    row_fwd_body(md, T, P, blockIdx.x);
+    // the partial last row (item a) goes first: dispatched last, it would run
+    // alone after the full rows whenever they fill every slot of the device
+    const uint32_t k = P.b ? (blockIdx.x == 0 ? P.a : blockIdx.x - 1) : blockIdx.x;
+    row_fwd_body(md, T, P, k);
 }
 // With P.early == 2 workgroup 0 builds Q (col_poly_body; dispatched first, it
-// runs beside the rows) and workgroup k + 1 takes row item k.
+// runs beside the rows).  The last row's pieces come next, the full rows last.
 template <class Mod>
 __global__ __launch_bounds__(kRowThreads) void k_row_inv(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P, uint64_t p) {
@@ -466,7 +469,10 @@ __global__ __launch_bounds__(kRowThreads) void k_row_inv(Mod md, Tables<typename
         col_poly_body(md, T, P, p);
         return;
     }
-    row_inv_body(md, T, P, blockIdx.x - (q ? 1u : 0u));
+    // then the last row's pieces (items a ..), then the full rows
+    const uint32_t r = blockIdx.x - (q ? 1u : 0u);
+    const uint32_t np = __builtin_popcount(P.b);   // the pieces of [0, b): one per set bit
+    row_inv_body(md, T, P, r < np ? P.a + r : r - np);
 }
 template <class Mod, int LOGC>
 __global__ __launch_bounds__(kColThreads) void k_col_inv(Mod md, Tables<typename Mod::Word> T,
@@ -479,6 +485,13 @@ __global__ __launch_bounds__(kLastThreads) void k_last_inv(Mod md, Tables<typena
                                                            TwoPass<typename Mod::Word> P) {
     last_inv_body(md, T, P);
 }
+// X[i] = i mod p (canonical residues for timing runs).
+template <class Word>
+__global__ __launch_bounds__(kThreads) void k_fill_index(Word* X, uint64_t n, uint64_t p) {
+    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kThreads)
+        X[i] = (Word)(i % p);
+}
+
 // X[c + d W] += t_c Q_d for c < b, d < a (t_c in the last-row slot of column c);
 // grid: x over columns (kThreads each), y over strided rows d.
 template <class Mod>

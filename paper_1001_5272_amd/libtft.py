@@ -26,6 +26,17 @@ _sz = ctypes.c_size_t
 _st = ctypes.c_int
 
 # name -> (restype, argtypes); must list every function of include/libtft.h
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("logW", ctypes.c_uint), ("W", _sz), ("a", _sz), ("b", _sz),
+                ("col_block", _sz), ("cols_per_tile", ctypes.c_uint), ("lds_bytes_col", _sz),
+                ("lds_bytes_row", _sz)]
+
+
+class _Calibration(ctypes.Structure):
+    _fields_ = [("valu_tops", ctypes.c_double), ("mad64_tops", ctypes.c_double),
+                ("butterflies_g", ctypes.c_double), ("copy_gbs", ctypes.c_double)]
+
+
 SIGNATURES = {
     "tft_ctx_create": (_st, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_vp)]),
     "tft_ctx_destroy": (None, [_vp]),
@@ -55,6 +66,11 @@ SIGNATURES = {
     "tft_queue_completion_ns": (_st, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
     "tft_queue_stats": (_st, [_vp, _vp]),
     "tft_queue_destroy": (None, [_vp]),
+    "tft_calibrate": (_st, [_vp, ctypes.POINTER(_Calibration)]),
+    "tft_autotune": (_st, [_vp, _sz, ctypes.POINTER(PlanDesc)]),
+    "tft_plan_cache_get": (_st, [_vp, ctypes.c_uint, ctypes.POINTER(ctypes.c_uint)]),
+    "tft_plan_cache_set": (_st, [_vp, ctypes.c_uint, ctypes.c_uint]),
+    "tft_plan_bucket": (ctypes.c_uint, [_sz]),
     "tft_timing_enable": (_st, [_vp, ctypes.c_int]),
     "tft_timing_read": (_st, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
     "tft_timing_reset": (_st, [_vp]),
@@ -84,12 +100,6 @@ class BatchDesc(ctypes.Structure):
 class QueueDesc(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "batches", "deferred", "pending",
                                                  "inflight", "pool_words", "pool_used_max")]
-
-
-class PlanDesc(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("logW", ctypes.c_uint), ("W", _sz), ("a", _sz), ("b", _sz),
-                ("col_block", _sz), ("cols_per_tile", ctypes.c_uint), ("lds_bytes_col", _sz),
-                ("lds_bytes_row", _sz)]
 
 
 _lib = None
@@ -220,8 +230,54 @@ def tft_plan_info(ctx: Context, n: int) -> dict:
     return {f: getattr(d, f) for f, _ in PlanDesc._fields_}
 
 
+def tft_autotune(ctx: Context, n: int) -> dict:
+    """Time the candidate column widths for length n and cache the fastest
+    for every length with the same ceil(lg n); returns the resulting plan."""
+    d = PlanDesc()
+    _check(load().tft_autotune(ctx.handle, n, ctypes.byref(d)), "tft_autotune")
+    return {f: getattr(d, f) for f, _ in PlanDesc._fields_}
+
+
+def tft_plan_cache_get(ctx: Context, bucket: int) -> int:
+    v = ctypes.c_uint()
+    _check(load().tft_plan_cache_get(ctx.handle, bucket, ctypes.byref(v)), "tft_plan_cache_get")
+    return int(v.value)
+
+
+def tft_plan_cache_set(ctx: Context, bucket: int, logW: int):
+    _check(load().tft_plan_cache_set(ctx.handle, bucket, logW), "tft_plan_cache_set")
+
+
+def tft_plan_bucket(n: int) -> int:
+    """Plan-cache bucket of a length: floor(4 lg n)."""
+    return int(load().tft_plan_bucket(n))
+
+
+def plan_cache_dump(ctx: Context) -> dict:
+    """The context's tuned plans as {bucket: logW} (JSON-ready)."""
+    out = {}
+    for k in range(0, 4 * 28 + 4):
+        v = tft_plan_cache_get(ctx, k)
+        if v:
+            out[k] = v
+    return out
+
+
+def plan_cache_load(ctx: Context, plans: dict):
+    for k, v in plans.items():
+        tft_plan_cache_set(ctx, int(k), int(v))
+
+
 def tft_set_plan_override(ctx: Context, logW: int):
     _check(load().tft_set_plan_override(ctx.handle, logW), "tft_set_plan_override")
+
+
+def tft_calibrate(ctx: Context) -> dict:
+    """Measured roofline denominators of the context's device (see the header)."""
+    c = _Calibration()
+    _check(load().tft_calibrate(ctx.handle, ctypes.byref(c)), "tft_calibrate")
+    return {"valu_tops": c.valu_tops, "mad64_tops": c.mad64_tops, "butterflies_g": c.butterflies_g,
+            "copy_gbs": c.copy_gbs}
 
 
 def tft_timing_enable(ctx: Context, on: bool = True):

@@ -44,3 +44,15 @@ def test_strerror_without_device():
     lib.tft_strerror.argtypes = [ctypes.c_int]
     assert lib.tft_strerror(0) == b"ok"
     assert lib.tft_strerror(-2) == b"length or prime out of range"
+
+
+def test_plan_bucket_without_device():
+    # floor(4 lg n), exactly: the largest t with n^4 >= 2^t
+    lib = ctypes.CDLL(LIB)
+    lib.tft_plan_bucket.restype = ctypes.c_uint
+    lib.tft_plan_bucket.argtypes = [ctypes.c_size_t]
+    for n in [1, 2, 3, 4, 5, 7, 8, 9, 100003, (1 << 22) - 1, 1 << 22, (1 << 22) + 1, 3 << 21, 5931642, (1 << 28)]:
+        t = 0
+        while n ** 4 >= 2 ** (t + 1):
+            t += 1
+        assert lib.tft_plan_bucket(n) == t, n

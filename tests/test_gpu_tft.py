@@ -68,10 +68,13 @@ def test_two_pass_forced_small(ctxs, name, logW):
     libtft.tft_set_plan_override(ctx, logW)
     try:
         W = 1 << logW
-        # includes the split columns (a = 2^k with b > 0, and a = 2^k + 1 with b = 0)
+        # includes the split columns (a = 2^k with b > 0, and a = 2^k + 1 with b = 0),
+        # a + 1 = 2^k with b > 0 (two inverse column phases), and the general
+        # last row (columns c < b completed by the rank-one update), also with b = 1
         ns = sorted({W + 1, 2 * W - 1, 2 * W, 3 * W + 1, 5 * W - 1, 17 * W, 17 * W + 3, 33 * W + W // 2,
                      100 * W + 7, 1000, 2499, 4097, 16 * W + 1, 16 * W + W - 1, 32 * W + 5, 65 * W, 129 * W,
-                     64 * W + W // 2, 2 * W + 1, 3 * W})
+                     64 * W + W // 2, 2 * W + 1, 3 * W, 5 * W + 1, 6 * W + 2, 11 * W + W - 1, 7 * W + 3,
+                     9 * W + 5, 23 * W + 1, 15 * W + W // 3, 127 * W + 1})
         for n in ns:
             if n <= W:
                 continue
