@@ -255,10 +255,10 @@ bool set_lds_limits() {
     return true;
 }
 
-// Threads of a row workgroup: one radix-8 unit per thread (W / 8), so that
-// the idle half of a wider workgroup does not hold wave slots of the CU.
+// Threads of a row workgroup: one radix-8 unit per thread (W / 8, 64 ..
+// 1024), so that idle threads of a wider workgroup do not hold wave slots.
 uint32_t row_threads(const Plan& P) {
-    return (uint32_t)std::min<uint64_t>(tft::kRowThreads, std::max<uint64_t>(256, P.W >> 3));
+    return (uint32_t)std::min<uint64_t>(tft::kRowThreads, std::max<uint64_t>(64, P.W >> 3));
 }
 
 template <class Word>
@@ -547,6 +547,7 @@ struct tft_batch {
     void* jobs;
     uint32_t* counter;
     size_t lds_col, lds_row, lds_small;
+    uint32_t row_thr, col_thr;   // workgroup sizes of the pass launches (widest row / tile of the batch)
     int logC;
     uint32_t small_grid;
     hipStream_t side;          // the single-workgroup jobs run here, beside the two-pass phases
@@ -565,6 +566,7 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
     std::vector<size_t> vwords;   // V area size per record
     size_t v_total = 0;
     B->lds_col = B->lds_row = B->lds_small = 0;
+    B->row_thr = B->col_thr = 64;
     B->logC = (w == 4) ? 4 : 3;
     const size_t small_lds_cap = kLdsHard - 32 * 1024;
     for (size_t k = 0; k < count; k++) {
@@ -592,6 +594,10 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
         if (products && !D.work) return TFT_EINVAL;
         B->lds_col = std::max(B->lds_col, P.lds_col);
         B->lds_row = std::max(B->lds_row, P.lds_row);
+        // one radix-8 unit per thread: rows of W words, tiles of M C words
+        B->row_thr = std::max(B->row_thr, row_threads(P));
+        B->col_thr = (uint32_t)std::max<uint64_t>(
+            B->col_thr, std::min<uint64_t>(tft::kColThreads, ((uint64_t)P.M << P.logC) >> 3));
         const uint32_t tiles = (uint32_t)(P.W >> P.logC);
         const uint32_t C = 1u << P.logC;
         const int nops = products ? 2 : 1;
@@ -695,24 +701,24 @@ tft_status batch_run(tft_batch* B, hipStream_t st) {
     const bool c3 = B->logC == 3;
     if (B->n_items[PH_COL_FWD])
         launch(ctx, TFT_K_COL_FWD, c3 ? tft::k_col_fwd_list<Mod, 3> : tft::k_col_fwd_list<Mod, 4>,
-               dim3(B->n_items[PH_COL_FWD]), dim3(tft::kColThreads), B->lds_col, st, md, T, recs,
+               dim3(B->n_items[PH_COL_FWD]), dim3(B->col_thr), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_FWD]);
     if (B->n_items[PH_ROW_FWD])
-        launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd_list<Mod>, dim3(B->n_items[PH_ROW_FWD]), dim3(tft::kRowThreads), B->lds_row,
+        launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd_list<Mod>, dim3(B->n_items[PH_ROW_FWD]), dim3(B->row_thr), B->lds_row,
                st, md, T, recs, (const tft::Item*)B->items[PH_ROW_FWD]);
     if (B->n_items[PH_ROW_INV])
-        launch(ctx, TFT_K_ROW_INV, tft::k_row_inv_list<Mod>, dim3(B->n_items[PH_ROW_INV]), dim3(tft::kRowThreads), B->lds_row,
+        launch(ctx, TFT_K_ROW_INV, tft::k_row_inv_list<Mod>, dim3(B->n_items[PH_ROW_INV]), dim3(B->row_thr), B->lds_row,
                st, md, T, recs, (const tft::Item*)B->items[PH_ROW_INV]);
     if (B->n_items[PH_COL_INV_SHORT])
         launch(ctx, TFT_K_COL_INV_SHORT, c3 ? tft::k_col_inv_list<Mod, 3> : tft::k_col_inv_list<Mod, 4>,
-               dim3(B->n_items[PH_COL_INV_SHORT]), dim3(tft::kColThreads), B->lds_col, st, md, T, recs,
+               dim3(B->n_items[PH_COL_INV_SHORT]), dim3(B->col_thr), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_INV_SHORT], 0);
     if (B->n_items[PH_LAST_INV])
-        launch(ctx, TFT_K_LAST_INV, tft::k_last_inv_list<Mod>, dim3(B->n_items[PH_LAST_INV]), dim3(tft::kLastThreads),
+        launch(ctx, TFT_K_LAST_INV, tft::k_last_inv_list<Mod>, dim3(B->n_items[PH_LAST_INV]), dim3(B->row_thr),
                B->lds_row, st, md, T, recs, (const tft::Item*)B->items[PH_LAST_INV]);
     if (B->n_items[PH_COL_INV_LONG])
         launch(ctx, TFT_K_COL_INV_LONG, c3 ? tft::k_col_inv_list<Mod, 3> : tft::k_col_inv_list<Mod, 4>,
-               dim3(B->n_items[PH_COL_INV_LONG]), dim3(tft::kColThreads), B->lds_col, st, md, T, recs,
+               dim3(B->n_items[PH_COL_INV_LONG]), dim3(B->col_thr), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_INV_LONG], 1);
     if (both) {
         if (hipEventRecord(B->join, B->side) != hipSuccess || hipStreamWaitEvent(st, B->join, 0) != hipSuccess)
