@@ -261,6 +261,12 @@ uint32_t row_threads(const Plan& P) {
     return (uint32_t)std::min<uint64_t>(tft::kRowThreads, std::max<uint64_t>(64, P.W >> 3));
 }
 
+// Threads of a column-tile workgroup: one radix-8 unit per thread (M C / 8,
+// 64 .. kColThreads).
+uint32_t col_threads(const Plan& P) {
+    return (uint32_t)std::min<uint64_t>(tft::kColThreads, std::max<uint64_t>(64, ((uint64_t)P.M << P.logC) >> 3));
+}
+
 template <class Word>
 tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t n_src, const Word* Y, Word* V) {
     tft::TwoPass<Word> G;
@@ -302,9 +308,9 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
     const auto G = two_pass_of<Word>(P, X, src, n_src, nullptr, V);
     const uint32_t tiles = (uint32_t)(P.W >> P.logC);
     if (P.logC == 3)
-        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(tft::kColThreads), P.lds_col, st, md, T, G, tiles);
+        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T, G, tiles);
     else
-        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(tft::kColThreads), P.lds_col, st, md, T, G, tiles);
+        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T, G, tiles);
     launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(row_threads(P)), P.lds_row,
            st, md, T, G);
     return launch_status();
@@ -353,7 +359,7 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
                    lds_one, st, md, T, G, 0, (uint32_t)(P.W - ncols), (uint32_t)ncols);
         } else {
             const uint32_t nt = tiles_all - t0;
-            launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 0, t0, nt);
+            launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(col_threads(P)), P.lds_col, st, md, T, G, 0, t0, nt);
         }
     }
     if (P.b) {
@@ -368,7 +374,7 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
                        lds_one, st, md, T, G, 1, 0u, (uint32_t)P.b);
             } else {
                 const uint32_t nt = (uint32_t)((P.b + C - 1) / C);
-                launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(tft::kColThreads), P.lds_col, st, md, T, G, 1,
+                launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(col_threads(P)), P.lds_col, st, md, T, G, 1,
                        0u, nt);
             }
         }
@@ -596,8 +602,7 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
         B->lds_row = std::max(B->lds_row, P.lds_row);
         // one radix-8 unit per thread: rows of W words, tiles of M C words
         B->row_thr = std::max(B->row_thr, row_threads(P));
-        B->col_thr = (uint32_t)std::max<uint64_t>(
-            B->col_thr, std::min<uint64_t>(tft::kColThreads, ((uint64_t)P.M << P.logC) >> 3));
+        B->col_thr = std::max(B->col_thr, col_threads(P));
         const uint32_t tiles = (uint32_t)(P.W >> P.logC);
         const uint32_t C = 1u << P.logC;
         const int nops = products ? 2 : 1;
