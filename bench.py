@@ -328,8 +328,14 @@ def products(ctx, p, dev):
         X2 = torch.empty(r, dtype=torch.uint64, device=dev)
         tpm = event_time(lambda: libtft.poly_mul_padded(ctx, A, B, X2, Ap, Bp), 5)
         same = bool(torch.equal(X, X2))
+        X3 = torch.empty(r, dtype=torch.uint64, device=dev)
+        trm = event_time(lambda: libtft.poly_mul_restricted(ctx, A, B, X3), 3)
+        same_r = bool(torch.equal(X, X3))
         prods.append({"r": r, "poly_mul_us": round(tm * 1e3, 1), "padded_mul_us": round(tpm * 1e3, 1),
-                      "mults_per_s": round(1e3 / tm, 1), "same_as_padded": same})
+                      "restricted_mul_us": round(trm * 1e3, 1),
+                      "mults_per_s": round(1e3 / tm, 1), "same_as_padded": same, "restricted_same": same_r,
+                      "written_words": {"poly_mul": 2 * r, "restricted": r, "padded": 2 * N + r}})
+        del X3
         del Ap, Bp, X2
     return prods
 

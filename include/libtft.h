@@ -85,6 +85,18 @@ tft_status tft_pointwise_mul(tft_ctx* ctx, void* X, const void* Y, size_t n, voi
 tft_status poly_mul(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X, void* Y,
                     void* hip_stream);
 
+/* Space-restricted product (section 5, Algorithm 3; Proposition 5.1): the same
+ * C = A B with X (r = m + nb - 1 words) as the only memory written -- no
+ * workspace.  For q = 0, L_0, L_0 + L_1, ... (L the largest power of two with
+ * q + 2L <= r, at most 2 lg r blocks) A and B are folded modulo x^L - w_{q/L}
+ * into X[q, q+L) and X[q+L, q+2L), both blocks are transformed (their values
+ * are A^_{q+i} and B^_{q+i}) and multiplied into X[q, q+L); the last slot gets
+ * A(w_{r-1}) B(w_{r-1}); then the inverse TFT of length r.  Each fold reads a
+ * whole operand, so this path moves more memory than poly_mul in exchange for
+ * the r-word footprint.  Errors as for poly_mul. */
+tft_status poly_mul_restricted(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X,
+                               void* hip_stream);
+
 /* Comparator, not the method: the ordinary padded radix-2 transform
  * (section 1.1) that the TFT smooths.  With N = 2^ceil(lg n):
  * tft_padded_forward copies X[0..n) into Xpad (N caller-owned words),
@@ -241,6 +253,7 @@ typedef enum {
     TFT_K_SMALL_LIST,      /* persistent single-workgroup jobs of a batch */
     TFT_K_CRT,             /* three-prime Chinese remaindering */
     TFT_K_COL_FIX,         /* inverse: rank-one completion of the columns c < b */
+    TFT_K_FOLD,            /* space-restricted product: operand folding */
     TFT_K_COUNT
 } tft_kernel_id;
 tft_status tft_timing_enable(tft_ctx* ctx, int on);

@@ -284,13 +284,14 @@ tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t
     G.split = P.split;
     G.early = 0;
     G.Q = nullptr;
+    G.g0 = 0;
     return G;
 }
 
 // -------------------------------------------------------------- forward
 template <class Mod>
 tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_src, typename Mod::Word* X,
-                        uint64_t n, hipStream_t st) {
+                        uint64_t n, hipStream_t st, uint64_t g0 = 0) {
     using Word = typename Mod::Word;
     const Mod& md = mod_of<Mod>(ctx);
     const auto T = tables_of<Word>(ctx);
@@ -300,12 +301,14 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
         if (src != X) {
             launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3(1), dim3(kThreads), 0, st, X, n, src, n_src);
         }
-        launch(ctx, TFT_K_SMALL_FWD, tft::k_small_fwd<Mod>, dim3(1), dim3(tft::kSmallThreads), P.lds_row + (size_t)P.M * ctx->wbytes, st, md, T, X, (uint32_t)n,
-                           P.M);
+        launch(ctx, TFT_K_SMALL_FWD, tft::k_small_fwd<Mod>, dim3(1), dim3(tft::kSmallThreads),
+               P.lds_row + (size_t)P.M * ctx->wbytes, st, md, T, X, (uint32_t)n, P.M, g0);
         return launch_status();
     }
+    if (g0 && P.b) return TFT_EINVAL;   // a block at g0 != 0 is a whole power-of-two block
     Word* V = reinterpret_cast<Word*>(ctx->scratch);
-    const auto G = two_pass_of<Word>(P, X, src, n_src, nullptr, V);
+    auto G = two_pass_of<Word>(P, X, src, n_src, nullptr, V);
+    G.g0 = g0;
     const uint32_t tiles = (uint32_t)(P.W >> P.logC);
     if (P.logC == 3)
         launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T, G, tiles);
@@ -412,6 +415,79 @@ tft_status mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const
     s = forward_impl<Mod>(ctx, B, nb, Y, r, st);
     if (s != TFT_OK) return s;
     return inverse_impl<Mod>(ctx, X, Y, r, st);
+}
+
+// Space-restricted product (section 5, Algorithm 3): the output buffer is the
+// only memory written.  For q = 0, L_0, L_0 + L_1, ... with L the largest
+// power of two such that q + 2L <= r: fold A modulo x^L - w_{q/L} into
+// X[q, q+L) and transform that block (global index q/L, so X_{q+i} = A(w_{q+i})),
+// the same for B into X[q+L, q+2L), multiply pointwise into X[q, q+L).  The
+// last point r - 1 is one evaluation of each operand, then the inverse TFT of
+// length r.  At most 2 lg r blocks; each fold reads the whole operand.
+template <class Mod>
+tft_status fold_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, typename Mod::Word* out, unsigned logL,
+                     uint64_t g, hipStream_t st) {
+    using Word = typename Mod::Word;
+    const Mod& md = mod_of<Mod>(ctx);
+    const auto T = tables_of<Word>(ctx);
+    const uint64_t L = 1ull << logL;
+    const uint64_t terms = (m + L - 1) >> logL;             // largest number of t per j
+    // enough threads to fill the device, at most 2^17 partial words (scratch)
+    uint64_t K = std::max<uint64_t>(1, std::min<uint64_t>(terms, (uint64_t(1) << 17) >> logL));
+    const uint64_t chunk = (terms + K - 1) / K;
+    K = (terms + chunk - 1) / chunk;
+    Word* part = reinterpret_cast<Word*>(ctx->scratch) + kVWords;
+    Word* dst = K == 1 ? out : part;
+    const uint64_t items = K << logL;
+    launch(ctx, TFT_K_FOLD, tft::k_fold<Mod>, dim3((uint32_t)((items + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+           md, T, A, m, dst, logL, (uint32_t)K, chunk, g);
+    if (K > 1) {
+        // sums of spans of the K partials, then (if more than one span) of those
+        const uint32_t spans = (uint32_t)((K + tft::kFoldSpan - 1) / tft::kFoldSpan);
+        Word* part2 = part + (size_t(1) << 17);   // spans * L <= 128 words: K > kFoldSpan only for L < 64
+        launch(ctx, TFT_K_FOLD, tft::k_fold_sum<Mod>, dim3((uint32_t)L, spans), dim3(kThreads), 0, st, md,
+               (const Word*)part, logL, (uint32_t)K, spans == 1 ? out : part2);
+        if (spans > 1)
+            launch(ctx, TFT_K_FOLD, tft::k_fold_sum<Mod>, dim3((uint32_t)L, 1), dim3(kThreads), 0, st, md,
+                   (const Word*)part2, logL, spans, out);
+    }
+    return launch_status();
+}
+
+template <class Mod>
+tft_status mul_restricted_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const typename Mod::Word* B,
+                               uint64_t nb, typename Mod::Word* X, hipStream_t st) {
+    using Word = typename Mod::Word;
+    const Mod& md = mod_of<Mod>(ctx);
+    const uint64_t r = m + nb - 1;
+    if (r > (1ull << ctx->v)) return TFT_ERANGE;
+    tft_status s = TFT_OK;
+    uint64_t q = 0;
+    while (s == TFT_OK && q + 1 < r) {
+        const unsigned logL = (63u - (unsigned)__builtin_clzll(r - q)) - 1u;
+        const uint64_t L = 1ull << logL, g = q >> logL;
+        s = fold_impl<Mod>(ctx, A, m, X + q, logL, g, st);
+        if (s == TFT_OK) s = forward_impl<Mod>(ctx, X + q, L, X + q, L, st, g);
+        if (s == TFT_OK) s = fold_impl<Mod>(ctx, B, nb, X + q + L, logL, g, st);
+        if (s == TFT_OK) s = forward_impl<Mod>(ctx, X + q + L, L, X + q + L, L, st, g);
+        if (s == TFT_OK) {
+            const uint64_t blocks = std::min<uint64_t>(8192, (L + kThreads - 1) / kThreads);
+            launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, md,
+                   X + q, (const Word*)(X + q + L), L);
+            s = launch_status();
+        }
+        q += L;
+    }
+    if (s != TFT_OK) return s;
+    // the last point w_{r-1}: A(w_{r-1}) into X[r-1], B(w_{r-1}) into a scratch word
+    Word* tmp = reinterpret_cast<Word*>(ctx->scratch) + kVWords + 2 * size_t(tft::kQStride);
+    s = fold_impl<Mod>(ctx, A, m, X + (r - 1), 0, r - 1, st);
+    if (s == TFT_OK) s = fold_impl<Mod>(ctx, B, nb, tmp, 0, r - 1, st);
+    if (s != TFT_OK) return s;
+    launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3(1), dim3(kThreads), 0, st, md, X + (r - 1),
+           (const Word*)tmp, (uint64_t)1);
+    s = launch_status();
+    return s == TFT_OK ? inverse_impl<Mod>(ctx, X, nullptr, r, st) : s;
 }
 
 template <class Mod>
@@ -1412,6 +1488,19 @@ tft_status tft_timing_reset(tft_ctx* ctx) {
     return s;
 }
 
+tft_status poly_mul_restricted(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X, void* stream) {
+    if (!ctx || !A || !B || !X || m == 0 || nb == 0) return TFT_EINVAL;
+    tft_status s = check_len(ctx, m + nb - 1);
+    if (s != TFT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    return dispatch(ctx, [&] {
+        if (ctx->wbytes == 4)
+            return mul_restricted_impl<tft::ModU32>(ctx, (const uint32_t*)A, m, (const uint32_t*)B, nb, (uint32_t*)X,
+                                                    st);
+        return mul_restricted_impl<tft::ModGL>(ctx, (const uint64_t*)A, m, (const uint64_t*)B, nb, (uint64_t*)X, st);
+    });
+}
+
 tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen) {
     if (!ctx || n == 0) return TFT_EINVAL;
     if (n > (1ull << ctx->v)) return TFT_ERANGE;
@@ -1554,7 +1643,7 @@ tft_status tft_calibrate(tft_ctx* ctx, tft_calibration* out) {
 const char* tft_kernel_name(int id) {
     static const char* names[TFT_K_COUNT] = {"small_fwd", "small_inv", "small_mul", "col_fwd", "row_fwd",
                                              "row_inv", "col_inv_short", "last_inv", "col_inv_long",
-                                             "pointwise", "copy_pad", "small_list", "crt3", "col_fix"};
+                                             "pointwise", "copy_pad", "small_list", "crt3", "col_fix", "fold"};
     return (id >= 0 && id < TFT_K_COUNT) ? names[id] : "unknown";
 }
 

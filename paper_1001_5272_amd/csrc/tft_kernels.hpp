@@ -52,13 +52,13 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t x, uint32_t tiles) {
 // ------------------------------------------------------ single workgroup
 template <class Mod>
 __device__ void small_forward_body(const Mod& md, const Tables<typename Mod::Word>& T0, typename Mod::Word* X,
-                                   uint32_t n, uint32_t M) {
+                                   uint32_t n, uint32_t M, uint64_t g0 = 0) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
     const Tables<Word> L = local_tables(T0, buf + padded_words(M), M / 2);
     for (uint32_t i = threadIdx.x; i < M; i += nthreads()) buf[pad(i)] = i < n ? X[i] : Word(0);
     __syncthreads();
-    dif_forward(md, L, buf, 0, M, 0, n, 0);
+    dif_forward(md, L, buf, 0, M, 0, n, g0);
     for (uint32_t i = threadIdx.x; i < n; i += nthreads()) X[i] = buf[pad(i)];
 }
 
@@ -103,8 +103,8 @@ constexpr int kSmallThreads = 1024;
 
 template <class Mod>
 __global__ __launch_bounds__(kSmallThreads) void k_small_fwd(Mod md, Tables<typename Mod::Word> T,
-                                                        typename Mod::Word* X, uint32_t n, uint32_t M) {
-    small_forward_body(md, T, X, n, M);
+                                                        typename Mod::Word* X, uint32_t n, uint32_t M, uint64_t g0) {
+    small_forward_body(md, T, X, n, M, g0);
 }
 
 template <class Mod>
@@ -139,6 +139,7 @@ struct TwoPass {
     uint32_t early;   // inverse with b > 0: 0 columns c < b after the last row; 1 split mode, 2 general
                       // (columns c < b run with phase 0, see col_inv_body and last_inv_body)
     Word* Q;          // early == 2: Q_0..Q_a at Q, scratch at Q + kQStride, 1 / Q(w_a) at Q[2 kQStride]
+    uint64_t g0;      // forward of a whole block (n = a W, b = 0): the block's global index, else 0
 };
 constexpr uint32_t kQStride = (1u << 16) + 64;
 
@@ -199,7 +200,7 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
         buf[pad(it)] = (d < P.Lout && idx < P.n_src) ? P.src[idx] : Word(0);
     }
     __syncthreads();
-    dif_forward(md, T, buf, LOGC, P.M, 0, P.Lout, 0);
+    dif_forward(md, T, buf, LOGC, P.M, 0, P.Lout, P.g0);
     for (uint32_t it = threadIdx.x; it < P.Lout * C; it += nthreads()) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint64_t idx = (c0 + c) + (uint64_t)d * W;
@@ -223,7 +224,7 @@ __device__ void row_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T,
     if (j < P.a) {
         for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = row[i];
         __syncthreads();
-        dif_forward(md, T, buf, 0, W, 0, W, j);
+        dif_forward(md, T, buf, 0, W, 0, W, P.g0 * P.a + j);
         for (uint32_t i = threadIdx.x; i < W; i += nthreads()) row[i] = buf[pad(i)];
     } else {
         for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = i < P.b ? row[i] : P.V[i];
@@ -485,6 +486,68 @@ __global__ __launch_bounds__(kLastThreads) void k_last_inv(Mod md, Tables<typena
                                                            TwoPass<typename Mod::Word> P) {
     last_inv_body(md, T, P);
 }
+// The folding step of the space-restricted product (section 5, Algorithm 3):
+// out[j] = sum_t c^t A[j + t L] for j < L with c = w_g (in twiddle form), the
+// coefficients of A mod (x^L - w_g), i.e. of the block at global index g and
+// size L.  Thread (k, j) runs Horner over the k-th chunk of T consecutive t
+// and scales by c^(k T); with K chunks the K partial vectors go to part
+// (k_fold_sum adds them), with K = 1 straight to out.
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_fold(Mod md, Tables<typename Mod::Word> T, const typename Mod::Word* A,
+                                                  uint64_t m, typename Mod::Word* out, uint32_t logL, uint32_t K,
+                                                  uint64_t chunk, uint64_t g) {
+    using Word = typename Mod::Word;
+    const uint64_t idx = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= ((uint64_t)K << logL)) return;
+    const uint64_t L = 1ull << logL;
+    const uint64_t j = idx & (L - 1), k = idx >> logL;
+    const uint64_t terms = j < m ? (m - 1 - j) / L + 1 : 0;   // t with j + t L < m
+    const uint64_t t0 = k * chunk;
+    const uint64_t t1 = t0 + chunk < terms ? t0 + chunk : terms;
+    const Word c = tw_fwd(md, T, g);
+    Word acc = 0;
+    for (uint64_t t = t1; t > t0; t--) acc = md.add(md.mul_tw(acc, c), A[j + (t - 1) * L]);
+    if (t0 > 0 && t0 < t1) {
+        // c^t0 by square and multiply over the bits of t0
+        Word z = c, e = md.one_tw();
+        for (uint64_t b = t0; b; b >>= 1) {
+            if (b & 1) e = md.tw_mul_tw(e, z);
+            z = md.tw_mul_tw(z, z);
+        }
+        acc = md.mul_tw(acc, e);
+    }
+    out[idx] = acc;
+}
+// out[b L + j] = sum_{k in span b} part[k L + j], span b = [b S, (b+1) S) with
+// S = kFoldSpan: workgroup (j, b), eight independent loads per thread, then
+// lane exchanges and the workgroup.  One span per j gives the final sums.
+constexpr uint32_t kFoldSpan = 8 * kThreads;
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_fold_sum(Mod md, const typename Mod::Word* part, uint32_t logL,
+                                                      uint32_t K, typename Mod::Word* out) {
+    using Word = typename Mod::Word;
+    __shared__ Word red[kThreads / 64];
+    const uint64_t j = blockIdx.x;
+    const uint32_t k0 = blockIdx.y * kFoldSpan;
+    Word v[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const uint32_t k = k0 + threadIdx.x + i * kThreads;
+        v[i] = k < K ? part[((uint64_t)k << logL) + j] : Word(0);
+    }
+    Word s = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) s = md.add(s, v[i]);
+    for (int o = 1; o < 64; o <<= 1) s = md.add(s, shfl_xor_word(s, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Word t = 0;
+        for (int w = 0; w < kThreads / 64; w++) t = md.add(t, red[w]);
+        out[((uint64_t)blockIdx.y << logL) + j] = t;
+    }
+}
+
 // X[i] = i mod p (canonical residues for timing runs).
 template <class Word>
 __global__ __launch_bounds__(kThreads) void k_fill_index(Word* X, uint64_t n, uint64_t p) {

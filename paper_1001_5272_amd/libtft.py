@@ -46,6 +46,7 @@ SIGNATURES = {
     "tft_inverse": (_st, [_vp, _vp, _sz, _vp]),
     "tft_pointwise_mul": (_st, [_vp, _vp, _vp, _sz, _vp]),
     "poly_mul": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp, _vp]),
+    "poly_mul_restricted": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp]),
     "tft_padded_forward": (_st, [_vp, _vp, _sz, _vp, _vp]),
     "tft_padded_inverse": (_st, [_vp, _vp, _sz, _vp, _vp]),
     "poly_mul_padded": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp, _vp, _vp]),
@@ -79,7 +80,7 @@ SIGNATURES = {
 }
 
 KERNEL_NAMES = ["small_fwd", "small_inv", "small_mul", "col_fwd", "row_fwd", "row_inv", "col_inv_short",
-                "last_inv", "col_inv_long", "pointwise", "copy_pad", "small_list", "crt3", "col_fix"]
+                "last_inv", "col_inv_long", "pointwise", "copy_pad", "small_list", "crt3", "col_fix", "fold"]
 
 
 class TftError(RuntimeError):
@@ -200,6 +201,14 @@ def poly_mul(ctx: Context, A, B, X, Y=None, stream=None):
     y = ctx._t(Y, "Y") if Y is not None else _vp(0)
     _check(load().poly_mul(ctx.handle, ctx._t(A, "A"), A.numel(), ctx._t(B, "B"), B.numel(), ctx._t(X, "X"), y,
                            _stream(stream)), "poly_mul")
+    return X
+
+
+def poly_mul_restricted(ctx: Context, A, B, X, stream=None):
+    """Space-restricted product (Algorithm 3): X (len(A) + len(B) - 1 words) is
+    the only memory written."""
+    _check(load().poly_mul_restricted(ctx.handle, ctx._t(A, "A"), A.numel(), ctx._t(B, "B"), B.numel(),
+                                      ctx._t(X, "X"), _stream(stream)), "poly_mul_restricted")
     return X
 
 

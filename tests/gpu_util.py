@@ -37,3 +37,11 @@ def gpu_mul(ctx, A, B):
     Y = torch.empty(r, dtype=ctx.dtype, device=dA.device)
     libtft.poly_mul(ctx, dA, dB, X, Y)
     return to_host(X)
+
+
+def gpu_mul_restricted(ctx, A, B):
+    r = len(A) + len(B) - 1
+    dA, dB = to_dev(ctx, A), to_dev(ctx, B)
+    X = torch.full((r,), 7, dtype=ctx.dtype, device=dA.device)   # garbage: the product overwrites every word
+    libtft.poly_mul_restricted(ctx, dA, dB, X)
+    return to_host(X)

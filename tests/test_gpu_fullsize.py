@@ -68,6 +68,10 @@ def test_products_at_full_size(ctxgl, r):
     for _ in range(2):
         z = rng.randrange(p)
         assert oracle.evaluate(p, C, z) == oracle.evaluate(p, A, z) * oracle.evaluate(p, B, z) % p
+    # the space-restricted product (output buffer only) gives the same words
+    X2 = torch.full((r,), 5, dtype=torch.uint64, device="cuda")
+    libtft.poly_mul_restricted(ctxgl, dA, dB, X2)
+    assert torch.equal(X2, X)
 
 
 def test_batch_4096_sampled():

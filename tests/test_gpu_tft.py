@@ -7,7 +7,7 @@ import pytest
 import oracle
 import synth
 from conftest import PRIMES
-from gpu_util import gpu_forward, gpu_inverse, gpu_mul
+from gpu_util import gpu_mul_restricted, gpu_forward, gpu_inverse, gpu_mul
 
 pytestmark = pytest.mark.gpu
 
@@ -118,6 +118,22 @@ def test_products(ctxs, name):
         C = gpu_mul(ctx, A, B)
         ref = oracle.mul_schoolbook(p, A, B) if m * nb <= 4_000_000 else oracle.mul_padded(p, g, A, B)
         assert (C == ref).all(), f"product {m}x{nb} mismatches at {np.nonzero(C != ref)[0][:5]}"
+
+
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+def test_restricted_products(ctxs, name):
+    # section 5's space-restricted product (Algorithm 3): X is the only memory
+    # written; blocks at global index q/L include two-pass ones with q > 0
+    p, g = PRIMES[name]
+    ctx = ctxs[name]
+    for m, nb in [(1, 1), (1, 2), (2, 2), (1, 7), (5, 1), (3, 4), (17, 16), (1000, 1500), (4096, 4097),
+                  (5000, 3000), (30000, 40001), (65536, 1), (12345, 98765)]:
+        print(f"[gpu] {name} restricted product {m}x{nb}", flush=True)
+        A = synth.residues(p, m, 300 + m)
+        B = synth.residues(p, nb, 400 + nb)
+        C = gpu_mul_restricted(ctx, A, B)
+        ref = oracle.mul_schoolbook(p, A, B) if m * nb <= 4_000_000 else oracle.mul_padded(p, g, A, B)
+        assert (C == ref).all(), f"restricted product {m}x{nb} mismatches at {np.nonzero(C != ref)[0][:5]}"
 
 
 def test_rejects_bad_arguments(ctxs):
