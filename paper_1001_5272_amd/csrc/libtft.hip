@@ -291,7 +291,7 @@ tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t
 // -------------------------------------------------------------- forward
 template <class Mod>
 tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_src, typename Mod::Word* X,
-                        uint64_t n, hipStream_t st, uint64_t g0 = 0) {
+                        uint64_t n, hipStream_t st, uint64_t g0 = 0, uint32_t copies = 1) {
     using Word = typename Mod::Word;
     const Mod& md = mod_of<Mod>(ctx);
     const auto T = tables_of<Word>(ctx);
@@ -301,8 +301,8 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
         if (src != X) {
             launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3(1), dim3(kThreads), 0, st, X, n, src, n_src);
         }
-        launch(ctx, TFT_K_SMALL_FWD, tft::k_small_fwd<Mod>, dim3(1), dim3(tft::kSmallThreads),
-               P.lds_row + (size_t)P.M * ctx->wbytes, st, md, T, X, (uint32_t)n, P.M, g0);
+        launch(ctx, TFT_K_SMALL_FWD, tft::k_small_fwd<Mod>, dim3(copies), dim3(tft::kSmallThreads),
+               P.lds_row + (size_t)P.M * ctx->wbytes, st, md, T, X, (uint32_t)n, P.M, g0, (uint64_t)n);
         return launch_status();
     }
     if (g0 && P.b) return TFT_EINVAL;   // a block at g0 != 0 is a whole power-of-two block
@@ -425,31 +425,49 @@ tft_status mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const
 // last point r - 1 is one evaluation of each operand, then the inverse TFT of
 // length r.  At most 2 lg r blocks; each fold reads the whole operand.
 template <class Mod>
-tft_status fold_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, typename Mod::Word* out, unsigned logL,
-                     uint64_t g, hipStream_t st) {
+tft_status fold_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, typename Mod::Word* outA,
+                     const typename Mod::Word* B, uint64_t nb, typename Mod::Word* outB, unsigned logL, uint64_t g,
+                     hipStream_t st) {
     using Word = typename Mod::Word;
     const Mod& md = mod_of<Mod>(ctx);
     const auto T = tables_of<Word>(ctx);
     const uint64_t L = 1ull << logL;
-    const uint64_t terms = (m + L - 1) >> logL;             // largest number of t per j
-    // enough threads to fill the device, at most 2^17 partial words (scratch)
-    uint64_t K = std::max<uint64_t>(1, std::min<uint64_t>(terms, (uint64_t(1) << 17) >> logL));
+    const uint64_t terms = (std::max(m, nb) + L - 1) >> logL;   // largest number of t per j
+    // enough threads to fill the device, at most 2^16 partial words per operand
+    uint64_t K = std::max<uint64_t>(1, std::min<uint64_t>(terms, (uint64_t(1) << 16) >> logL));
     const uint64_t chunk = (terms + K - 1) / K;
     K = (terms + chunk - 1) / chunk;
-    Word* part = reinterpret_cast<Word*>(ctx->scratch) + kVWords;
-    Word* dst = K == 1 ? out : part;
+    Word* part = reinterpret_cast<Word*>(ctx->scratch) + kVWords;   // two areas of 2^16 words
+    tft::FoldArgs<Word> F;
+    F.A[0] = A;
+    F.A[1] = B;
+    F.m[0] = m;
+    F.m[1] = nb;
+    F.out[0] = K == 1 ? outA : part;
+    F.out[1] = K == 1 ? outB : part + (size_t(1) << 16);
     const uint64_t items = K << logL;
-    launch(ctx, TFT_K_FOLD, tft::k_fold<Mod>, dim3((uint32_t)((items + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
-           md, T, A, m, dst, logL, (uint32_t)K, chunk, g);
+    launch(ctx, TFT_K_FOLD, tft::k_fold<Mod>, dim3((uint32_t)((items + kThreads - 1) / kThreads), 2), dim3(kThreads), 0,
+           st, md, T, F, logL, (uint32_t)K, chunk, g);
     if (K > 1) {
         // sums of spans of the K partials, then (if more than one span) of those
         const uint32_t spans = (uint32_t)((K + tft::kFoldSpan - 1) / tft::kFoldSpan);
-        Word* part2 = part + (size_t(1) << 17);   // spans * L <= 128 words: K > kFoldSpan only for L < 64
-        launch(ctx, TFT_K_FOLD, tft::k_fold_sum<Mod>, dim3((uint32_t)L, spans), dim3(kThreads), 0, st, md,
-               (const Word*)part, logL, (uint32_t)K, spans == 1 ? out : part2);
-        if (spans > 1)
-            launch(ctx, TFT_K_FOLD, tft::k_fold_sum<Mod>, dim3((uint32_t)L, 1), dim3(kThreads), 0, st, md,
-                   (const Word*)part2, logL, spans, out);
+        Word* part2 = part + (size_t(1) << 17);   // 2 x spans * L <= 128 words: K > kFoldSpan only for L < 32
+        tft::SumArgs<Word> S1;
+        S1.part[0] = part;
+        S1.part[1] = part + (size_t(1) << 16);
+        S1.out[0] = spans == 1 ? outA : part2;
+        S1.out[1] = spans == 1 ? outB : part2 + 64;
+        launch(ctx, TFT_K_FOLD, tft::k_fold_sum<Mod>, dim3((uint32_t)L, spans, 2), dim3(kThreads), 0, st, md, S1, logL,
+               (uint32_t)K);
+        if (spans > 1) {
+            tft::SumArgs<Word> S2;
+            S2.part[0] = part2;
+            S2.part[1] = part2 + 64;
+            S2.out[0] = outA;
+            S2.out[1] = outB;
+            launch(ctx, TFT_K_FOLD, tft::k_fold_sum<Mod>, dim3((uint32_t)L, 1, 2), dim3(kThreads), 0, st, md, S2, logL,
+                   spans);
+        }
     }
     return launch_status();
 }
@@ -466,10 +484,13 @@ tft_status mul_restricted_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64
     while (s == TFT_OK && q + 1 < r) {
         const unsigned logL = (63u - (unsigned)__builtin_clzll(r - q)) - 1u;
         const uint64_t L = 1ull << logL, g = q >> logL;
-        s = fold_impl<Mod>(ctx, A, m, X + q, logL, g, st);
-        if (s == TFT_OK) s = forward_impl<Mod>(ctx, X + q, L, X + q, L, st, g);
-        if (s == TFT_OK) s = fold_impl<Mod>(ctx, B, nb, X + q + L, logL, g, st);
-        if (s == TFT_OK) s = forward_impl<Mod>(ctx, X + q + L, L, X + q + L, L, st, g);
+        s = fold_impl<Mod>(ctx, A, m, X + q, B, nb, X + q + L, logL, g, st);
+        if (s == TFT_OK && make_plan(ctx, L).kind == 0) {
+            s = forward_impl<Mod>(ctx, X + q, L, X + q, L, st, g, 2);   // both blocks in one launch
+        } else if (s == TFT_OK) {
+            s = forward_impl<Mod>(ctx, X + q, L, X + q, L, st, g);
+            if (s == TFT_OK) s = forward_impl<Mod>(ctx, X + q + L, L, X + q + L, L, st, g);
+        }
         if (s == TFT_OK) {
             const uint64_t blocks = std::min<uint64_t>(8192, (L + kThreads - 1) / kThreads);
             launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, md,
@@ -481,8 +502,7 @@ tft_status mul_restricted_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64
     if (s != TFT_OK) return s;
     // the last point w_{r-1}: A(w_{r-1}) into X[r-1], B(w_{r-1}) into a scratch word
     Word* tmp = reinterpret_cast<Word*>(ctx->scratch) + kVWords + 2 * size_t(tft::kQStride);
-    s = fold_impl<Mod>(ctx, A, m, X + (r - 1), 0, r - 1, st);
-    if (s == TFT_OK) s = fold_impl<Mod>(ctx, B, nb, tmp, 0, r - 1, st);
+    s = fold_impl<Mod>(ctx, A, m, X + (r - 1), B, nb, tmp, 0, r - 1, st);
     if (s != TFT_OK) return s;
     launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3(1), dim3(kThreads), 0, st, md, X + (r - 1),
            (const Word*)tmp, (uint64_t)1);

@@ -103,8 +103,10 @@ constexpr int kSmallThreads = 1024;
 
 template <class Mod>
 __global__ __launch_bounds__(kSmallThreads) void k_small_fwd(Mod md, Tables<typename Mod::Word> T,
-                                                        typename Mod::Word* X, uint32_t n, uint32_t M, uint64_t g0) {
-    small_forward_body(md, T, X, n, M, g0);
+                                                        typename Mod::Word* X, uint32_t n, uint32_t M, uint64_t g0,
+                                                        uint64_t stride) {
+    // workgroup b transforms X + b stride (several blocks of one length)
+    small_forward_body(md, T, X + blockIdx.x * stride, n, M, g0);
 }
 
 template <class Mod>
@@ -491,14 +493,23 @@ __global__ __launch_bounds__(kLastThreads) void k_last_inv(Mod md, Tables<typena
 // coefficients of A mod (x^L - w_g), i.e. of the block at global index g and
 // size L.  Thread (k, j) runs Horner over the k-th chunk of T consecutive t
 // and scales by c^(k T); with K chunks the K partial vectors go to part
-// (k_fold_sum adds them), with K = 1 straight to out.
+// (k_fold_sum adds them), with K = 1 straight to out.  blockIdx.y selects the
+// operand (both operands of a block in one launch).
+template <class Word>
+struct FoldArgs {
+    const Word* A[2];
+    uint64_t m[2];
+    Word* out[2];   // K == 1: the block; else the partial area of the operand
+};
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_fold(Mod md, Tables<typename Mod::Word> T, const typename Mod::Word* A,
-                                                  uint64_t m, typename Mod::Word* out, uint32_t logL, uint32_t K,
+__global__ __launch_bounds__(kThreads) void k_fold(Mod md, Tables<typename Mod::Word> T,
+                                                  FoldArgs<typename Mod::Word> F, uint32_t logL, uint32_t K,
                                                   uint64_t chunk, uint64_t g) {
     using Word = typename Mod::Word;
     const uint64_t idx = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= ((uint64_t)K << logL)) return;
+    const Word* A = F.A[blockIdx.y];
+    const uint64_t m = F.m[blockIdx.y];
     const uint64_t L = 1ull << logL;
     const uint64_t j = idx & (L - 1), k = idx >> logL;
     const uint64_t terms = j < m ? (m - 1 - j) / L + 1 : 0;   // t with j + t L < m
@@ -516,17 +527,25 @@ __global__ __launch_bounds__(kThreads) void k_fold(Mod md, Tables<typename Mod::
         }
         acc = md.mul_tw(acc, e);
     }
-    out[idx] = acc;
+    F.out[blockIdx.y][idx] = acc;
 }
+
 // out[b L + j] = sum_{k in span b} part[k L + j], span b = [b S, (b+1) S) with
-// S = kFoldSpan: workgroup (j, b), eight independent loads per thread, then
-// lane exchanges and the workgroup.  One span per j gives the final sums.
+// S = kFoldSpan: workgroup (j, b, operand), eight independent loads per
+// thread, then lane exchanges and the workgroup.  One span per j gives the
+// final sums.
 constexpr uint32_t kFoldSpan = 8 * kThreads;
+template <class Word>
+struct SumArgs {
+    const Word* part[2];
+    Word* out[2];
+};
 template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_fold_sum(Mod md, const typename Mod::Word* part, uint32_t logL,
-                                                      uint32_t K, typename Mod::Word* out) {
+__global__ __launch_bounds__(kThreads) void k_fold_sum(Mod md, SumArgs<typename Mod::Word> S, uint32_t logL,
+                                                      uint32_t K) {
     using Word = typename Mod::Word;
     __shared__ Word red[kThreads / 64];
+    const Word* part = S.part[blockIdx.z];
     const uint64_t j = blockIdx.x;
     const uint32_t k0 = blockIdx.y * kFoldSpan;
     Word v[8];
@@ -544,7 +563,7 @@ __global__ __launch_bounds__(kThreads) void k_fold_sum(Mod md, const typename Mo
     if (threadIdx.x == 0) {
         Word t = 0;
         for (int w = 0; w < kThreads / 64; w++) t = md.add(t, red[w]);
-        out[((uint64_t)blockIdx.y << logL) + j] = t;
+        S.out[blockIdx.z][((uint64_t)blockIdx.y << logL) + j] = t;
     }
 }
 
