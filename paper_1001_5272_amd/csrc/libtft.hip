@@ -1545,7 +1545,10 @@ tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen) {
                 tft::k_fill_index<uint32_t><<<1024, kThreads>>>((uint32_t*)X, n, ctx->p);
             if (hipGetLastError() != hipSuccess) st = TFT_EDEVICE;
         }
-        float best_ms = 0.f;
+        // median of five timed round trips per candidate (after one warm-up);
+        // another width replaces the planner's only when 3 % faster, so that
+        // run-to-run noise does not move the plan
+        float base_ms = 0.f, best_ms = 0.f;
         const int lo = std::max<int>((int)base.logW - 2, (int)base.logC), hi = std::min<int>((int)base.logW + 2, 16);
         for (int lw = lo; lw <= hi && st == TFT_OK; lw++) {
             if ((1ull << lw) >= n) break;
@@ -1556,8 +1559,9 @@ tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen) {
                 tft_status b = tft_inverse(ctx, X, n, nullptr);
                 return a != TFT_OK ? a : b;
             };
-            float ms_min = 0.f;
-            for (int rep = 0; rep < 4 && st == TFT_OK; rep++) {
+            float t[6];
+            for (int rep = 0; rep < 6 && st == TFT_OK; rep++) {
+                t[rep] = 0.f;
                 if (hipEventRecord(e0, nullptr) != hipSuccess) { st = TFT_EDEVICE; break; }
                 const tft_status r = round_trip();
                 if (r != TFT_OK) { st = r; break; }
@@ -1565,15 +1569,18 @@ tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen) {
                     st = TFT_EDEVICE;
                     break;
                 }
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (rep > 0 && (ms_min == 0.f || ms < ms_min)) ms_min = ms;   // first run warms up
+                (void)hipEventElapsedTime(&t[rep], e0, e1);
             }
-            if (st == TFT_OK && ms_min > 0.f && (best == 0 || ms_min < best_ms)) {
+            if (st != TFT_OK) break;
+            std::sort(t + 1, t + 6);   // t[0] is the warm-up
+            const float ms = t[3];
+            if ((unsigned)lw == base.logW) base_ms = ms;
+            if (best == 0 || ms < best_ms) {
                 best = (unsigned)lw;
-                best_ms = ms_min;
+                best_ms = ms;
             }
         }
+        if (st == TFT_OK && best != base.logW && base_ms > 0.f && best_ms > 0.97f * base_ms) best = base.logW;
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         if (X) (void)hipFree(X);
