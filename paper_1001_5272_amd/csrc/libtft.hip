@@ -285,6 +285,7 @@ tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t
     G.early = 0;
     G.Q = nullptr;
     G.g0 = 0;
+    G.nparts = 0;
     return G;
 }
 
@@ -362,6 +363,7 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
                    lds_one, st, md, T, G, 0, (uint32_t)(P.W - ncols), (uint32_t)ncols);
         } else {
             const uint32_t nt = tiles_all - t0;
+            if (P.b == 1 && t0 == 0) G.nparts = nt;   // every tile leaves its share of the last-row sum
             launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(col_threads(P)), P.lds_col, st, md, T, G, 0, t0, nt);
         }
     }

@@ -298,9 +298,21 @@ __device__ __forceinline__ Word shfl_xor_word(Word v, int mask) {
 // values are summed across each wavefront by lane exchanges (threads of one
 // lane sit C apart), then across wavefronts.  red is LDS scratch of
 // (nthreads() / 64) C words, res of C words; C <= 64.
+// The scale factors z^(t chunk) of eval_lanes for the threads t < nthreads() /
+// C of a lane, into zp (LDS, written by those threads; the caller's next
+// barrier publishes them).  Called early, their power chains overlap the
+// caller's loads instead of lengthening the evaluation.
+template <class Mod>
+__device__ __forceinline__ void eval_scales(const Mod& md, int logC, uint32_t len, typename Mod::Word z,
+                                            typename Mod::Word* zp) {
+    const uint32_t tpc = nthreads() >> logC;
+    const uint32_t chunk = (len + tpc - 1) / tpc;
+    if (threadIdx.x < tpc) zp[threadIdx.x] = pow_tw(md, z, threadIdx.x * chunk);
+}
+
 template <class Mod>
 __device__ void eval_lanes(const Mod& md, const typename Mod::Word* buf, int logC, uint32_t len, typename Mod::Word z,
-                           typename Mod::Word* red, typename Mod::Word* res) {
+                           typename Mod::Word* red, typename Mod::Word* res, const typename Mod::Word* zp = nullptr) {
     using Word = typename Mod::Word;
     const uint32_t C = 1u << logC;
     const uint32_t tpc = nthreads() >> logC;
@@ -310,7 +322,7 @@ __device__ void eval_lanes(const Mod& md, const typename Mod::Word* buf, int log
     const uint32_t hi = lo + chunk < len ? lo + chunk : len;
     Word acc = 0;
     for (uint32_t d = hi; d > lo; d--) acc = md.add(md.mul_tw(acc, z), buf[pad((d - 1) * C + c)]);
-    if (lo > 0 && lo < hi) acc = md.mul_tw(acc, pow_tw(md, z, lo));
+    if (lo > 0 && lo < hi) acc = md.mul_tw(acc, zp ? zp[t] : pow_tw(md, z, lo));
     for (uint32_t o = C; o < 64; o <<= 1) acc = md.add(acc, shfl_xor_word(acc, (int)o));
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane < C) red[wave * C + lane] = acc;

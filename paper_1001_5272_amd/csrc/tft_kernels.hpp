@@ -142,6 +142,7 @@ struct TwoPass {
                       // (columns c < b run with phase 0, see col_inv_body and last_inv_body)
     Word* Q;          // early == 2: Q_0..Q_a at Q, scratch at Q + kQStride, 1 / Q(w_a) at Q[2 kQStride]
     uint64_t g0;      // forward of a whole block (n = a W, b = 0): the block's global index, else 0
+    uint32_t nparts;  // inverse with b = 1: column tiles leaving a partial last-row sum at Q + kQStride, or 0
 };
 constexpr uint32_t kQStride = (1u << 16) + 64;
 
@@ -170,10 +171,12 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
         // H is P_c(w_H) = (lo - hi)(w_H) = (lo + hi)(w_H) - 2 x_H, one
         // evaluation of the folded block taken before its transform.
         const uint32_t H = P.M;
+        __shared__ Word zp[kColThreads >> LOGC];   // one power per thread of a lane
         for (uint32_t c = threadIdx.x; c < C; c += nthreads()) {
             const uint64_t idx = (c0 + c) + (uint64_t)H * W;
             hi0[c] = idx < P.n_src ? P.src[idx] : Word(0);
         }
+        eval_scales(md, LOGC, H, tw_fwd(md, T, H), zp);
         __syncthreads();
         for (uint32_t it = threadIdx.x; it < H * C; it += nthreads()) {
             const uint32_t c = it & (C - 1), d = it >> LOGC;
@@ -183,7 +186,7 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
             buf[pad(it)] = v;
         }
         __syncthreads();
-        eval_lanes(md, buf, LOGC, H, tw_fwd(md, T, H), red, extra);
+        eval_lanes(md, buf, LOGC, H, tw_fwd(md, T, H), red, extra, zp);
         dif_forward(md, T, buf, LOGC, H, 0, H, 0);
         for (uint32_t it = threadIdx.x; it < (H + 1) * C; it += nthreads()) {
             const uint32_t c = it & (C - 1), d = it >> LOGC;
@@ -304,6 +307,12 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
     // general, k_col_fix) finishes the columns c < b
     const bool every = P.early && phase == 0;
     auto mine_col = [&](uint32_t col) { return every || (phase ? (col < P.b) : (col >= P.b)); };
+    // powers for the evaluations at the end, computed first (few waves, and
+    // nothing else is live yet); the next barrier publishes them
+    __shared__ Word ypow[C], zp[kColThreads >> LOGC];   // zp: one power per thread of a lane
+    if (phase == 0 && P.b == 1 && P.nparts && threadIdx.x < C)   // w_{aW}^c
+        ypow[threadIdx.x] = pow_tw(md, tw_fwd(md, T, (uint64_t)P.a << P.logW), c0 + threadIdx.x);
+    if (phase == 0 && P.b) eval_scales(md, LOGC, P.a, tw_fwd(md, T, P.a), zp);
     for (uint32_t it = threadIdx.x; it < Mb * C; it += nthreads()) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint32_t col = c0 + c;
@@ -340,9 +349,23 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
     if (phase == 0 && P.b) {
         // the extra value V_c = P_c(w_a) of the restored column (early mode:
         // for c < b the same evaluation gives C0(w_H), H = a)
-        eval_lanes(md, buf, LOGC, P.a, tw_fwd(md, T, P.a), red, extra);
+        eval_lanes(md, buf, LOGC, P.a, tw_fwd(md, T, P.a), red, extra, zp);
         for (uint32_t c = threadIdx.x; c < C; c += nthreads())
             if (mine_col(c0 + c)) P.V[c0 + c] = extra[c];
+        if (P.nparts) {
+            // b = 1: this tile's share sum_{c >= 1} V_c w_{aW}^c of the last-row
+            // evaluation (last_inv_body adds the tiles' shares)
+            if (threadIdx.x < C) {
+                const uint32_t c = c0 + threadIdx.x;
+                last[threadIdx.x] = c >= 1 ? md.mul_tw(extra[threadIdx.x], ypow[threadIdx.x]) : Word(0);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                Word sum = 0;
+                for (uint32_t c = 0; c < C; c++) sum = md.add(sum, last[c]);
+                P.Q[kQStride + tile] = sum;
+            }
+        }
     }
 }
 
@@ -363,7 +386,20 @@ __device__ void last_inv_body(const Mod& md, const Tables<typename Mod::Word>& T
     Word* buf = lds_buf<Word>();
     const uint32_t W = 1u << P.logW;
     Word* row = P.X + (uint64_t)P.a * W;
-    if (P.b == 1) {
+    if (P.b == 1 && P.nparts) {
+        // the column tiles left their shares of sum_{c >= 1} V_c w_{aW}^c
+        Word s = 0;
+        for (uint32_t i = threadIdx.x; i < P.nparts; i += nthreads()) s = md.add(s, P.Q[kQStride + i]);
+        for (int o = 1; o < 64; o <<= 1) s = md.add(s, shfl_xor_word(s, o));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            Word t = 0;
+            for (uint32_t w = 0; w < (nthreads() >> 6); w++) t = md.add(t, red[w]);
+            buf[pad(0)] = md.sub(row[0], t);
+        }
+        __syncthreads();
+    } else if (P.b == 1) {
         for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = i == 0 ? Word(0) : P.V[i];
         __syncthreads();
         eval_lanes(md, buf, 0, W, tw_fwd(md, T, (uint64_t)P.a * W), red, val);
