@@ -311,11 +311,15 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
     auto G = two_pass_of<Word>(P, X, src, n_src, nullptr, V);
     G.g0 = g0;
     const uint32_t tiles = (uint32_t)(P.W >> P.logC);
+    // b = 1: the column tiles leave shares of the last row's one output
+    // (scratch after V), and the row pass needs no workgroup for that row
+    G.Q = V + kVWords;
+    if (P.b == 1) G.nparts = tiles;
     if (P.logC == 3)
         launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T, G, tiles);
     else
         launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T, G, tiles);
-    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b ? 1 : 0))), dim3(row_threads(P)), P.lds_row,
+    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b > 1 ? 1 : 0))), dim3(row_threads(P)), P.lds_row,
            st, md, T, G);
     return launch_status();
 }

@@ -164,6 +164,19 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
     const Tables<Word> T = local_tables(T0, buf + padded_words(P.M << LOGC), P.M / 2);
     const uint32_t c0 = tile * C;
     const uint64_t W = 1ull << P.logW;
+    // b = 1 (P.nparts): the tile's share sum_c Z_c w_{aW}^c of the last row's
+    // one output, Z_c = P_c(w_a) being output a of column c (slot or V_c)
+    __shared__ Word ypow[C], zterm[C];
+    const bool share = P.b == 1 && P.nparts;
+    if (share && threadIdx.x < C) ypow[threadIdx.x] = pow_tw(md, tw_fwd(md, T, (uint64_t)P.a << P.logW), c0 + threadIdx.x);
+    auto put_share = [&]() {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            Word sum = 0;
+            for (uint32_t c = 0; c < C; c++) sum = md.add(sum, zterm[c]);
+            P.Q[kQStride + tile] = sum;
+        }
+    };
     if (P.split) {
         // Lout = H + 1 with H = P.M a power of two, and every column has at
         // most H + 1 coefficients.  Outputs s < H are the H-point transform of
@@ -196,7 +209,9 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
                 P.X[idx] = v;
             else if (P.b && d == P.a)
                 P.V[c0 + c] = v;
+            if (share && d == H) zterm[c] = md.mul_tw(v, ypow[c]);
         }
+        if (share) put_share();
         return;
     }
     for (uint32_t it = threadIdx.x; it < P.M * C; it += nthreads()) {
@@ -213,7 +228,9 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
             P.X[idx] = buf[pad(it)];
         else if (P.b && d == P.a)
             P.V[c0 + c] = buf[pad(it)];
+        if (share && d == P.a) zterm[c] = md.mul_tw(buf[pad(it)], ypow[c]);
     }
+    if (share) put_share();
 }
 
 // Forward row pass: row j < a is transformed in full (global block index j at
@@ -493,6 +510,26 @@ __global__ __launch_bounds__(kColThreads) void k_col_fwd(Mod md, Tables<typename
 template <class Mod>
 __global__ __launch_bounds__(kRowThreads) void k_row_fwd(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P) {
+    using Word = typename Mod::Word;
+    if (P.b == 1 && P.nparts) {
+        // one output in the last row: the sum of the column tiles' shares,
+        // added by workgroup 0 before its own row (no workgroup of its own)
+        if (blockIdx.x == 0) {
+            __shared__ Word red[kRowThreads / 64];
+            Word s = 0;
+            for (uint32_t i = threadIdx.x; i < P.nparts; i += nthreads()) s = md.add(s, P.Q[kQStride + i]);
+            for (int o = 1; o < 64; o <<= 1) s = md.add(s, shfl_xor_word(s, o));
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                Word t = 0;
+                for (uint32_t w = 0; w < (nthreads() >> 6); w++) t = md.add(t, red[w]);
+                P.X[(uint64_t)P.a << P.logW] = t;
+            }
+        }
+        row_fwd_body(md, T, P, blockIdx.x);
+        return;
+    }
     // the partial last row (item a) goes first: dispatched last, it would run
     // alone after the full rows whenever they fill every slot of the device
     const uint32_t k = P.b ? (blockIdx.x == 0 ? P.a : blockIdx.x - 1) : blockIdx.x;
