@@ -216,7 +216,9 @@ struct Unit {
             }
         }
     }
-    // inverse: (a, b) -> ((a + b)/2, (a - b) w^-1 / 2), stages s = S-1 .. 0
+    // inverse: (a, b) -> ((a + b)/2, (a - b) w^-1 / 2), stages s = S-1 .. 0;
+    // HALF = false leaves out the halvings (the caller scales by 2^-stages)
+    template <bool HALF = true>
     __device__ __forceinline__ void inverse(const Mod& md, Word (&x)[R]) const {
 #pragma unroll
         for (int s = S - 1; s >= 0; s--) {
@@ -228,8 +230,13 @@ struct Unit {
                 for (int t = 0; t < dist; t++) {
                     const int a = q * 2 * dist + t, b = a + dist;
                     const Word u = x[a], v = x[b];
-                    x[a] = md.half(md.add(u, v));
-                    x[b] = md.mul_tw(md.half(md.sub(u, v)), w);
+                    if (HALF) {
+                        x[a] = md.half(md.add(u, v));
+                        x[b] = md.mul_tw(md.half(md.sub(u, v)), w);
+                    } else {
+                        x[a] = md.add(u, v);
+                        x[b] = md.mul_tw(md.sub(u, v), w);
+                    }
                 }
             }
         }
@@ -365,7 +372,7 @@ __device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, 
 
 // One group of S inverse stages ending at half-size h (stages h/2^(S-1) .. h)
 // over every block of size 2h inside [off, off + Sz).
-template <class Mod, int S, bool SYNC = true>
+template <class Mod, int S, bool SYNC = true, bool HALF = true>
 __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
                                           int logC, uint32_t off, uint32_t Sz, uint32_t h, uint64_t g) {
     using Word = typename Mod::Word;
@@ -387,7 +394,7 @@ __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename M
 #pragma unroll
         for (int t = 0; t < R; t++) x[t] = buf[pad((base + t * q) * C + c)];
         un.load_inv(md, T, gbase + i);
-        un.inverse(md, x);
+        un.template inverse<HALF>(md, x);
 #pragma unroll
         for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
     }
@@ -395,8 +402,9 @@ __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename M
 }
 
 // Full inverse of the forward stages on the block of size Sz at offset off with
-// global block index g: stages 1, 2, ..., Sz/2.
-template <class Mod>
+// global block index g: stages 1, 2, ..., Sz/2.  HALF = false leaves every
+// value multiplied by Sz (the caller scales by 1/Sz, e.g. on its store).
+template <class Mod, bool HALF = true>
 __device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                              uint32_t off, uint32_t Sz, uint64_t g) {
     if (Sz < 2) return;
@@ -405,11 +413,19 @@ __device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T,
     for (int done = 0; done < L;) {      // stages 2^0 .. 2^(done-1) finished
         const int S = group_stages(words, L - done);
         const uint32_t h = 1u << (done + S - 1);
-        if (S == 3) dit_group<Mod, 3>(md, T, buf, logC, off, Sz, h, g);
-        else if (S == 2) dit_group<Mod, 2>(md, T, buf, logC, off, Sz, h, g);
-        else dit_group<Mod, 1>(md, T, buf, logC, off, Sz, h, g);
+        if (S == 3) dit_group<Mod, 3, true, HALF>(md, T, buf, logC, off, Sz, h, g);
+        else if (S == 2) dit_group<Mod, 2, true, HALF>(md, T, buf, logC, off, Sz, h, g);
+        else dit_group<Mod, 1, true, HALF>(md, T, buf, logC, off, Sz, h, g);
         done += S;
     }
+}
+
+// 2^-L in twiddle form.
+template <class Mod>
+__device__ __forceinline__ typename Mod::Word inv_pow2_tw(const Mod& md, int L) {
+    typename Mod::Word s = md.one_tw();
+    for (int i = 0; i < L; i++) s = md.half(s);   // halving commutes with the twiddle form's constant factor
+    return s;
 }
 
 // Generalised inverse truncated transform of one block.

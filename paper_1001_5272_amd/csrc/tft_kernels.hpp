@@ -288,8 +288,15 @@ __device__ void row_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
         for (uint32_t i = threadIdx.x; i < len; i += nthreads()) buf[pad(i)] = row[i];
     }
     __syncthreads();
-    full_inverse(md, T, buf, 0, 0, len, g);
-    for (uint32_t i = threadIdx.x; i < len; i += nthreads()) row[i] = buf[pad(i)];
+    if (k < P.a) {
+        // full row: no halvings in the butterflies, one scaling by 2^-lg W on the store
+        full_inverse<Mod, false>(md, T, buf, 0, 0, len, g);
+        const Word sc = inv_pow2_tw(md, P.logW);
+        for (uint32_t i = threadIdx.x; i < len; i += nthreads()) row[i] = md.mul_tw(buf[pad(i)], sc);
+    } else {
+        full_inverse(md, T, buf, 0, 0, len, g);
+        for (uint32_t i = threadIdx.x; i < len; i += nthreads()) row[i] = buf[pad(i)];
+    }
 }
 
 // Number of inverse-row items: a rows plus the last row's pieces.
@@ -354,6 +361,13 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
             last[threadIdx.x] = xh;
             buf[pad(threadIdx.x)] = md.sub(buf[pad(threadIdx.x)], xh);
         }
+        __syncthreads();
+    } else if (len == Mg) {
+        // whole columns: no halvings in the butterflies, one scaling by
+        // 2^-lg Mg afterwards
+        full_inverse<Mod, false>(md, T, buf, LOGC, 0, Mg, 0);
+        const Word sc = inv_pow2_tw(md, __builtin_ctz(Mg));
+        for (uint32_t it = threadIdx.x; it < Mg * C; it += nthreads()) buf[pad(it)] = md.mul_tw(buf[pad(it)], sc);
         __syncthreads();
     } else {
         gitft(md, T, buf, LOGC, Mg, len, 0);
