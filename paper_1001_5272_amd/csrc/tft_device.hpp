@@ -529,7 +529,7 @@ __device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename
 #pragma unroll
             for (int t = 0; t < R; t++) x[t] = buf[pad((base + t * q) * C + c)];
             uS.load_inv(md, T, (gbase >> (s0 + S)) + i);
-            uS.inverse(md, x);
+            uS.template inverse<false>(md, x);
 #pragma unroll
             for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
         } else if (u < nS + n4) {
@@ -538,7 +538,7 @@ __device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename
 #pragma unroll
             for (int t = 0; t < 4; t++) x[t] = buf[pad((base + t * q) * C + c)];
             u4.load_inv(md, T, (gbase + off4) >> (s0 + 2));
-            u4.inverse(md, x);
+            u4.template inverse<false>(md, x);
 #pragma unroll
             for (int t = 0; t < 4; t++) buf[pad((base + t * q) * C + c)] = x[t];
         } else {
@@ -547,7 +547,7 @@ __device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename
 #pragma unroll
             for (int t = 0; t < 2; t++) x[t] = buf[pad((base + t * q) * C + c)];
             u2.load_inv(md, T, (gbase + off2) >> (s0 + 1));
-            u2.inverse(md, x);
+            u2.template inverse<false>(md, x);
 #pragma unroll
             for (int t = 0; t < 2; t++) buf[pad((base + t * q) * C + c)] = x[t];
         }
@@ -555,17 +555,32 @@ __device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename
     __syncthreads();
 }
 
+// The passes leave out the butterflies' halvings; a last pass scales each
+// position by 2^-e, e the size exponent of its piece (the highest bit in which
+// the position differs from m).
 template <class Mod>
 __device__ void pieces_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                                uint32_t M, uint32_t m, uint64_t g0) {
+    using Word = typename Mod::Word;
+    __shared__ Word scale[32];
     const uint64_t gbase = g0 << __builtin_ctz(M);   // global position of the block's first word
     const int top = 31 - __builtin_clz(m);            // largest piece: 2^top
+    if (threadIdx.x <= (uint32_t)top) scale[threadIdx.x] = inv_pow2_tw(md, (int)threadIdx.x);
     for (int s0 = 0; s0 < top;) {
         const int S = group_stages(m << logC, top - s0);
         if (S == 3) pieces_pass<Mod, 3>(md, T, buf, logC, m, gbase, (uint32_t)s0);
         else if (S == 2) pieces_pass<Mod, 2>(md, T, buf, logC, m, gbase, (uint32_t)s0);
         else pieces_pass<Mod, 1>(md, T, buf, logC, m, gbase, (uint32_t)s0);
         s0 += S;
+    }
+    if (top > 0) {
+        const uint32_t items = m << logC;
+        for (uint32_t it = threadIdx.x; it < items; it += nthreads()) {
+            const uint32_t x = it >> logC;
+            const int e = 31 - __builtin_clz(x ^ m);
+            if (e > 0) buf[pad(it)] = md.mul_tw(buf[pad(it)], scale[e]);
+        }
+        __syncthreads();
     }
 }
 

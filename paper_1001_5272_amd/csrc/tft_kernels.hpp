@@ -288,15 +288,10 @@ __device__ void row_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
         for (uint32_t i = threadIdx.x; i < len; i += nthreads()) buf[pad(i)] = row[i];
     }
     __syncthreads();
-    if (k < P.a) {
-        // full row: no halvings in the butterflies, one scaling by 2^-lg W on the store
-        full_inverse<Mod, false>(md, T, buf, 0, 0, len, g);
-        const Word sc = inv_pow2_tw(md, P.logW);
-        for (uint32_t i = threadIdx.x; i < len; i += nthreads()) row[i] = md.mul_tw(buf[pad(i)], sc);
-    } else {
-        full_inverse(md, T, buf, 0, 0, len, g);
-        for (uint32_t i = threadIdx.x; i < len; i += nthreads()) row[i] = buf[pad(i)];
-    }
+    // no halvings in the butterflies, one scaling by 2^-lg len on the store
+    full_inverse<Mod, false>(md, T, buf, 0, 0, len, g);
+    const Word sc = inv_pow2_tw(md, __builtin_ctz(len));
+    for (uint32_t i = threadIdx.x; i < len; i += nthreads()) row[i] = md.mul_tw(buf[pad(i)], sc);
 }
 
 // Number of inverse-row items: a rows plus the last row's pieces.
