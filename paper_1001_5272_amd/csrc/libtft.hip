@@ -222,6 +222,7 @@ tft::Tables<Word> tables_of(const tft_ctx* ctx) {
     T.f2 = base + ctx->n1;
     T.i1 = base + ctx->n1 + ctx->n2;
     T.i2 = base + 2 * ctx->n1 + ctx->n2;
+    T.K = ctx->v;
     return T;
 }
 

@@ -39,6 +39,9 @@ struct Tables {
     const Word* lf = nullptr;
     const Word* li = nullptr;
     uint32_t nl = 0;
+    // w_s = w[K]^(rev_K s): K is the order (log 2) of the root the tables
+    // expand, so w[K]^e = w_{rev_K e} for 0 <= e < 2^K
+    uint32_t K = 0;
 };
 
 // Threads in the workgroup.  Every launch here has uniform workgroups, so the
@@ -140,6 +143,19 @@ __device__ __forceinline__ typename Mod::Word tw_inv(const Mod& md, const Tables
     return t;
 }
 
+// w[K]^e and w[K]^-e (0 <= e < 2^K) in twiddle form: the tables index roots
+// by bit-reversed exponent.
+template <class Mod>
+__device__ __forceinline__ typename Mod::Word root_pow(const Mod& md, const Tables<typename Mod::Word>& T,
+                                                       uint32_t e) {
+    return tw_fwd(md, T, (uint64_t)(__builtin_bitreverse32(e) >> (32 - T.K)));
+}
+template <class Mod>
+__device__ __forceinline__ typename Mod::Word root_pow_inv(const Mod& md, const Tables<typename Mod::Word>& T,
+                                                           uint32_t e) {
+    return tw_inv(md, T, (uint64_t)(__builtin_bitreverse32(e) >> (32 - T.K)));
+}
+
 // Copy w_{2i} and w_{2i}^-1 (i < nl, 2 nl <= 2^B1) into LDS at dst (2 nl
 // words) and return tables that read them from there.  One coalesced pass
 // replaces a dependent global load at the start of every stage group.
@@ -167,6 +183,24 @@ __device__ __forceinline__ typename Mod::Word pow_tw(const Mod& md, typename Mod
         e >>= 1;
     }
     return r;
+}
+
+// Workgroup-strided loop over items it < count (it = threadIdx.x + k
+// nthreads()) doing put(it, load(it)).  Each thread issues the loads of U
+// items before it consumes any, so U memory requests per thread are in flight
+// at once rather than one round trip per item.
+template <int U, class Load, class Put>
+__device__ __forceinline__ void staged_copy(uint32_t count, Load&& load, Put&& put) {
+    const uint32_t nt = nthreads();
+    uint32_t it = threadIdx.x;
+    for (; it + (U - 1) * nt < count; it += U * nt) {
+        decltype(load(it)) v[U];
+#pragma unroll
+        for (int m = 0; m < U; m++) v[m] = load(it + m * nt);
+#pragma unroll
+        for (int m = 0; m < U; m++) put(it + m * nt, v[m]);
+    }
+    for (; it < count; it += nt) put(it, load(it));
 }
 
 // ------------------------------------------------------- register units
@@ -197,7 +231,19 @@ struct Unit {
 #pragma unroll
             for (int q = 0; q < (1 << s); q++) tw[(1 << s) - 1 + q] = tw_inv(md, T, 2 * ((g << s) + q));
     }
-    // forward: (a, b) -> (a + w b, a - w b), stages s = 0 .. S-1
+    // Inside a block at global index 0 the sub-block indices are small, and
+    // w_{2x} = tab[x << sh] (tab = lf or li with sh = 0, f1 or i1 with sh = 1):
+    // one load per twiddle, with no branch, so all of them are in flight at once.
+    __device__ __forceinline__ void load0(const Word* tab, uint32_t sh, uint32_t i) {
+#pragma unroll
+        for (int s = 0; s < S; s++)
+#pragma unroll
+            for (int q = 0; q < (1 << s); q++) tw[(1 << s) - 1 + q] = tab[((i << s) + q) << sh];
+    }
+    // forward: (a, b) -> (a + w b, a - w b), stages s = 0 .. S-1.  TOP: the
+    // unit sits in the block at global index 0 (G = 0), where every
+    // sub-block q = 0 has twiddle w_0 = 1 and its products are left out.
+    template <bool TOP = false>
     __device__ __forceinline__ void forward(const Mod& md, Word (&x)[R]) const {
 #pragma unroll
         for (int s = 0; s < S; s++) {
@@ -208,7 +254,7 @@ struct Unit {
 #pragma unroll
                 for (int t = 0; t < dist; t++) {
                     const int a = q * 2 * dist + t, b = a + dist;
-                    const Word v = md.mul_tw(x[b], w);
+                    const Word v = (TOP && q == 0) ? x[b] : md.mul_tw(x[b], w);
                     const Word u = x[a];
                     x[a] = md.add(u, v);
                     x[b] = md.sub(u, v);
@@ -217,8 +263,9 @@ struct Unit {
         }
     }
     // inverse: (a, b) -> ((a + b)/2, (a - b) w^-1 / 2), stages s = S-1 .. 0;
-    // HALF = false leaves out the halvings (the caller scales by 2^-stages)
-    template <bool HALF = true>
+    // HALF = false leaves out the halvings (the caller scales by 2^-stages);
+    // TOP as in forward
+    template <bool HALF = true, bool TOP = false>
     __device__ __forceinline__ void inverse(const Mod& md, Word (&x)[R]) const {
 #pragma unroll
         for (int s = S - 1; s >= 0; s--) {
@@ -230,12 +277,15 @@ struct Unit {
                 for (int t = 0; t < dist; t++) {
                     const int a = q * 2 * dist + t, b = a + dist;
                     const Word u = x[a], v = x[b];
+                    const bool one = TOP && q == 0;
                     if (HALF) {
                         x[a] = md.half(md.add(u, v));
-                        x[b] = md.mul_tw(md.half(md.sub(u, v)), w);
+                        const Word d = md.half(md.sub(u, v));
+                        x[b] = one ? d : md.mul_tw(d, w);
                     } else {
                         x[a] = md.add(u, v);
-                        x[b] = md.mul_tw(md.sub(u, v), w);
+                        const Word d = md.sub(u, v);
+                        x[b] = one ? d : md.mul_tw(d, w);
                     }
                 }
             }
@@ -257,10 +307,12 @@ __host__ __device__ __forceinline__ uint32_t padded_words(uint32_t n) { return n
 
 // One group of S forward stages starting at half-size h over the blocks of
 // size 2h that meet the wanted outputs [out_lo, out_hi).
-template <class Mod, int S>
+// Z: the block is at global index 0 and its twiddles come from tab (see
+// Unit::load0); TOP (with Z): this is its first group.
+template <class Mod, int S, bool Z = false, bool TOP = false>
 __device__ __forceinline__ void dif_group(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
                                           int logC, uint32_t M, uint32_t h, uint32_t out_lo, uint32_t out_hi,
-                                          uint64_t g0) {
+                                          uint64_t g0, const typename Mod::Word* tab = nullptr, uint32_t sh = 0) {
     using Word = typename Mod::Word;
     constexpr int R = 1 << S;
     const uint32_t C = 1u << logC;
@@ -280,8 +332,9 @@ __device__ __forceinline__ void dif_group(const Mod& md, const Tables<typename M
         Word x[R];
 #pragma unroll
         for (int t = 0; t < R; t++) x[t] = buf[pad((base + t * q) * C + c)];
-        un.load_fwd(md, T, gbase + i);
-        un.forward(md, x);
+        if (Z) un.load0(tab, sh, i);
+        else un.load_fwd(md, T, gbase + i);
+        un.template forward<TOP>(md, x);
 #pragma unroll
         for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
     }
@@ -361,6 +414,27 @@ template <class Mod>
 __device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                             uint32_t M, uint32_t out_lo, uint32_t out_hi, uint64_t g0) {
     const uint32_t words = M << logC;
+    if (g0 == 0) {
+        // block 0: twiddles w_{2x}, x < M/2, from the LDS copy when it reaches
+        // that far, else read in place from f1 (x < 2^(B1-1) for M <= 2^B1)
+        const bool lds = T.nl >= (M >> 1);
+        const typename Mod::Word* tab = lds ? T.lf : T.f1;
+        const uint32_t sh = lds ? 0u : 1u;
+        for (uint32_t h = M >> 1; h >= 1;) {
+            const int S = group_stages(words, __builtin_ctz(h) + 1);
+            if (h == M >> 1) {   // the first group: sub-blocks q = 0 have twiddle 1
+                if (S == 3) dif_group<Mod, 3, true, true>(md, T, buf, logC, M, h, out_lo, out_hi, 0, tab, sh);
+                else if (S == 2) dif_group<Mod, 2, true, true>(md, T, buf, logC, M, h, out_lo, out_hi, 0, tab, sh);
+                else dif_group<Mod, 1, true, true>(md, T, buf, logC, M, h, out_lo, out_hi, 0, tab, sh);
+            } else {
+                if (S == 3) dif_group<Mod, 3, true>(md, T, buf, logC, M, h, out_lo, out_hi, 0, tab, sh);
+                else if (S == 2) dif_group<Mod, 2, true>(md, T, buf, logC, M, h, out_lo, out_hi, 0, tab, sh);
+                else dif_group<Mod, 1, true>(md, T, buf, logC, M, h, out_lo, out_hi, 0, tab, sh);
+            }
+            h >>= S;
+        }
+        return;
+    }
     for (uint32_t h = M >> 1; h >= 1;) {
         const int S = group_stages(words, __builtin_ctz(h) + 1);
         if (S == 3) dif_group<Mod, 3>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
@@ -372,9 +446,11 @@ __device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, 
 
 // One group of S inverse stages ending at half-size h (stages h/2^(S-1) .. h)
 // over every block of size 2h inside [off, off + Sz).
-template <class Mod, int S, bool SYNC = true, bool HALF = true>
+// Z and TOP as in dif_group (TOP: the last group of a block at index 0).
+template <class Mod, int S, bool SYNC = true, bool HALF = true, bool Z = false, bool TOP = false>
 __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
-                                          int logC, uint32_t off, uint32_t Sz, uint32_t h, uint64_t g) {
+                                          int logC, uint32_t off, uint32_t Sz, uint32_t h, uint64_t g,
+                                          const typename Mod::Word* tab = nullptr, uint32_t sh = 0) {
     using Word = typename Mod::Word;
     constexpr int R = 1 << S;
     const uint32_t C = 1u << logC;
@@ -393,8 +469,9 @@ __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename M
         Word x[R];
 #pragma unroll
         for (int t = 0; t < R; t++) x[t] = buf[pad((base + t * q) * C + c)];
-        un.load_inv(md, T, gbase + i);
-        un.template inverse<HALF>(md, x);
+        if (Z) un.load0(tab, sh, i);
+        else un.load_inv(md, T, gbase + i);
+        un.template inverse<HALF, TOP>(md, x);
 #pragma unroll
         for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
     }
@@ -413,9 +490,24 @@ __device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T,
     for (int done = 0; done < L;) {      // stages 2^0 .. 2^(done-1) finished
         const int S = group_stages(words, L - done);
         const uint32_t h = 1u << (done + S - 1);
-        if (S == 3) dit_group<Mod, 3, true, HALF>(md, T, buf, logC, off, Sz, h, g);
-        else if (S == 2) dit_group<Mod, 2, true, HALF>(md, T, buf, logC, off, Sz, h, g);
-        else dit_group<Mod, 1, true, HALF>(md, T, buf, logC, off, Sz, h, g);
+        if (g == 0) {   // block 0: twiddles as in dif_forward; the last group skips twiddle 1
+            const bool lds = T.nl >= (Sz >> 1);
+            const typename Mod::Word* tab = lds ? T.li : T.i1;
+            const uint32_t sh = lds ? 0u : 1u;
+            if (done + S == L) {
+                if (S == 3) dit_group<Mod, 3, true, HALF, true, true>(md, T, buf, logC, off, Sz, h, 0, tab, sh);
+                else if (S == 2) dit_group<Mod, 2, true, HALF, true, true>(md, T, buf, logC, off, Sz, h, 0, tab, sh);
+                else dit_group<Mod, 1, true, HALF, true, true>(md, T, buf, logC, off, Sz, h, 0, tab, sh);
+            } else {
+                if (S == 3) dit_group<Mod, 3, true, HALF, true>(md, T, buf, logC, off, Sz, h, 0, tab, sh);
+                else if (S == 2) dit_group<Mod, 2, true, HALF, true>(md, T, buf, logC, off, Sz, h, 0, tab, sh);
+                else dit_group<Mod, 1, true, HALF, true>(md, T, buf, logC, off, Sz, h, 0, tab, sh);
+            }
+        } else {
+            if (S == 3) dit_group<Mod, 3, true, HALF>(md, T, buf, logC, off, Sz, h, g);
+            else if (S == 2) dit_group<Mod, 2, true, HALF>(md, T, buf, logC, off, Sz, h, g);
+            else dit_group<Mod, 1, true, HALF>(md, T, buf, logC, off, Sz, h, g);
+        }
         done += S;
     }
 }

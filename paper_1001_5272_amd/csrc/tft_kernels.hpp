@@ -214,22 +214,22 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
         if (share) put_share();
         return;
     }
-    for (uint32_t it = threadIdx.x; it < P.M * C; it += nthreads()) {
+    staged_copy<8>(P.M * C, [&](uint32_t it) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint64_t idx = (c0 + c) + (uint64_t)d * W;
-        buf[pad(it)] = (d < P.Lout && idx < P.n_src) ? P.src[idx] : Word(0);
-    }
+        return (d < P.Lout && idx < P.n_src) ? P.src[idx] : Word(0);
+    }, [&](uint32_t it, Word v) { buf[pad(it)] = v; });
     __syncthreads();
     dif_forward(md, T, buf, LOGC, P.M, 0, P.Lout, P.g0);
-    for (uint32_t it = threadIdx.x; it < P.Lout * C; it += nthreads()) {
+    staged_copy<8>(P.Lout * C, [&](uint32_t it) { return buf[pad(it)]; }, [&](uint32_t it, Word v) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint64_t idx = (c0 + c) + (uint64_t)d * W;
         if (idx < P.n)
-            P.X[idx] = buf[pad(it)];
+            P.X[idx] = v;
         else if (P.b && d == P.a)
-            P.V[c0 + c] = buf[pad(it)];
-        if (share && d == P.a) zterm[c] = md.mul_tw(buf[pad(it)], ypow[c]);
-    }
+            P.V[c0 + c] = v;
+        if (share && d == P.a) zterm[c] = md.mul_tw(v, ypow[c]);
+    });
     if (share) put_share();
 }
 
@@ -244,10 +244,24 @@ __device__ void row_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T,
     const uint32_t W = 1u << P.logW;
     Word* row = P.X + (uint64_t)j * W;
     if (j < P.a) {
-        for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = row[i];
+        // Row j holds F mod (x^W - w_g), g its global block index; its outputs
+        // are F(w_{gW + r}) = F(z w_r) with z = w_{gW} (disjoint bits), i.e. the
+        // transform at block index 0 of G(x) = F(z x) mod (x^W - 1).  Twisting
+        // coefficient i by z^i costs one product each (z^i = w[K]^(i E) with
+        // z = w[K]^E), and the block-0 transform takes every twiddle straight
+        // from the table and skips the unit twiddles of its first group.
+        const uint64_t g = P.g0 * P.a + j;
+        const uint32_t nt = nthreads(), maskK = (1u << T.K) - 1;
+        const uint32_t E = __builtin_bitreverse32((uint32_t)(g << P.logW)) >> (32 - T.K);
+        const Word step = root_pow(md, T, (nt * E) & maskK);
+        Word f = root_pow(md, T, (threadIdx.x * E) & maskK);
+        staged_copy<8>(W, [&](uint32_t i) { return row[i]; }, [&](uint32_t i, Word v) {
+            buf[pad(i)] = md.mul_tw(v, f);
+            f = md.tw_mul_tw(f, step);
+        });
         __syncthreads();
-        dif_forward(md, T, buf, 0, W, 0, W, P.g0 * P.a + j);
-        for (uint32_t i = threadIdx.x; i < W; i += nthreads()) row[i] = buf[pad(i)];
+        dif_forward(md, T, buf, 0, W, 0, W, 0);
+        staged_copy<8>(W, [&](uint32_t i) { return buf[pad(i)]; }, [&](uint32_t i, Word v) { row[i] = v; });
     } else {
         for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = i < P.b ? row[i] : P.V[i];
         __syncthreads();
@@ -283,15 +297,33 @@ __device__ void row_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
     Word* row = P.X + start;
     if (P.Y) {
         const Word* yr = P.Y + start;
-        for (uint32_t i = threadIdx.x; i < len; i += nthreads()) buf[pad(i)] = md.mul(row[i], yr[i]);
+        struct Two { Word x, y; };
+        staged_copy<8>(len, [&](uint32_t i) { return Two{row[i], yr[i]}; },
+                       [&](uint32_t i, Two v) { buf[pad(i)] = md.mul(v.x, v.y); });
     } else {
-        for (uint32_t i = threadIdx.x; i < len; i += nthreads()) buf[pad(i)] = row[i];
+        staged_copy<8>(len, [&](uint32_t i) { return row[i]; }, [&](uint32_t i, Word v) { buf[pad(i)] = v; });
     }
     __syncthreads();
+    const Word sc = inv_pow2_tw(md, __builtin_ctz(len));
+    const uint32_t nt = nthreads();
+    if (k < P.a) {
+        // A full row inverts at block index 0 (the twist of row_fwd_body):
+        // the result is len G_i with G_i = c_i z^i, so the store multiplies
+        // by z^-i / len, z = w_{gW} = w[K]^E
+        full_inverse<Mod, false>(md, T, buf, 0, 0, len, 0);
+        const uint32_t maskK = (1u << T.K) - 1;
+        const uint32_t E = __builtin_bitreverse32((uint32_t)(g << P.logW)) >> (32 - T.K);
+        const Word step = root_pow_inv(md, T, (nt * E) & maskK);
+        Word f = md.tw_mul_tw(sc, root_pow_inv(md, T, (threadIdx.x * E) & maskK));
+        staged_copy<8>(len, [&](uint32_t i) { return buf[pad(i)]; }, [&](uint32_t i, Word v) {
+            row[i] = md.mul_tw(v, f);
+            f = md.tw_mul_tw(f, step);
+        });
+        return;
+    }
     // no halvings in the butterflies, one scaling by 2^-lg len on the store
     full_inverse<Mod, false>(md, T, buf, 0, 0, len, g);
-    const Word sc = inv_pow2_tw(md, __builtin_ctz(len));
-    for (uint32_t i = threadIdx.x; i < len; i += nthreads()) row[i] = md.mul_tw(buf[pad(i)], sc);
+    for (uint32_t i = threadIdx.x; i < len; i += nt) row[i] = md.mul_tw(buf[pad(i)], sc);
 }
 
 // Number of inverse-row items: a rows plus the last row's pieces.
@@ -332,11 +364,11 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
     if (phase == 0 && P.b == 1 && P.nparts && threadIdx.x < C)   // w_{aW}^c
         ypow[threadIdx.x] = pow_tw(md, tw_fwd(md, T, (uint64_t)P.a << P.logW), c0 + threadIdx.x);
     if (phase == 0 && P.b) eval_scales(md, LOGC, P.a, tw_fwd(md, T, P.a), zp);
-    for (uint32_t it = threadIdx.x; it < Mb * C; it += nthreads()) {
+    staged_copy<8>(Mb * C, [&](uint32_t it) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint32_t col = c0 + c;
-        buf[pad(it)] = (mine_col(col) && d < len) ? P.X[col + (uint64_t)d * W] : Word(0);
-    }
+        return (mine_col(col) && d < len) ? P.X[col + (uint64_t)d * W] : Word(0);
+    }, [&](uint32_t it, Word v) { buf[pad(it)] = v; });
     if (top) {
         for (uint32_t c = threadIdx.x; c < C; c += nthreads()) {
             const uint32_t col = c0 + c;
@@ -359,19 +391,31 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
         __syncthreads();
     } else if (len == Mg) {
         // whole columns: no halvings in the butterflies, one scaling by
-        // 2^-lg Mg afterwards
+        // 2^-lg Mg afterwards -- on the store, unless the evaluation below
+        // reads the coefficients from LDS
         full_inverse<Mod, false>(md, T, buf, LOGC, 0, Mg, 0);
         const Word sc = inv_pow2_tw(md, __builtin_ctz(Mg));
+        if (!(phase == 0 && P.b)) {
+            staged_copy<8>(len * C, [&](uint32_t it) { return buf[pad(it)]; }, [&](uint32_t it, Word v) {
+                const uint32_t c = it & (C - 1), d = it >> LOGC;
+                const uint32_t col = c0 + c;
+                if (mine_col(col)) P.X[col + (uint64_t)d * W] = md.mul_tw(v, sc);
+            });
+            return;
+        }
         for (uint32_t it = threadIdx.x; it < Mg * C; it += nthreads()) buf[pad(it)] = md.mul_tw(buf[pad(it)], sc);
         __syncthreads();
     } else {
         gitft(md, T, buf, LOGC, Mg, len, 0);
     }
-    for (uint32_t it = threadIdx.x; it < len * C; it += nthreads()) {
+    staged_copy<8>(len * C, [&](uint32_t it) {
+        const uint32_t c = it & (C - 1), d = it >> LOGC;
+        return d < Mb ? buf[pad(it)] : last[c];
+    }, [&](uint32_t it, Word v) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint32_t col = c0 + c;
-        if (mine_col(col)) P.X[col + (uint64_t)d * W] = d < Mb ? buf[pad(it)] : last[c];
-    }
+        if (mine_col(col)) P.X[col + (uint64_t)d * W] = v;
+    });
     if (phase == 0 && P.b) {
         // the extra value V_c = P_c(w_a) of the restored column (early mode:
         // for c < b the same evaluation gives C0(w_H), H = a)
