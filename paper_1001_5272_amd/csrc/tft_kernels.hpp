@@ -298,7 +298,7 @@ __device__ void row_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
     if (P.Y) {
         const Word* yr = P.Y + start;
         struct Two { Word x, y; };
-        staged_copy<8>(len, [&](uint32_t i) { return Two{row[i], yr[i]}; },
+        staged_copy<4>(len, [&](uint32_t i) { return Two{row[i], yr[i]}; },
                        [&](uint32_t i, Two v) { buf[pad(i)] = md.mul(v.x, v.y); });
     } else {
         staged_copy<8>(len, [&](uint32_t i) { return row[i]; }, [&](uint32_t i, Word v) { buf[pad(i)] = v; });
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(kColThreads) void k_col_fwd(Mod md, Tables<typename
     col_fwd_body<Mod, LOGC>(md, T, P, xcd_remap(blockIdx.x, tiles));
 }
 template <class Mod>
-__global__ __launch_bounds__(kRowThreads) void k_row_fwd(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_row_fwd(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P) {
     using Word = typename Mod::Word;
     if (P.b == 1 && P.nparts) {
@@ -591,7 +591,7 @@ __global__ __launch_bounds__(kRowThreads) void k_row_fwd(Mod md, Tables<typename
 // With P.early == 2 workgroup 0 builds Q (col_poly_body; dispatched first, it
 // runs beside the rows).  The last row's pieces come next, the full rows last.
 template <class Mod>
-__global__ __launch_bounds__(kRowThreads) void k_row_inv(Mod md, Tables<typename Mod::Word> T,
+__global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_row_inv(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P, uint64_t p) {
     const bool q = P.early == 2;
     if (q && blockIdx.x == 0) {
