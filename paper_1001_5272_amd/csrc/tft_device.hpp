@@ -410,18 +410,21 @@ __device__ __forceinline__ int group_stages(uint32_t words, int left) {
 // Forward transform of the block of size M at global index g0 (the block is
 // F mod (x^M - w_{g0})); only blocks meeting [out_lo, out_hi) are computed, so
 // positions outside that range end with unspecified values.
+// Stages h_hi, h_hi/2, ..., h_lo (powers of two, h_lo <= h_hi <= M/2) of the
+// forward transform of that block, in groups of at most three.
 template <class Mod>
-__device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
-                            uint32_t M, uint32_t out_lo, uint32_t out_hi, uint64_t g0) {
+__device__ void dif_stages(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+                           uint32_t M, uint32_t h_hi, uint32_t h_lo, uint32_t out_lo, uint32_t out_hi, uint64_t g0) {
     const uint32_t words = M << logC;
+    const int lo = __builtin_ctz(h_lo);
     if (g0 == 0) {
         // block 0: twiddles w_{2x}, x < M/2, from the LDS copy when it reaches
         // that far, else read in place from f1 (x < 2^(B1-1) for M <= 2^B1)
         const bool lds = T.nl >= (M >> 1);
         const typename Mod::Word* tab = lds ? T.lf : T.f1;
         const uint32_t sh = lds ? 0u : 1u;
-        for (uint32_t h = M >> 1; h >= 1;) {
-            const int S = group_stages(words, __builtin_ctz(h) + 1);
+        for (uint32_t h = h_hi; h >= h_lo;) {
+            const int S = group_stages(words, __builtin_ctz(h) - lo + 1);
             if (h == M >> 1) {   // the first group: sub-blocks q = 0 have twiddle 1
                 if (S == 3) dif_group<Mod, 3, true, true>(md, T, buf, logC, M, h, out_lo, out_hi, 0, tab, sh);
                 else if (S == 2) dif_group<Mod, 2, true, true>(md, T, buf, logC, M, h, out_lo, out_hi, 0, tab, sh);
@@ -435,13 +438,22 @@ __device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, 
         }
         return;
     }
-    for (uint32_t h = M >> 1; h >= 1;) {
-        const int S = group_stages(words, __builtin_ctz(h) + 1);
+    for (uint32_t h = h_hi; h >= h_lo;) {
+        const int S = group_stages(words, __builtin_ctz(h) - lo + 1);
         if (S == 3) dif_group<Mod, 3>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
         else if (S == 2) dif_group<Mod, 2>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
         else dif_group<Mod, 1>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
         h >>= S;
     }
+}
+
+// Forward transform of the block of size M at global index g0 (the block is
+// F mod (x^M - w_{g0})); only blocks meeting [out_lo, out_hi) are computed, so
+// positions outside that range end with unspecified values.
+template <class Mod>
+__device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+                            uint32_t M, uint32_t out_lo, uint32_t out_hi, uint64_t g0) {
+    if (M >= 2) dif_stages(md, T, buf, logC, M, M >> 1, 1, out_lo, out_hi, g0);
 }
 
 // One group of S inverse stages ending at half-size h (stages h/2^(S-1) .. h)
@@ -478,19 +490,17 @@ __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename M
     if (SYNC) __syncthreads();
 }
 
-// Full inverse of the forward stages on the block of size Sz at offset off with
-// global block index g: stages 1, 2, ..., Sz/2.  HALF = false leaves every
-// value multiplied by Sz (the caller scales by 1/Sz, e.g. on its store).
+// Inverse stages 2^d0 .. 2^(d1-1) (0 <= d0 < d1 <= lg Sz) of the block of size
+// Sz at offset off with global block index g, in groups of at most three.
 template <class Mod, bool HALF = true>
-__device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
-                             uint32_t off, uint32_t Sz, uint64_t g) {
-    if (Sz < 2) return;
-    const int L = __builtin_ctz(Sz);     // number of stages
+__device__ void dit_stages(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+                           uint32_t off, uint32_t Sz, int d0, int d1, uint64_t g) {
+    const int L = __builtin_ctz(Sz);
     const uint32_t words = Sz << logC;
-    for (int done = 0; done < L;) {      // stages 2^0 .. 2^(done-1) finished
-        const int S = group_stages(words, L - done);
+    for (int done = d0; done < d1;) {    // stages 2^d0 .. 2^(done-1) finished
+        const int S = group_stages(words, d1 - done);
         const uint32_t h = 1u << (done + S - 1);
-        if (g == 0) {   // block 0: twiddles as in dif_forward; the last group skips twiddle 1
+        if (g == 0) {   // block 0: twiddles as in dif_stages; the last group skips twiddle 1
             const bool lds = T.nl >= (Sz >> 1);
             const typename Mod::Word* tab = lds ? T.li : T.i1;
             const uint32_t sh = lds ? 0u : 1u;
@@ -510,6 +520,15 @@ __device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T,
         }
         done += S;
     }
+}
+
+// Full inverse of the forward stages on the block of size Sz at offset off with
+// global block index g: stages 1, 2, ..., Sz/2.  HALF = false leaves every
+// value multiplied by Sz (the caller scales by 1/Sz, e.g. on its store).
+template <class Mod, bool HALF = true>
+__device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+                             uint32_t off, uint32_t Sz, uint64_t g) {
+    if (Sz >= 2) dit_stages<Mod, HALF>(md, T, buf, logC, off, Sz, 0, __builtin_ctz(Sz), g);
 }
 
 // 2^-L in twiddle form.

@@ -214,13 +214,36 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
         if (share) put_share();
         return;
     }
-    staged_copy<8>(P.M * C, [&](uint32_t it) {
-        const uint32_t c = it & (C - 1), d = it >> LOGC;
-        const uint64_t idx = (c0 + c) + (uint64_t)d * W;
-        return (d < P.Lout && idx < P.n_src) ? P.src[idx] : Word(0);
-    }, [&](uint32_t it, Word v) { buf[pad(it)] = v; });
-    __syncthreads();
-    dif_forward(md, T, buf, LOGC, P.M, 0, P.Lout, P.g0);
+    if (P.g0 == 0 && P.M >= 16) {
+        // the first radix-8 group (stages M/2, M/4, M/8 of block 0) straight
+        // from HBM: the unit of lane c at u holds rows u + t M/8
+        const uint32_t M8 = P.M >> 3;
+        Unit<Mod, 3> top;
+        top.load0(T.lf, 0, 0);
+        for (uint32_t it = threadIdx.x; it < M8 * C; it += nthreads()) {
+            const uint32_t c = it & (C - 1), u = it >> LOGC;
+            Word x[8];
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const uint32_t d = u + t * M8;
+                const uint64_t idx = (c0 + c) + (uint64_t)d * W;
+                x[t] = (d < P.Lout && idx < P.n_src) ? P.src[idx] : Word(0);
+            }
+            top.template forward<true>(md, x);
+#pragma unroll
+            for (int t = 0; t < 8; t++) buf[pad((u + t * M8) * C + c)] = x[t];
+        }
+        __syncthreads();
+        dif_stages(md, T, buf, LOGC, P.M, P.M >> 4, 1, 0, P.Lout, 0);
+    } else {
+        staged_copy<8>(P.M * C, [&](uint32_t it) {
+            const uint32_t c = it & (C - 1), d = it >> LOGC;
+            const uint64_t idx = (c0 + c) + (uint64_t)d * W;
+            return (d < P.Lout && idx < P.n_src) ? P.src[idx] : Word(0);
+        }, [&](uint32_t it, Word v) { buf[pad(it)] = v; });
+        __syncthreads();
+        dif_forward(md, T, buf, LOGC, P.M, 0, P.Lout, P.g0);
+    }
     staged_copy<8>(P.Lout * C, [&](uint32_t it) { return buf[pad(it)]; }, [&](uint32_t it, Word v) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
         const uint64_t idx = (c0 + c) + (uint64_t)d * W;
@@ -233,6 +256,105 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
     if (share) put_share();
 }
 
+// Full rows of W = 2^logW words, logW >= 6, with the first and last radix-8
+// groups fused with the HBM transfers: a unit of the first forward group
+// (stages W/2, W/4, W/8) holds words u + t W/8, t < 8 -- one coalesced load
+// per t -- and a unit of the last group (stages 4, 2, 1) holds eight
+// consecutive words; the inverse runs the same groups in the other order.
+// Each unit works on its own loads as soon as they land, and the row makes
+// two LDS round trips and two barriers fewer than a load / transform / store
+// sequence.  Twiddles of block 0: w_{2x} = tab[x << sh].
+
+// 8 consecutive words at p (p 64-byte aligned)
+template <class Word>
+__device__ __forceinline__ void load8(const Word* p, Word (&x)[8]) {
+#pragma unroll
+    for (int t = 0; t < 8; t++) x[t] = p[t];
+}
+template <class Word>
+__device__ __forceinline__ void store8(Word* p, const Word (&x)[8]) {
+#pragma unroll
+    for (int t = 0; t < 8; t++) p[t] = x[t];
+}
+
+// Forward transform of row g (block F mod (x^W - w_g)) in place at row,
+// twisted to block index 0 as described in row_fwd_body.
+template <class Mod>
+__device__ void row_fwd_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+                              typename Mod::Word* row, uint32_t logW, uint64_t g) {
+    using Word = typename Mod::Word;
+    const uint32_t W = 1u << logW, W8 = W >> 3, nt = nthreads(), maskK = (1u << T.K) - 1;
+    const Word* tab = T.f1;   // w_{2x} = f1[2x], x < W/2 <= 2^(B1-1)
+    const uint32_t E = __builtin_bitreverse32((uint32_t)(g << logW)) >> (32 - T.K);
+    const Word z8 = root_pow(md, T, (W8 * E) & maskK);   // z^(W/8)
+    Unit<Mod, 3> top;
+    top.load0(tab, 1, 0);
+    for (uint32_t u = threadIdx.x; u < W8; u += nt) {
+        Word x[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) x[t] = row[u + t * W8];
+        Word f = root_pow(md, T, (u * E) & maskK);         // z^u, then z^(u + t W/8)
+        x[0] = md.mul_tw(x[0], f);
+#pragma unroll
+        for (int t = 1; t < 8; t++) {
+            f = md.tw_mul_tw(f, z8);
+            x[t] = md.mul_tw(x[t], f);
+        }
+        top.template forward<true>(md, x);
+#pragma unroll
+        for (int t = 0; t < 8; t++) buf[pad(u + t * W8)] = x[t];
+    }
+    __syncthreads();
+    dif_stages(md, T, buf, 0, W, W >> 4, 1, 0, W, 0);
+    staged_copy<8>(W, [&](uint32_t i) { return buf[pad(i)]; }, [&](uint32_t i, Word v) { row[i] = v; });
+}
+
+// Inverse of row_fwd_fused: coefficients of row g from its W values at row
+// (times Y pointwise first when yr is set).
+template <class Mod>
+__device__ void row_inv_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+                              typename Mod::Word* row, const typename Mod::Word* yr, uint32_t logW, uint64_t g) {
+    using Word = typename Mod::Word;
+    const uint32_t W = 1u << logW, W8 = W >> 3, nt = nthreads(), maskK = (1u << T.K) - 1;
+    const Word* tab = T.i1;
+    for (uint32_t i = threadIdx.x; i < W8; i += nt) {
+        Word x[8];
+        load8(row + 8 * i, x);
+        if (yr) {
+            Word y[8];
+            load8(yr + 8 * i, y);
+#pragma unroll
+            for (int t = 0; t < 8; t++) x[t] = md.mul(x[t], y[t]);
+        }
+        Unit<Mod, 3> un;
+        un.load0(tab, 1, i);
+        un.template inverse<false>(md, x);
+#pragma unroll
+        for (int t = 0; t < 8; t++) buf[pad(8 * i + t)] = x[t];
+    }
+    __syncthreads();
+    if (logW > 6) dit_stages<Mod, false>(md, T, buf, 0, 0, W, 3, (int)logW - 3, 0);
+    // the last group, then z^-i / W on the store (z = w_{gW} = w[K]^E)
+    const uint32_t E = __builtin_bitreverse32((uint32_t)(g << logW)) >> (32 - T.K);
+    const Word z8 = root_pow_inv(md, T, (W8 * E) & maskK);
+    const Word sc = inv_pow2_tw(md, (int)logW);
+    Unit<Mod, 3> top;
+    top.load0(tab, 1, 0);
+    for (uint32_t u = threadIdx.x; u < W8; u += nt) {
+        Word x[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) x[t] = buf[pad(u + t * W8)];
+        top.template inverse<false, true>(md, x);
+        Word f = md.tw_mul_tw(sc, root_pow_inv(md, T, (u * E) & maskK));
+        row[u] = md.mul_tw(x[0], f);
+#pragma unroll
+        for (int t = 1; t < 8; t++) {
+            f = md.tw_mul_tw(f, z8);
+            row[u + t * W8] = md.mul_tw(x[t], f);
+        }
+    }
+}
+
 // Forward row pass: row j < a is transformed in full (global block index j at
 // size W); row a (when b > 0) is built from its b slots and V_c (c >= b) and
 // keeps b outputs.
@@ -243,7 +365,9 @@ __device__ void row_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T,
     Word* buf = lds_buf<Word>();
     const uint32_t W = 1u << P.logW;
     Word* row = P.X + (uint64_t)j * W;
-    if (j < P.a) {
+    if (j < P.a && P.logW >= 6) {
+        row_fwd_fused(md, T, buf, row, P.logW, P.g0 * P.a + j);
+    } else if (j < P.a) {
         // Row j holds F mod (x^W - w_g), g its global block index; its outputs
         // are F(w_{gW + r}) = F(z w_r) with z = w_{gW} (disjoint bits), i.e. the
         // transform at block index 0 of G(x) = F(z x) mod (x^W - 1).  Twisting
@@ -295,6 +419,10 @@ __device__ void row_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
         g = pc.g;
     }
     Word* row = P.X + start;
+    if (k < P.a && P.logW >= 6) {
+        row_inv_fused(md, T, buf, row, P.Y ? P.Y + start : nullptr, P.logW, g);
+        return;
+    }
     if (P.Y) {
         const Word* yr = P.Y + start;
         struct Two { Word x, y; };
@@ -358,6 +486,44 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
     // general, k_col_fix) finishes the columns c < b
     const bool every = P.early && phase == 0;
     auto mine_col = [&](uint32_t col) { return every || (phase ? (col < P.b) : (col >= P.b)); };
+    if (!top && len == Mg && Mg >= 64 && !(phase == 0 && P.b)) {
+        // whole columns with nothing evaluated afterwards: the first radix-8
+        // group (stages 1, 2, 4 on eight consecutive rows) straight from HBM,
+        // the last (stages Mg/8, Mg/4, Mg/2) straight to HBM, scaled by 1/Mg
+        const uint32_t M8 = Mg >> 3;
+        for (uint32_t it = threadIdx.x; it < M8 * C; it += nthreads()) {
+            const uint32_t c = it & (C - 1), i = it >> LOGC;
+            const uint32_t col = c0 + c;
+            const bool mine = mine_col(col);
+            Word x[8];
+#pragma unroll
+            for (int t = 0; t < 8; t++) x[t] = mine ? P.X[col + (uint64_t)(8 * i + t) * W] : Word(0);
+            Unit<Mod, 3> un;
+            un.load0(T.li, 0, i);
+            un.template inverse<false>(md, x);
+#pragma unroll
+            for (int t = 0; t < 8; t++) buf[pad((8 * i + t) * C + c)] = x[t];
+        }
+        __syncthreads();
+        const int L = __builtin_ctz(Mg);
+        dit_stages<Mod, false>(md, T, buf, LOGC, 0, Mg, 3, L - 3, 0);
+        const Word sc = inv_pow2_tw(md, L);
+        Unit<Mod, 3> last;
+        last.load0(T.li, 0, 0);
+        for (uint32_t it = threadIdx.x; it < M8 * C; it += nthreads()) {
+            const uint32_t c = it & (C - 1), u = it >> LOGC;
+            const uint32_t col = c0 + c;
+            Word x[8];
+#pragma unroll
+            for (int t = 0; t < 8; t++) x[t] = buf[pad((u + t * M8) * C + c)];
+            last.template inverse<false, true>(md, x);
+            if (mine_col(col)) {
+#pragma unroll
+                for (int t = 0; t < 8; t++) P.X[col + (uint64_t)(u + t * M8) * W] = md.mul_tw(x[t], sc);
+            }
+        }
+        return;
+    }
     // powers for the evaluations at the end, computed first (few waves, and
     // nothing else is live yet); the next barrier publishes them
     __shared__ Word ypow[C], zp[kColThreads >> LOGC];   // zp: one power per thread of a lane
