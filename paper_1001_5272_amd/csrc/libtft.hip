@@ -160,6 +160,30 @@ unsigned plan_bucket(uint64_t n) {
     return 4 * e + j;
 }
 
+// Columns per tile, 2^logC: a tile row is one 64-byte segment (16 words of 4
+// bytes, 8 of 8 bytes).  Narrower tiles (4 words of 8 bytes) fit more tiles on
+// a CU but measured slower: half-used segments and no gain in occupancy, which
+// the column kernels' registers already bound.
+constexpr int col_log_width(unsigned w) { return w == 4 ? 4 : 3; }
+
+// Column-tile kernels by tile width (2^3 or 2^4 columns).
+template <class Mod>
+auto col_fwd_kernel(int logC) {
+    return logC == 3 ? tft::k_col_fwd<Mod, 3> : tft::k_col_fwd<Mod, 4>;
+}
+template <class Mod>
+auto col_inv_kernel(int logC) {
+    return logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
+}
+template <class Mod>
+auto col_fwd_list_kernel(int logC) {
+    return logC == 3 ? tft::k_col_fwd_list<Mod, 3> : tft::k_col_fwd_list<Mod, 4>;
+}
+template <class Mod>
+auto col_inv_list_kernel(int logC) {
+    return logC == 3 ? tft::k_col_inv_list<Mod, 3> : tft::k_col_inv_list<Mod, 4>;
+}
+
 Plan make_plan(const tft_ctx* ctx, uint64_t n) {
     Plan P{};
     P.n = n;
@@ -171,7 +195,7 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
         return P;
     }
     P.kind = 1;
-    P.logC = (w == 4) ? 4 : 3;   // 64-byte segments per column tile row
+    P.logC = col_log_width(w);
     auto fill = [&](unsigned logW) {
         P.logW = logW;
         P.W = 1ull << logW;
@@ -181,7 +205,7 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
         P.M = (uint32_t)pow2ceil(P.Lout);
         P.split = (P.M >= 4 && P.Lout == P.M / 2 + 1) ? 1 : 0;
         if (P.split) P.M /= 2;
-        P.lds_col = ((size_t)tft::padded_words(P.M << P.logC) + P.M) * w;   // tile + LDS twiddles
+        P.lds_col = ((size_t)tft::padded_words(P.M << P.logC) + P.M / 2) * w;   // tile + one LDS twiddle table
         P.lds_row = (size_t)tft::padded_words((uint32_t)P.W) * w;
     };
     const unsigned logC = (unsigned)P.logC;
@@ -245,7 +269,8 @@ bool set_lds_limits() {
         (const void*)tft::k_col_inv<Mod, 3>,      (const void*)tft::k_col_inv<Mod, 4>,
         (const void*)tft::k_col_inv<Mod, 0>,
         (const void*)tft::k_row_fwd<Mod>,         (const void*)tft::k_row_inv<Mod>,
-        (const void*)tft::k_last_inv<Mod>,        (const void*)tft::k_col_fwd_list<Mod, 3>,
+        (const void*)tft::k_last_inv<Mod>,        (const void*)tft::k_tail_inv<Mod>,
+        (const void*)tft::k_col_fwd_list<Mod, 3>,
         (const void*)tft::k_col_fwd_list<Mod, 4>, (const void*)tft::k_col_inv_list<Mod, 3>,
         (const void*)tft::k_col_inv_list<Mod, 4>, (const void*)tft::k_row_fwd_list<Mod>,
         (const void*)tft::k_row_inv_list<Mod>,    (const void*)tft::k_last_inv_list<Mod>,
@@ -316,10 +341,8 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
     // (scratch after V), and the row pass needs no workgroup for that row
     G.Q = V + kVWords;
     if (P.b == 1) G.nparts = tiles;
-    if (P.logC == 3)
-        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 3>, dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T, G, tiles);
-    else
-        launch(ctx, TFT_K_COL_FWD, tft::k_col_fwd<Mod, 4>, dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T, G, tiles);
+    launch(ctx, TFT_K_COL_FWD, col_fwd_kernel<Mod>(P.logC), dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T, G,
+           tiles);
     launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b > 1 ? 1 : 0))), dim3(row_threads(P)), P.lds_row,
            st, md, T, G);
     return launch_status();
@@ -349,14 +372,24 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     // a power of two the columns c < b are full inverses and the columns c >= b
     // the truncated ones, so the two classes keep their own passes.
     const bool full_long = P.b && ((P.a + 1) & P.a) == 0;
-    G.early = (P.b && !full_long) ? (P.split ? 1u : 2u) : 0u;
+    // b = W - 1 as well: the one short column and the last row are full
+    // inverses with one value missing (k_tail_inv), no truncated walks
+    const size_t lds_tail = ((size_t)tft::padded_words((uint32_t)P.a + 1) + (P.a + 1) / 2) * ctx->wbytes;
+    const bool one_short = full_long && P.b + 1 == P.W && P.logW >= 6 && lds_tail <= kLdsDynMax;
+    G.early = one_short ? 3u : (P.b && !full_long) ? (P.split ? 1u : 2u) : 0u;
     G.Q = V + kVWords;
     const uint32_t C = 1u << P.logC;
     const uint32_t tiles_all = (uint32_t)(P.W >> P.logC);
-    const uint32_t nrows = tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
+    const uint32_t nrows = one_short ? (uint32_t)P.a + 1 : tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
     launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows + (G.early == 2 ? 1u : 0u)), dim3(row_threads(P)),
            P.lds_row, st, md, T, G, ctx->p);
-    auto kern = P.logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
+    auto kern = col_inv_kernel<Mod>(P.logC);
+    if (one_short) {
+        launch(ctx, TFT_K_LAST_INV, tft::k_tail_inv<Mod>, dim3(1), dim3(tft::kLastThreads), lds_tail, st, md, T, G);
+        const uint32_t nt = (uint32_t)((P.b + C - 1) / C);   // columns c < b, in full
+        launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(col_threads(P)), P.lds_col, st, md, T, G, 1, 0u, nt);
+        return launch_status();
+    }
     // A class with only a few columns runs one column per workgroup, so that a
     // tile does not transform C - 1 skipped columns on one CU.
     const size_t lds_one = ((size_t)tft::padded_words(P.M) + P.M) * ctx->wbytes;
@@ -676,7 +709,7 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
     size_t v_total = 0;
     B->lds_col = B->lds_row = B->lds_small = 0;
     B->row_thr = B->col_thr = 64;
-    B->logC = (w == 4) ? 4 : 3;
+    B->logC = col_log_width(w);
     const size_t small_lds_cap = kLdsHard - 32 * 1024;
     for (size_t k = 0; k < count; k++) {
         const tft_mul_desc& D = d[k];
@@ -806,9 +839,8 @@ tft_status batch_run(tft_batch* B, hipStream_t st) {
         launch(ctx, TFT_K_SMALL_LIST, tft::k_small_list<Mod>, dim3(B->small_grid), dim3(kThreads), B->lds_small,
                small_st, md, T, (const tft::SmallJob<Word>*)B->jobs, (uint32_t)B->n_small, B->counter);
     }
-    const bool c3 = B->logC == 3;
     if (B->n_items[PH_COL_FWD])
-        launch(ctx, TFT_K_COL_FWD, c3 ? tft::k_col_fwd_list<Mod, 3> : tft::k_col_fwd_list<Mod, 4>,
+        launch(ctx, TFT_K_COL_FWD, col_fwd_list_kernel<Mod>(B->logC),
                dim3(B->n_items[PH_COL_FWD]), dim3(B->col_thr), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_FWD]);
     if (B->n_items[PH_ROW_FWD])
@@ -818,14 +850,14 @@ tft_status batch_run(tft_batch* B, hipStream_t st) {
         launch(ctx, TFT_K_ROW_INV, tft::k_row_inv_list<Mod>, dim3(B->n_items[PH_ROW_INV]), dim3(B->row_thr), B->lds_row,
                st, md, T, recs, (const tft::Item*)B->items[PH_ROW_INV]);
     if (B->n_items[PH_COL_INV_SHORT])
-        launch(ctx, TFT_K_COL_INV_SHORT, c3 ? tft::k_col_inv_list<Mod, 3> : tft::k_col_inv_list<Mod, 4>,
+        launch(ctx, TFT_K_COL_INV_SHORT, col_inv_list_kernel<Mod>(B->logC),
                dim3(B->n_items[PH_COL_INV_SHORT]), dim3(B->col_thr), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_INV_SHORT], 0);
     if (B->n_items[PH_LAST_INV])
         launch(ctx, TFT_K_LAST_INV, tft::k_last_inv_list<Mod>, dim3(B->n_items[PH_LAST_INV]), dim3(B->row_thr),
                B->lds_row, st, md, T, recs, (const tft::Item*)B->items[PH_LAST_INV]);
     if (B->n_items[PH_COL_INV_LONG])
-        launch(ctx, TFT_K_COL_INV_LONG, c3 ? tft::k_col_inv_list<Mod, 3> : tft::k_col_inv_list<Mod, 4>,
+        launch(ctx, TFT_K_COL_INV_LONG, col_inv_list_kernel<Mod>(B->logC),
                dim3(B->n_items[PH_COL_INV_LONG]), dim3(B->col_thr), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_INV_LONG], 1);
     if (both) {

@@ -34,11 +34,12 @@ struct Tables {
     const Word* f2;
     const Word* i1;
     const Word* i2;
-    // optional LDS copy of the small-index twiddles: lf[i] = w_{2i},
-    // li[i] = w_{2i}^-1 for i < nl (every twiddle of a block at global index 0)
+    // optional LDS copies of the small-index twiddles: lf[i] = w_{2i} for
+    // i < nlf, li[i] = w_{2i}^-1 for i < nli (every twiddle of a block at
+    // global index 0 below that size)
     const Word* lf = nullptr;
     const Word* li = nullptr;
-    uint32_t nl = 0;
+    uint32_t nlf = 0, nli = 0;
     // w_s = w[K]^(rev_K s): K is the order (log 2) of the root the tables
     // expand, so w[K]^e = w_{rev_K e} for 0 <= e < 2^K
     uint32_t K = 0;
@@ -126,7 +127,7 @@ struct ModGL {
 template <class Mod>
 __device__ __forceinline__ typename Mod::Word tw_fwd(const Mod& md, const Tables<typename Mod::Word>& T,
                                                       uint64_t s) {
-    if ((s >> 1) < T.nl && !(s & 1)) return T.lf[s >> 1];
+    if ((s >> 1) < T.nlf && !(s & 1)) return T.lf[s >> 1];
     typename Mod::Word t = T.f1[s & kMask1];
     const uint64_t h = s >> kB1;
     if (h) t = md.tw_mul_tw(t, T.f2[h]);
@@ -136,7 +137,7 @@ __device__ __forceinline__ typename Mod::Word tw_fwd(const Mod& md, const Tables
 template <class Mod>
 __device__ __forceinline__ typename Mod::Word tw_inv(const Mod& md, const Tables<typename Mod::Word>& T,
                                                       uint64_t s) {
-    if ((s >> 1) < T.nl && !(s & 1)) return T.li[s >> 1];
+    if ((s >> 1) < T.nli && !(s & 1)) return T.li[s >> 1];
     typename Mod::Word t = T.i1[s & kMask1];
     const uint64_t h = s >> kB1;
     if (h) t = md.tw_mul_tw(t, T.i2[h]);
@@ -159,17 +160,23 @@ __device__ __forceinline__ typename Mod::Word root_pow_inv(const Mod& md, const 
 // Copy w_{2i} and w_{2i}^-1 (i < nl, 2 nl <= 2^B1) into LDS at dst (2 nl
 // words) and return tables that read them from there.  One coalesced pass
 // replaces a dependent global load at the start of every stage group.
-template <class Word>
+// FWD / INV: copy only that direction's table (nl words).
+template <class Word, bool FWD = true, bool INV = true>
 __device__ Tables<Word> local_tables(const Tables<Word>& T, Word* dst, uint32_t nl) {
+    Tables<Word> L = T;
     for (uint32_t i = threadIdx.x; i < nl; i += nthreads()) {
-        dst[i] = T.f1[2 * i];
-        dst[nl + i] = T.i1[2 * i];
+        if (FWD) dst[i] = T.f1[2 * i];
+        if (INV) dst[(FWD ? nl : 0) + i] = T.i1[2 * i];
     }
     __syncthreads();
-    Tables<Word> L = T;
-    L.lf = dst;
-    L.li = dst + nl;
-    L.nl = nl;
+    if (FWD) {
+        L.lf = dst;
+        L.nlf = nl;
+    }
+    if (INV) {
+        L.li = dst + (FWD ? nl : 0);
+        L.nli = nl;
+    }
     return L;
 }
 
@@ -420,7 +427,7 @@ __device__ void dif_stages(const Mod& md, const Tables<typename Mod::Word>& T, t
     if (g0 == 0) {
         // block 0: twiddles w_{2x}, x < M/2, from the LDS copy when it reaches
         // that far, else read in place from f1 (x < 2^(B1-1) for M <= 2^B1)
-        const bool lds = T.nl >= (M >> 1);
+        const bool lds = T.nlf >= (M >> 1);
         const typename Mod::Word* tab = lds ? T.lf : T.f1;
         const uint32_t sh = lds ? 0u : 1u;
         for (uint32_t h = h_hi; h >= h_lo;) {
@@ -501,7 +508,7 @@ __device__ void dit_stages(const Mod& md, const Tables<typename Mod::Word>& T, t
         const int S = group_stages(words, d1 - done);
         const uint32_t h = 1u << (done + S - 1);
         if (g == 0) {   // block 0: twiddles as in dif_stages; the last group skips twiddle 1
-            const bool lds = T.nl >= (Sz >> 1);
+            const bool lds = T.nli >= (Sz >> 1);
             const typename Mod::Word* tab = lds ? T.li : T.i1;
             const uint32_t sh = lds ? 0u : 1u;
             if (done + S == L) {

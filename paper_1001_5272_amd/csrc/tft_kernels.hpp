@@ -139,7 +139,8 @@ struct TwoPass {
     uint32_t logW, a, b, Lout, M;
     uint32_t split;   // 1: Lout = M + 1 with M a power of two (see col_fwd_body)
     uint32_t early;   // inverse with b > 0: 0 columns c < b after the last row; 1 split mode, 2 general
-                      // (columns c < b run with phase 0, see col_inv_body and last_inv_body)
+                      // (columns c < b run with phase 0, see col_inv_body and last_inv_body);
+                      // 3 b = W - 1 with a + 1 a power of two (see tail_inv_body)
     Word* Q;          // early == 2: Q_0..Q_a at Q, scratch at Q + kQStride, 1 / Q(w_a) at Q[2 kQStride]
     uint64_t g0;      // forward of a whole block (n = a W, b = 0): the block's global index, else 0
     uint32_t nparts;  // inverse with b = 1: column tiles leaving a partial last-row sum at Q + kQStride, or 0
@@ -158,10 +159,10 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
                              const TwoPass<typename Mod::Word>& P, uint32_t tile) {
     using Word = typename Mod::Word;
     constexpr uint32_t C = 1u << LOGC;
-    __shared__ Word red[(kColThreads / 64) * kMaxC];
-    __shared__ Word extra[kMaxC], hi0[kMaxC];
+    __shared__ Word red[(kColThreads / 64) * C];
+    __shared__ Word extra[C], hi0[C];
     Word* buf = lds_buf<Word>();
-    const Tables<Word> T = local_tables(T0, buf + padded_words(P.M << LOGC), P.M / 2);
+    const Tables<Word> T = local_tables<Word, true, false>(T0, buf + padded_words(P.M << LOGC), P.M / 2);
     const uint32_t c0 = tile * C;
     const uint64_t W = 1ull << P.logW;
     // b = 1 (P.nparts): the tile's share sum_c Z_c w_{aW}^c of the last row's
@@ -311,18 +312,31 @@ __device__ void row_fwd_fused(const Mod& md, const Tables<typename Mod::Word>& T
 
 // Inverse of row_fwd_fused: coefficients of row g from its W values at row
 // (times Y pointwise first when yr is set).
-template <class Mod>
+// PART: only words below lim < W exist at row (and yr); the missing ones enter
+// as 0 and the coefficient at index lim is stored to *beyond.
+template <class Mod, bool PART = false>
 __device__ void row_inv_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
-                              typename Mod::Word* row, const typename Mod::Word* yr, uint32_t logW, uint64_t g) {
+                              typename Mod::Word* row, const typename Mod::Word* yr, uint32_t logW, uint64_t g,
+                              uint32_t lim = 0, typename Mod::Word* beyond = nullptr) {
     using Word = typename Mod::Word;
     const uint32_t W = 1u << logW, W8 = W >> 3, nt = nthreads(), maskK = (1u << T.K) - 1;
     const Word* tab = T.i1;
     for (uint32_t i = threadIdx.x; i < W8; i += nt) {
         Word x[8];
-        load8(row + 8 * i, x);
+        if (PART) {
+#pragma unroll
+            for (int t = 0; t < 8; t++) x[t] = 8 * i + t < lim ? row[8 * i + t] : Word(0);
+        } else {
+            load8(row + 8 * i, x);
+        }
         if (yr) {
             Word y[8];
-            load8(yr + 8 * i, y);
+            if (PART) {
+#pragma unroll
+                for (int t = 0; t < 8; t++) y[t] = 8 * i + t < lim ? yr[8 * i + t] : Word(0);
+            } else {
+                load8(yr + 8 * i, y);
+            }
 #pragma unroll
             for (int t = 0; t < 8; t++) x[t] = md.mul(x[t], y[t]);
         }
@@ -346,11 +360,15 @@ __device__ void row_inv_fused(const Mod& md, const Tables<typename Mod::Word>& T
         for (int t = 0; t < 8; t++) x[t] = buf[pad(u + t * W8)];
         top.template inverse<false, true>(md, x);
         Word f = md.tw_mul_tw(sc, root_pow_inv(md, T, (u * E) & maskK));
-        row[u] = md.mul_tw(x[0], f);
 #pragma unroll
-        for (int t = 1; t < 8; t++) {
-            f = md.tw_mul_tw(f, z8);
-            row[u + t * W8] = md.mul_tw(x[t], f);
+        for (int t = 0; t < 8; t++) {
+            if (t) f = md.tw_mul_tw(f, z8);
+            const uint32_t idx = u + t * W8;
+            const Word v = md.mul_tw(x[t], f);
+            if (!PART || idx < lim)
+                row[idx] = v;
+            else if (idx == lim)
+                *beyond = v;
         }
     }
 }
@@ -406,6 +424,13 @@ __device__ void row_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
     const uint32_t W = 1u << P.logW;
+    if (P.early == 3 && k == P.a) {
+        // the last row with one value missing (b = W - 1): its full inverse
+        // with that value 0; tail_inv_body adds the missing value's share
+        row_inv_fused<Mod, true>(md, T, buf, P.X + (uint64_t)P.a * W, P.Y ? P.Y + (uint64_t)P.a * W : nullptr, P.logW,
+                                 P.a, P.b, P.V + (W - 1));
+        return;
+    }
     uint64_t start, g;
     uint32_t len;
     if (k < P.a) {
@@ -470,10 +495,10 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
                              const TwoPass<typename Mod::Word>& P, int phase, uint32_t tile) {
     using Word = typename Mod::Word;
     constexpr uint32_t C = 1u << LOGC;
-    __shared__ Word red[(kColThreads / 64) * kMaxC];
-    __shared__ Word extra[kMaxC], last[kMaxC];
+    __shared__ Word red[(kColThreads / 64) * C];
+    __shared__ Word extra[C], last[C];
     Word* buf = lds_buf<Word>();
-    const Tables<Word> T = local_tables(T0, buf + padded_words(P.M << LOGC), P.M / 2);
+    const Tables<Word> T = local_tables<Word, false, true>(T0, buf + padded_words(P.M << LOGC), P.M / 2);
     const uint32_t c0 = tile * C;
     const uint64_t W = 1ull << P.logW;
     const uint32_t len = phase ? P.a + 1 : P.a;
@@ -603,6 +628,52 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
             }
         }
     }
+}
+
+// Inverse with b = W - 1 and a + 1 = Mg a power of two (early mode 3): column
+// W - 1 is the only one with a values, every other column has a + 1 = Mg, and
+// the last row lacks only the value at s = W - 1.  With ones missing value set
+// to 0, each of the two is a full inverse of block size (done in LDS here for
+// the column, by the row pass for the row); the missing value is fixed by a
+// known coefficient, and its share is a rank-one term -- the inverse of a unit
+// vector at point z of a block of size N is (z^-d / N)_d (Lagrange basis).
+//  * column W - 1: coefficient a of P_c is 0, so with B = N x (the full
+//    inverse of (y, 0), unscaled) the missing value is t = -B_a w_a^a,
+//    P_c(w_a) = t, and the coefficients are (B_d - B_a w_a^(a-d)) / Mg;
+//  * last row: its coefficient W - 1 is t, the row pass left r' (inverse of
+//    (y, 0)) in X and r'_{W-1} in V[W - 1], and the coefficients are
+//    r'_d + (t - r'_{W-1}) z^(W-1-d) with z = w_{aW + W - 1}.
+// The columns c < b then invert in full (phase 1).
+template <class Mod>
+__device__ void tail_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0,
+                              const TwoPass<typename Mod::Word>& P) {
+    using Word = typename Mod::Word;
+    __shared__ Word tsh;
+    Word* buf = lds_buf<Word>();
+    const uint32_t Mg = P.a + 1, W = 1u << P.logW, nt = nthreads();
+    const Tables<Word> T = local_tables<Word, false, true>(T0, buf + padded_words(Mg), Mg / 2);
+    const uint32_t maskK = (1u << T.K) - 1;
+    const uint64_t c = W - 1;
+    staged_copy<8>(Mg, [&](uint32_t d) { return d < P.a ? P.X[c + (uint64_t)d * W] : Word(0); },
+                   [&](uint32_t d, Word v) { buf[pad(d)] = v; });
+    __syncthreads();
+    full_inverse<Mod, false>(md, T, buf, 0, 0, Mg, 0);
+    const uint32_t Ea = __builtin_bitreverse32(P.a) >> (32 - T.K);    // w_a = w[K]^Ea
+    if (threadIdx.x == 0) tsh = buf[pad(P.a)];
+    __syncthreads();
+    const Word Ba = tsh;
+    const Word sc = inv_pow2_tw(md, __builtin_ctz(Mg));
+    for (uint32_t d = threadIdx.x; d < P.a; d += nt) {
+        const Word wd = root_pow(md, T, ((P.a - d) * Ea) & maskK);      // w_a^(a-d)
+        P.X[c + (uint64_t)d * W] = md.mul_tw(md.sub(buf[pad(d)], md.mul_tw(Ba, wd)), sc);
+    }
+    const Word t = md.sub(Word(0), md.mul_tw(Ba, root_pow(md, T, (P.a * Ea) & maskK)));
+    const Word D = md.sub(t, P.V[W - 1]);
+    const uint64_t zi = (uint64_t)P.a * W + (W - 1);
+    const uint32_t Ez = __builtin_bitreverse32((uint32_t)zi) >> (32 - T.K);   // z = w[K]^Ez
+    Word* row = P.X + (uint64_t)P.a * W;
+    for (uint32_t d = threadIdx.x; d + 1 < W; d += nt)
+        row[d] = md.add(row[d], md.mul_tw(D, root_pow(md, T, ((W - 1 - d) * Ez) & maskK)));
 }
 
 // Inverse of the last row after its pieces were inverted by the row pass: the
@@ -764,6 +835,10 @@ __global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))
         col_poly_body(md, T, P, p);
         return;
     }
+    if (P.early == 3) {   // the last row (item a) first, then rows 0 .. a-1
+        row_inv_body(md, T, P, blockIdx.x == 0 ? P.a : blockIdx.x - 1);
+        return;
+    }
     // then the last row's pieces (items a ..), then the full rows
     const uint32_t r = blockIdx.x - (q ? 1u : 0u);
     const uint32_t np = __builtin_popcount(P.b);   // the pieces of [0, b): one per set bit
@@ -779,6 +854,11 @@ template <class Mod>
 __global__ __launch_bounds__(kLastThreads) void k_last_inv(Mod md, Tables<typename Mod::Word> T,
                                                            TwoPass<typename Mod::Word> P) {
     last_inv_body(md, T, P);
+}
+template <class Mod>
+__global__ __launch_bounds__(kLastThreads) void k_tail_inv(Mod md, Tables<typename Mod::Word> T,
+                                                           TwoPass<typename Mod::Word> P) {
+    tail_inv_body(md, T, P);
 }
 // The folding step of the space-restricted product (section 5, Algorithm 3):
 // out[j] = sum_t c^t A[j + t L] for j < L with c = w_g (in twiddle form), the

@@ -74,7 +74,9 @@ def test_two_pass_forced_small(ctxs, name, logW):
         ns = sorted({W + 1, 2 * W - 1, 2 * W, 3 * W + 1, 5 * W - 1, 17 * W, 17 * W + 3, 33 * W + W // 2,
                      100 * W + 7, 1000, 2499, 4097, 16 * W + 1, 16 * W + W - 1, 32 * W + 5, 65 * W, 129 * W,
                      64 * W + W // 2, 2 * W + 1, 3 * W, 5 * W + 1, 6 * W + 2, 11 * W + W - 1, 7 * W + 3,
-                     9 * W + 5, 23 * W + 1, 15 * W + W // 3, 127 * W + 1})
+                     9 * W + 5, 23 * W + 1, 15 * W + W // 3, 127 * W + 1,
+                     # b = W - 1 with a + 1 a power of two (one short column)
+                     4 * W - 1, 8 * W - 1, 64 * W - 1, 128 * W - 1})
         for n in ns:
             if n <= W:
                 continue
