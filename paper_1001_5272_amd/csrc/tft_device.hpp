@@ -51,6 +51,15 @@ struct Tables {
 // vector load of the dispatch data that is repeated after every barrier.
 __device__ __forceinline__ uint32_t nthreads() { return __builtin_amdgcn_workgroup_size_x(); }
 
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wave's LDS operations, not for its global loads and stores, so those stay in
+// flight across it (__syncthreads also drains the vector memory counter).
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------- 31-bit primes
 // Residues in [0, p), p < 2^31 odd.  Twiddles are kept in Montgomery form
 // (w 2^32 mod p) so that mul_tw(x, w 2^32) = x w mod p.
@@ -168,7 +177,7 @@ __device__ Tables<Word> local_tables(const Tables<Word>& T, Word* dst, uint32_t 
         if (FWD) dst[i] = T.f1[2 * i];
         if (INV) dst[(FWD ? nl : 0) + i] = T.i1[2 * i];
     }
-    __syncthreads();
+    lds_sync();
     if (FWD) {
         L.lf = dst;
         L.nlf = nl;
@@ -345,7 +354,7 @@ __device__ __forceinline__ void dif_group(const Mod& md, const Tables<typename M
 #pragma unroll
         for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
     }
-    __syncthreads();
+    lds_sync();
 }
 
 // Lane exchange of one word across the wavefront (64-bit words as two halves).
@@ -393,13 +402,13 @@ __device__ void eval_lanes(const Mod& md, const typename Mod::Word* buf, int log
     for (uint32_t o = C; o < 64; o <<= 1) acc = md.add(acc, shfl_xor_word(acc, (int)o));
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane < C) red[wave * C + lane] = acc;
-    __syncthreads();
+    lds_sync();
     if (threadIdx.x < C) {
         Word sum = 0;
         for (uint32_t k = 0; k < (nthreads() >> 6); k++) sum = md.add(sum, red[k * C + threadIdx.x]);
         res[threadIdx.x] = sum;
     }
-    __syncthreads();
+    lds_sync();
 }
 
 // Stages per LDS round trip (1..3, at most `left`) for a pass over `words`
@@ -494,7 +503,7 @@ __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename M
 #pragma unroll
         for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
     }
-    if (SYNC) __syncthreads();
+    if (SYNC) lds_sync();
 }
 
 // Inverse stages 2^d0 .. 2^(d1-1) (0 <= d0 < d1 <= lg Sz) of the block of size
@@ -670,7 +679,7 @@ __device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename
             for (int t = 0; t < 2; t++) buf[pad((base + t * q) * C + c)] = x[t];
         }
     }
-    __syncthreads();
+    lds_sync();
 }
 
 // The passes leave out the butterflies' halvings; a last pass scales each
@@ -698,7 +707,7 @@ __device__ void pieces_inverse(const Mod& md, const Tables<typename Mod::Word>& 
             const int e = 31 - __builtin_clz(x ^ m);
             if (e > 0) buf[pad(it)] = md.mul_tw(buf[pad(it)], scale[e]);
         }
-        __syncthreads();
+        lds_sync();
     }
 }
 
@@ -799,7 +808,7 @@ __device__ void walk_group(const Mod& md, typename Mod::Word* buf, int logC, int
             for (int k = 0; k < R; k++) buf[pad((off + j + (k ^ rmask) * u) * C + c)] = x[k];
         }
     }
-    __syncthreads();
+    lds_sync();
 }
 
 template <class Mod>
@@ -826,7 +835,7 @@ __device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typena
         L.wi[d] = tw_inv(md, T, 2 * v.g);
     }
     if (!skip_full && (m >> 1) != 0) pieces_inverse(md, T, buf, logC, M, m, g0);   // ends with a barrier
-    else __syncthreads();
+    else lds_sync();
     for (int d = 0; d < depth; d += 3) walk_levels(md, buf, logC, d, depth - d < 3 ? depth - d : 3, L, true);
     for (int e = depth; e > 0; e -= 3) {
         const int S = e < 3 ? e : 3;
