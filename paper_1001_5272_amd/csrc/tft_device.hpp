@@ -368,6 +368,26 @@ __device__ __forceinline__ Word shfl_xor_word(Word v, int mask) {
     }
 }
 
+// res[c] = sum of acc over the threads of lane c (thread t is in lane t mod C,
+// C <= 64): lane exchanges across each wavefront, then the wavefronts' sums
+// through red (LDS, (nthreads() / 64) C words).  Ends with a barrier.
+template <class Mod>
+__device__ __forceinline__ void reduce_lanes(const Mod& md, typename Mod::Word acc, int logC, typename Mod::Word* red,
+                                             typename Mod::Word* res) {
+    using Word = typename Mod::Word;
+    const uint32_t C = 1u << logC;
+    for (uint32_t o = C; o < 64; o <<= 1) acc = md.add(acc, shfl_xor_word(acc, (int)o));
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < C) red[wave * C + lane] = acc;
+    lds_sync();
+    if (threadIdx.x < C) {
+        Word sum = 0;
+        for (uint32_t k = 0; k < (nthreads() >> 6); k++) sum = md.add(sum, red[k * C + threadIdx.x]);
+        res[threadIdx.x] = sum;
+    }
+    lds_sync();
+}
+
 // Evaluation at one point for every lane of a tile: res[c] = sum_{d < len}
 // buf[d C + c] z^d (z in twiddle form).  The nthreads() / C threads of a lane
 // each run Horner over one chunk of d and scale by z^(chunk start); the chunk
@@ -399,16 +419,7 @@ __device__ void eval_lanes(const Mod& md, const typename Mod::Word* buf, int log
     Word acc = 0;
     for (uint32_t d = hi; d > lo; d--) acc = md.add(md.mul_tw(acc, z), buf[pad((d - 1) * C + c)]);
     if (lo > 0 && lo < hi) acc = md.mul_tw(acc, zp ? zp[t] : pow_tw(md, z, lo));
-    for (uint32_t o = C; o < 64; o <<= 1) acc = md.add(acc, shfl_xor_word(acc, (int)o));
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane < C) red[wave * C + lane] = acc;
-    lds_sync();
-    if (threadIdx.x < C) {
-        Word sum = 0;
-        for (uint32_t k = 0; k < (nthreads() >> 6); k++) sum = md.add(sum, red[k * C + threadIdx.x]);
-        res[threadIdx.x] = sum;
-    }
-    lds_sync();
+    reduce_lanes(md, acc, logC, red, res);
 }
 
 // Stages per LDS round trip (1..3, at most `left`) for a pass over `words`

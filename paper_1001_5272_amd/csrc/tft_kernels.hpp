@@ -190,18 +190,50 @@ __device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0
             const uint64_t idx = (c0 + c) + (uint64_t)H * W;
             hi0[c] = idx < P.n_src ? P.src[idx] : Word(0);
         }
-        eval_scales(md, LOGC, H, tw_fwd(md, T, H), zp);
-        __syncthreads();
-        for (uint32_t it = threadIdx.x; it < H * C; it += nthreads()) {
-            const uint32_t c = it & (C - 1), d = it >> LOGC;
-            const uint64_t idx = (c0 + c) + (uint64_t)d * W;
-            Word v = idx < P.n_src ? P.src[idx] : Word(0);
-            if (d == 0) v = md.add(v, hi0[c]);
-            buf[pad(it)] = v;
+        if (H >= 16) {
+            // the first radix-8 group straight from HBM (as below), each unit
+            // also adding its share of the evaluation at z = w_H: the rows
+            // u + t H/8 contribute z^u sum_t x_t (z^(H/8))^t
+            __syncthreads();
+            const uint32_t M8 = H >> 3, maskK = (1u << T.K) - 1;
+            const uint32_t EH = __builtin_bitreverse32(H) >> (32 - T.K);   // w_H = w[K]^EH
+            const Word z8 = root_pow(md, T, (M8 * EH) & maskK);
+            Unit<Mod, 3> top;
+            top.load0(T.lf, 0, 0);
+            Word acc = 0;
+            for (uint32_t it = threadIdx.x; it < M8 * C; it += nthreads()) {
+                const uint32_t c = it & (C - 1), u = it >> LOGC;
+                Word x[8];
+#pragma unroll
+                for (int t = 0; t < 8; t++) {
+                    const uint64_t idx = (c0 + c) + (uint64_t)(u + t * M8) * W;
+                    x[t] = idx < P.n_src ? P.src[idx] : Word(0);
+                }
+                if (u == 0) x[0] = md.add(x[0], hi0[c]);
+                Word e = x[7];
+#pragma unroll
+                for (int t = 6; t >= 0; t--) e = md.add(md.mul_tw(e, z8), x[t]);
+                acc = md.add(acc, md.mul_tw(e, root_pow(md, T, (u * EH) & maskK)));
+                top.template forward<true>(md, x);
+#pragma unroll
+                for (int t = 0; t < 8; t++) buf[pad((u + t * M8) * C + c)] = x[t];
+            }
+            reduce_lanes(md, acc, LOGC, red, extra);   // its barriers also publish the tile
+            dif_stages(md, T, buf, LOGC, H, H >> 4, 1, 0, H, 0);
+        } else {
+            eval_scales(md, LOGC, H, tw_fwd(md, T, H), zp);
+            __syncthreads();
+            for (uint32_t it = threadIdx.x; it < H * C; it += nthreads()) {
+                const uint32_t c = it & (C - 1), d = it >> LOGC;
+                const uint64_t idx = (c0 + c) + (uint64_t)d * W;
+                Word v = idx < P.n_src ? P.src[idx] : Word(0);
+                if (d == 0) v = md.add(v, hi0[c]);
+                buf[pad(it)] = v;
+            }
+            __syncthreads();
+            eval_lanes(md, buf, LOGC, H, tw_fwd(md, T, H), red, extra, zp);
+            dif_forward(md, T, buf, LOGC, H, 0, H, 0);
         }
-        __syncthreads();
-        eval_lanes(md, buf, LOGC, H, tw_fwd(md, T, H), red, extra, zp);
-        dif_forward(md, T, buf, LOGC, H, 0, H, 0);
         for (uint32_t it = threadIdx.x; it < (H + 1) * C; it += nthreads()) {
             const uint32_t c = it & (C - 1), d = it >> LOGC;
             const uint64_t idx = (c0 + c) + (uint64_t)d * W;
@@ -511,10 +543,36 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
     // general, k_col_fix) finishes the columns c < b
     const bool every = P.early && phase == 0;
     auto mine_col = [&](uint32_t col) { return every || (phase ? (col < P.b) : (col >= P.b)); };
-    if (!top && len == Mg && Mg >= 64 && !(phase == 0 && P.b)) {
-        // whole columns with nothing evaluated afterwards: the first radix-8
-        // group (stages 1, 2, 4 on eight consecutive rows) straight from HBM,
-        // the last (stages Mg/8, Mg/4, Mg/2) straight to HBM, scaled by 1/Mg
+    // powers for the evaluations at the end, computed first (few waves, and
+    // nothing else is live yet); the next barrier publishes them
+    __shared__ Word ypow[C], zp[kColThreads >> LOGC];   // zp: one power per thread of a lane
+    if (phase == 0 && P.b == 1 && P.nparts && threadIdx.x < C)   // w_{aW}^c
+        ypow[threadIdx.x] = pow_tw(md, tw_fwd(md, T, (uint64_t)P.a << P.logW), c0 + threadIdx.x);
+    // the extra values V_c = P_c(w_a) of the restored columns (sums in
+    // extra[c]) and, with b = 1, this tile's share sum_{c >= 1} V_c w_{aW}^c
+    // of the last-row evaluation (last_inv_body adds the tiles' shares)
+    auto put_extra = [&]() {
+        for (uint32_t c = threadIdx.x; c < C; c += nthreads())
+            if (mine_col(c0 + c)) P.V[c0 + c] = extra[c];
+        if (P.nparts) {
+            if (threadIdx.x < C) {
+                const uint32_t c = c0 + threadIdx.x;
+                last[threadIdx.x] = c >= 1 ? md.mul_tw(extra[threadIdx.x], ypow[threadIdx.x]) : Word(0);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                Word sum = 0;
+                for (uint32_t c = 0; c < C; c++) sum = md.add(sum, last[c]);
+                P.Q[kQStride + tile] = sum;
+            }
+        }
+    };
+    if (!top && len == Mg && Mg >= 64) {
+        // whole columns: the first radix-8 group (stages 1, 2, 4 on eight
+        // consecutive rows) straight from HBM, the last (stages Mg/8, Mg/4,
+        // Mg/2) straight to HBM, scaled by 1/Mg; with b > 0 in phase 0 the last
+        // group's units also add their shares of V_c = P_c(w_a), w_a = w[K]^Ea
+        const bool ev = phase == 0 && P.b;
         const uint32_t M8 = Mg >> 3;
         for (uint32_t it = threadIdx.x; it < M8 * C; it += nthreads()) {
             const uint32_t c = it & (C - 1), i = it >> LOGC;
@@ -533,27 +591,36 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
         const int L = __builtin_ctz(Mg);
         dit_stages<Mod, false>(md, T, buf, LOGC, 0, Mg, 3, L - 3, 0);
         const Word sc = inv_pow2_tw(md, L);
-        Unit<Mod, 3> last;
-        last.load0(T.li, 0, 0);
+        const uint32_t maskK = (1u << T.K) - 1;
+        const uint32_t Ea = __builtin_bitreverse32(P.a) >> (32 - T.K);
+        const Word z8 = ev ? root_pow(md, T, (M8 * Ea) & maskK) : Word(0);
+        Unit<Mod, 3> lastg;
+        lastg.load0(T.li, 0, 0);
+        Word acc = 0;
         for (uint32_t it = threadIdx.x; it < M8 * C; it += nthreads()) {
             const uint32_t c = it & (C - 1), u = it >> LOGC;
             const uint32_t col = c0 + c;
             Word x[8];
 #pragma unroll
             for (int t = 0; t < 8; t++) x[t] = buf[pad((u + t * M8) * C + c)];
-            last.template inverse<false, true>(md, x);
+            lastg.template inverse<false, true>(md, x);
             if (mine_col(col)) {
 #pragma unroll
                 for (int t = 0; t < 8; t++) P.X[col + (uint64_t)(u + t * M8) * W] = md.mul_tw(x[t], sc);
             }
+            if (ev) {
+                Word e = x[7];
+#pragma unroll
+                for (int t = 6; t >= 0; t--) e = md.add(md.mul_tw(e, z8), x[t]);
+                acc = md.add(acc, md.mul_tw(e, root_pow(md, T, (u * Ea) & maskK)));
+            }
+        }
+        if (ev) {
+            reduce_lanes(md, md.mul_tw(acc, sc), LOGC, red, extra);
+            put_extra();
         }
         return;
     }
-    // powers for the evaluations at the end, computed first (few waves, and
-    // nothing else is live yet); the next barrier publishes them
-    __shared__ Word ypow[C], zp[kColThreads >> LOGC];   // zp: one power per thread of a lane
-    if (phase == 0 && P.b == 1 && P.nparts && threadIdx.x < C)   // w_{aW}^c
-        ypow[threadIdx.x] = pow_tw(md, tw_fwd(md, T, (uint64_t)P.a << P.logW), c0 + threadIdx.x);
     if (phase == 0 && P.b) eval_scales(md, LOGC, P.a, tw_fwd(md, T, P.a), zp);
     staged_copy<8>(Mb * C, [&](uint32_t it) {
         const uint32_t c = it & (C - 1), d = it >> LOGC;
@@ -611,22 +678,7 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
         // the extra value V_c = P_c(w_a) of the restored column (early mode:
         // for c < b the same evaluation gives C0(w_H), H = a)
         eval_lanes(md, buf, LOGC, P.a, tw_fwd(md, T, P.a), red, extra, zp);
-        for (uint32_t c = threadIdx.x; c < C; c += nthreads())
-            if (mine_col(c0 + c)) P.V[c0 + c] = extra[c];
-        if (P.nparts) {
-            // b = 1: this tile's share sum_{c >= 1} V_c w_{aW}^c of the last-row
-            // evaluation (last_inv_body adds the tiles' shares)
-            if (threadIdx.x < C) {
-                const uint32_t c = c0 + threadIdx.x;
-                last[threadIdx.x] = c >= 1 ? md.mul_tw(extra[threadIdx.x], ypow[threadIdx.x]) : Word(0);
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                Word sum = 0;
-                for (uint32_t c = 0; c < C; c++) sum = md.add(sum, last[c]);
-                P.Q[kQStride + tile] = sum;
-            }
-        }
+        put_extra();
     }
 }
 
