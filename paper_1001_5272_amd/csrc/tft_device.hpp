@@ -639,11 +639,16 @@ __host__ __device__ __forceinline__ int gitft_depth(uint32_t M, uint32_t m) {
 // 2^(s0+S) are unions of aligned blocks of that size, which together fill
 // [0, mS) (m rounded down to a multiple of 2^(s0+S)) and take radix-2^S
 // units, while the pieces for bits s0+2 and s0+1 of m (below s0+S) take their
-// last two or one stages here.  One barrier per pass.
+// last two or one stages here.  One barrier per pass.  The butterflies leave
+// out the halvings: a unit whose piece this pass completes (piece size
+// 2^(s0+S), 2^(s0+2) or 2^(s0+1)) scales its values by 2^-e from scale[e].
+// With tab set the block sits at global index 0 and its twiddles come from tab
+// (see Unit::load0).
 template <class Mod, int S>
 __device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename Mod::Word>& T,
                                             typename Mod::Word* buf, int logC, uint32_t m, uint64_t gbase,
-                                            uint32_t s0) {
+                                            uint32_t s0, const typename Mod::Word* scale,
+                                            const typename Mod::Word* tab, uint32_t sh) {
     using Word = typename Mod::Word;
     constexpr int R = 1 << S;
     const uint32_t C = 1u << logC;
@@ -657,6 +662,13 @@ __device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename
     Unit<Mod, S> uS;
     Unit<Mod, 2> u4;
     Unit<Mod, 1> u2;
+    if (tab) {
+        if (n4) u4.load0(tab, sh, off4 >> (s0 + 2));
+        if (n2) u2.load0(tab, sh, off2 >> (s0 + 1));
+    } else {
+        if (n4) u4.load_inv(md, T, (gbase + off4) >> (s0 + 2));
+        if (n2) u2.load_inv(md, T, (gbase + off2) >> (s0 + 1));
+    }
     for (uint32_t it = threadIdx.x; it < items; it += nthreads()) {
         const uint32_t c = it & (C - 1);
         const uint32_t u = it >> logC;
@@ -666,8 +678,14 @@ __device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename
             Word x[R];
 #pragma unroll
             for (int t = 0; t < R; t++) x[t] = buf[pad((base + t * q) * C + c)];
-            uS.load_inv(md, T, (gbase >> (s0 + S)) + i);
+            if (tab) uS.load0(tab, sh, i);
+            else uS.load_inv(md, T, (gbase >> (s0 + S)) + i);
             uS.template inverse<false>(md, x);
+            if (31 - __builtin_clz(base ^ m) == (int)(s0 + S)) {   // the unit's piece is complete
+                const Word sc = scale[s0 + S];
+#pragma unroll
+                for (int t = 0; t < R; t++) x[t] = md.mul_tw(x[t], sc);
+            }
 #pragma unroll
             for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
         } else if (u < nS + n4) {
@@ -675,27 +693,26 @@ __device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename
             Word x[4];
 #pragma unroll
             for (int t = 0; t < 4; t++) x[t] = buf[pad((base + t * q) * C + c)];
-            u4.load_inv(md, T, (gbase + off4) >> (s0 + 2));
             u4.template inverse<false>(md, x);
+            const Word sc = scale[s0 + 2];
 #pragma unroll
-            for (int t = 0; t < 4; t++) buf[pad((base + t * q) * C + c)] = x[t];
+            for (int t = 0; t < 4; t++) buf[pad((base + t * q) * C + c)] = md.mul_tw(x[t], sc);
         } else {
             const uint32_t base = off2 + (u - nS - n4);
             Word x[2];
 #pragma unroll
             for (int t = 0; t < 2; t++) x[t] = buf[pad((base + t * q) * C + c)];
-            u2.load_inv(md, T, (gbase + off2) >> (s0 + 1));
             u2.template inverse<false>(md, x);
+            const Word sc = scale[s0 + 1];
 #pragma unroll
-            for (int t = 0; t < 2; t++) buf[pad((base + t * q) * C + c)] = x[t];
+            for (int t = 0; t < 2; t++) buf[pad((base + t * q) * C + c)] = md.mul_tw(x[t], sc);
         }
     }
     lds_sync();
 }
 
-// The passes leave out the butterflies' halvings; a last pass scales each
-// position by 2^-e, e the size exponent of its piece (the highest bit in which
-// the position differs from m).
+// The full inverses of the pieces (see pieces_pass), each scaled by 2^-e for
+// its size 2^e in the pass that completes it.
 template <class Mod>
 __device__ void pieces_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                                uint32_t M, uint32_t m, uint64_t g0) {
@@ -703,22 +720,22 @@ __device__ void pieces_inverse(const Mod& md, const Tables<typename Mod::Word>& 
     __shared__ Word scale[32];
     const uint64_t gbase = g0 << __builtin_ctz(M);   // global position of the block's first word
     const int top = 31 - __builtin_clz(m);            // largest piece: 2^top
+    if (top == 0) return;
     if (threadIdx.x <= (uint32_t)top) scale[threadIdx.x] = inv_pow2_tw(md, (int)threadIdx.x);
+    lds_sync();
+    // block 0: twiddles w_{2x}^-1 from the LDS copy or read in place from i1
+    const Word* tab = nullptr;
+    uint32_t sh = 0;
+    if (g0 == 0) {
+        tab = T.nli >= (M >> 1) ? T.li : T.i1;
+        sh = T.nli >= (M >> 1) ? 0u : 1u;
+    }
     for (int s0 = 0; s0 < top;) {
         const int S = group_stages(m << logC, top - s0);
-        if (S == 3) pieces_pass<Mod, 3>(md, T, buf, logC, m, gbase, (uint32_t)s0);
-        else if (S == 2) pieces_pass<Mod, 2>(md, T, buf, logC, m, gbase, (uint32_t)s0);
-        else pieces_pass<Mod, 1>(md, T, buf, logC, m, gbase, (uint32_t)s0);
+        if (S == 3) pieces_pass<Mod, 3>(md, T, buf, logC, m, gbase, (uint32_t)s0, scale, tab, sh);
+        else if (S == 2) pieces_pass<Mod, 2>(md, T, buf, logC, m, gbase, (uint32_t)s0, scale, tab, sh);
+        else pieces_pass<Mod, 1>(md, T, buf, logC, m, gbase, (uint32_t)s0, scale, tab, sh);
         s0 += S;
-    }
-    if (top > 0) {
-        const uint32_t items = m << logC;
-        for (uint32_t it = threadIdx.x; it < items; it += nthreads()) {
-            const uint32_t x = it >> logC;
-            const int e = 31 - __builtin_clz(x ^ m);
-            if (e > 0) buf[pad(it)] = md.mul_tw(buf[pad(it)], scale[e]);
-        }
-        lds_sync();
     }
 }
 
