@@ -409,7 +409,7 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
         launch(ctx, TFT_K_LAST_INV, tft::k_last_inv<Mod>, dim3(1), dim3(tft::kLastThreads), P.lds_row, st, md, T, G);
         if (G.early == 2) {
             const uint32_t gx = (uint32_t)((P.b + kThreads - 1) / kThreads);
-            const uint32_t gy = (uint32_t)std::min<uint64_t>(P.a, std::max<uint64_t>(1, 4096 / gx));
+            const uint32_t gy = (uint32_t)((P.a + tft::kFixRows - 1) / tft::kFixRows);
             launch(ctx, TFT_K_COL_FIX, tft::k_col_fix<Mod>, dim3(gx, gy), dim3(kThreads), 0, st, md, G);
         } else if (!G.early) {   // columns c < b, after the last row
             if (P.b <= kFewColumns) {

@@ -171,7 +171,7 @@ __device__ __forceinline__ typename Mod::Word root_pow_inv(const Mod& md, const 
 // replaces a dependent global load at the start of every stage group.
 // FWD / INV: copy only that direction's table (nl words).
 template <class Word, bool FWD = true, bool INV = true>
-__device__ Tables<Word> local_tables(const Tables<Word>& T, Word* dst, uint32_t nl) {
+__device__ __forceinline__ Tables<Word> local_tables(const Tables<Word>& T, Word* dst, uint32_t nl) {
     Tables<Word> L = T;
     for (uint32_t i = threadIdx.x; i < nl; i += nthreads()) {
         if (FWD) dst[i] = T.f1[2 * i];
@@ -407,7 +407,7 @@ __device__ __forceinline__ void eval_scales(const Mod& md, int logC, uint32_t le
 }
 
 template <class Mod>
-__device__ void eval_lanes(const Mod& md, const typename Mod::Word* buf, int logC, uint32_t len, typename Mod::Word z,
+__device__ __forceinline__ void eval_lanes(const Mod& md, const typename Mod::Word* buf, int logC, uint32_t len, typename Mod::Word z,
                            typename Mod::Word* red, typename Mod::Word* res, const typename Mod::Word* zp = nullptr) {
     using Word = typename Mod::Word;
     const uint32_t C = 1u << logC;
@@ -440,7 +440,7 @@ __device__ __forceinline__ int group_stages(uint32_t words, int left) {
 // Stages h_hi, h_hi/2, ..., h_lo (powers of two, h_lo <= h_hi <= M/2) of the
 // forward transform of that block, in groups of at most three.
 template <class Mod>
-__device__ void dif_stages(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+__device__ __forceinline__ void dif_stages(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                            uint32_t M, uint32_t h_hi, uint32_t h_lo, uint32_t out_lo, uint32_t out_hi, uint64_t g0) {
     const uint32_t words = M << logC;
     const int lo = __builtin_ctz(h_lo);
@@ -478,7 +478,7 @@ __device__ void dif_stages(const Mod& md, const Tables<typename Mod::Word>& T, t
 // F mod (x^M - w_{g0})); only blocks meeting [out_lo, out_hi) are computed, so
 // positions outside that range end with unspecified values.
 template <class Mod>
-__device__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+__device__ __forceinline__ void dif_forward(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                             uint32_t M, uint32_t out_lo, uint32_t out_hi, uint64_t g0) {
     if (M >= 2) dif_stages(md, T, buf, logC, M, M >> 1, 1, out_lo, out_hi, g0);
 }
@@ -520,7 +520,7 @@ __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename M
 // Inverse stages 2^d0 .. 2^(d1-1) (0 <= d0 < d1 <= lg Sz) of the block of size
 // Sz at offset off with global block index g, in groups of at most three.
 template <class Mod, bool HALF = true>
-__device__ void dit_stages(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+__device__ __forceinline__ void dit_stages(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                            uint32_t off, uint32_t Sz, int d0, int d1, uint64_t g) {
     const int L = __builtin_ctz(Sz);
     const uint32_t words = Sz << logC;
@@ -553,7 +553,7 @@ __device__ void dit_stages(const Mod& md, const Tables<typename Mod::Word>& T, t
 // global block index g: stages 1, 2, ..., Sz/2.  HALF = false leaves every
 // value multiplied by Sz (the caller scales by 1/Sz, e.g. on its store).
 template <class Mod, bool HALF = true>
-__device__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+__device__ __forceinline__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                              uint32_t off, uint32_t Sz, uint64_t g) {
     if (Sz >= 2) dit_stages<Mod, HALF>(md, T, buf, logC, off, Sz, 0, __builtin_ctz(Sz), g);
 }
@@ -714,7 +714,7 @@ __device__ __forceinline__ void pieces_pass(const Mod& md, const Tables<typename
 // The full inverses of the pieces (see pieces_pass), each scaled by 2^-e for
 // its size 2^e in the pass that completes it.
 template <class Mod>
-__device__ void pieces_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+__device__ __forceinline__ void pieces_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                                uint32_t M, uint32_t m, uint64_t g0) {
     using Word = typename Mod::Word;
     __shared__ Word scale[32];
@@ -763,7 +763,7 @@ constexpr uint32_t kRightBit = 1u << 31;
 //     right, C0_j = lo_j + w hi_j on the left) for j in the level's range;
 //   down = false: the upward steps, deepest level first.
 template <class Mod, int S>
-__device__ void walk_group(const Mod& md, typename Mod::Word* buf, int logC, int d0,
+__device__ __forceinline__ void walk_group(const Mod& md, typename Mod::Word* buf, int logC, int d0,
                            const WalkTable<typename Mod::Word>& L, bool down) {
     using Word = typename Mod::Word;
     constexpr int R = 1 << S;
@@ -840,7 +840,7 @@ __device__ void walk_group(const Mod& md, typename Mod::Word* buf, int logC, int
 }
 
 template <class Mod>
-__device__ void walk_levels(const Mod& md, typename Mod::Word* buf, int logC, int d0, int S,
+__device__ __forceinline__ void walk_levels(const Mod& md, typename Mod::Word* buf, int logC, int d0, int S,
                             const WalkTable<typename Mod::Word>& L, bool down) {
     if (S == 3) walk_group<Mod, 3>(md, buf, logC, d0, L, down);
     else if (S == 2) walk_group<Mod, 2>(md, buf, logC, d0, L, down);
@@ -848,7 +848,7 @@ __device__ void walk_levels(const Mod& md, typename Mod::Word* buf, int logC, in
 }
 
 template <class Mod>
-__device__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
+__device__ __forceinline__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                       uint32_t M, uint32_t m, uint64_t g0, bool skip_full = false) {
     using Word = typename Mod::Word;
     __shared__ WalkTable<Word> L;

@@ -51,7 +51,7 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t x, uint32_t tiles) {
 
 // ------------------------------------------------------ single workgroup
 template <class Mod>
-__device__ void small_forward_body(const Mod& md, const Tables<typename Mod::Word>& T0, typename Mod::Word* X,
+__device__ __forceinline__ void small_forward_body(const Mod& md, const Tables<typename Mod::Word>& T0, typename Mod::Word* X,
                                    uint32_t n, uint32_t M, uint64_t g0 = 0) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
@@ -63,7 +63,7 @@ __device__ void small_forward_body(const Mod& md, const Tables<typename Mod::Wor
 }
 
 template <class Mod>
-__device__ void small_inverse_body(const Mod& md, const Tables<typename Mod::Word>& T0, typename Mod::Word* X,
+__device__ __forceinline__ void small_inverse_body(const Mod& md, const Tables<typename Mod::Word>& T0, typename Mod::Word* X,
                                    uint32_t n, uint32_t M) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
@@ -77,7 +77,7 @@ __device__ void small_inverse_body(const Mod& md, const Tables<typename Mod::Wor
 // Whole product in one workgroup: both operands zero-extended to M words of
 // LDS, forward transforms truncated to r outputs, pointwise product, inverse.
 template <class Mod>
-__device__ void small_mul_body(const Mod& md, const Tables<typename Mod::Word>& T0, const typename Mod::Word* A,
+__device__ __forceinline__ void small_mul_body(const Mod& md, const Tables<typename Mod::Word>& T0, const typename Mod::Word* A,
                                uint32_t m, const typename Mod::Word* B, uint32_t nb, typename Mod::Word* X,
                                uint32_t M) {
     using Word = typename Mod::Word;
@@ -155,7 +155,7 @@ constexpr int kLastThreads = 1024;   // the last-row inverse is one workgroup: g
 // an LDS block of M = 2^ceil(lg Lout) words per column, writes the outputs
 // that have a slot and the extra value P_c(w_a) of columns c >= b to V[c].
 template <class Mod, int LOGC>
-__device__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0,
+__device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0,
                              const TwoPass<typename Mod::Word>& P, uint32_t tile) {
     using Word = typename Mod::Word;
     constexpr uint32_t C = 1u << LOGC;
@@ -313,7 +313,7 @@ __device__ __forceinline__ void store8(Word* p, const Word (&x)[8]) {
 // Forward transform of row g (block F mod (x^W - w_g)) in place at row,
 // twisted to block index 0 as described in row_fwd_body.
 template <class Mod>
-__device__ void row_fwd_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+__device__ __forceinline__ void row_fwd_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
                               typename Mod::Word* row, uint32_t logW, uint64_t g) {
     using Word = typename Mod::Word;
     const uint32_t W = 1u << logW, W8 = W >> 3, nt = nthreads(), maskK = (1u << T.K) - 1;
@@ -347,7 +347,7 @@ __device__ void row_fwd_fused(const Mod& md, const Tables<typename Mod::Word>& T
 // PART: only words below lim < W exist at row (and yr); the missing ones enter
 // as 0 and the coefficient at index lim is stored to *beyond.
 template <class Mod, bool PART = false>
-__device__ void row_inv_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+__device__ __forceinline__ void row_inv_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
                               typename Mod::Word* row, const typename Mod::Word* yr, uint32_t logW, uint64_t g,
                               uint32_t lim = 0, typename Mod::Word* beyond = nullptr) {
     using Word = typename Mod::Word;
@@ -409,7 +409,7 @@ __device__ void row_inv_fused(const Mod& md, const Tables<typename Mod::Word>& T
 // size W); row a (when b > 0) is built from its b slots and V_c (c >= b) and
 // keeps b outputs.
 template <class Mod>
-__device__ void row_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T,
+__device__ __forceinline__ void row_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T,
                              const TwoPass<typename Mod::Word>& P, uint32_t j) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
@@ -451,7 +451,7 @@ __device__ void row_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T,
 // in parallel with the rows).  With P.Y set, values are first multiplied
 // pointwise by Y (the product step fused into the load).
 template <class Mod>
-__device__ void row_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
+__device__ __forceinline__ void row_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
                              const TwoPass<typename Mod::Word>& P, uint32_t k) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
@@ -523,7 +523,7 @@ __host__ __device__ inline uint32_t row_inv_items(uint32_t W, uint32_t a, uint32
 // restored coefficients; phase 1 handles c < b (length a + 1).  Columns of the
 // other class inside the tile are skipped.
 template <class Mod, int LOGC>
-__device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0,
+__device__ __forceinline__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0,
                              const TwoPass<typename Mod::Word>& P, int phase, uint32_t tile) {
     using Word = typename Mod::Word;
     constexpr uint32_t C = 1u << LOGC;
@@ -697,7 +697,7 @@ __device__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0
 //    r'_d + (t - r'_{W-1}) z^(W-1-d) with z = w_{aW + W - 1}.
 // The columns c < b then invert in full (phase 1).
 template <class Mod>
-__device__ void tail_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0,
+__device__ __forceinline__ void tail_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0,
                               const TwoPass<typename Mod::Word>& P) {
     using Word = typename Mod::Word;
     __shared__ Word tsh;
@@ -738,7 +738,7 @@ __device__ void tail_inv_body(const Mod& md, const Tables<typename Mod::Word>& T
 // col_inv_body): their top coefficient is x_H = (C0(w_H) - P_c(w_a)) / 2, with
 // C0(w_H) left in V[c], and x_0 = C0_0 - x_H.
 template <class Mod>
-__device__ void last_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
+__device__ __forceinline__ void last_inv_body(const Mod& md, const Tables<typename Mod::Word>& T,
                               const TwoPass<typename Mod::Word>& P) {
     using Word = typename Mod::Word;
     __shared__ Word red[kLastThreads / 64], val[1];
@@ -805,7 +805,7 @@ __device__ typename Mod::Word pow_normal(const Mod& md, typename Mod::Word x, ui
 }
 
 template <class Mod>
-__device__ void col_poly_body(const Mod& md, const Tables<typename Mod::Word>& T,
+__device__ __forceinline__ void col_poly_body(const Mod& md, const Tables<typename Mod::Word>& T,
                               const TwoPass<typename Mod::Word>& P, uint64_t p) {
     using Word = typename Mod::Word;
     const uint32_t a = P.a;
@@ -999,7 +999,9 @@ __global__ __launch_bounds__(kThreads) void k_fill_index(Word* X, uint64_t n, ui
 }
 
 // X[c + d W] += t_c Q_d for c < b, d < a (t_c in the last-row slot of column c);
-// grid: x over columns (kThreads each), y over strided rows d.
+// grid: x over columns (kThreads each), y over groups of kFixRows rows, whose
+// loads a thread issues together.
+constexpr uint32_t kFixRows = 8;
 template <class Mod>
 __global__ __launch_bounds__(kThreads) void k_col_fix(Mod md, TwoPass<typename Mod::Word> P) {
     using Word = typename Mod::Word;
@@ -1007,10 +1009,14 @@ __global__ __launch_bounds__(kThreads) void k_col_fix(Mod md, TwoPass<typename M
     if (c >= P.b) return;
     const uint64_t W = 1ull << P.logW;
     const Word t = P.X[(uint64_t)P.a * W + c];
-    for (uint32_t d = blockIdx.y; d < P.a; d += gridDim.y) {
-        Word* x = P.X + c + (uint64_t)d * W;
-        *x = md.add(*x, md.mul(t, P.Q[d]));
-    }
+    const uint32_t d0 = blockIdx.y * kFixRows;
+    Word x[kFixRows];
+#pragma unroll
+    for (uint32_t k = 0; k < kFixRows; k++)
+        if (d0 + k < P.a) x[k] = P.X[c + (uint64_t)(d0 + k) * W];
+#pragma unroll
+    for (uint32_t k = 0; k < kFixRows; k++)
+        if (d0 + k < P.a) P.X[c + (uint64_t)(d0 + k) * W] = md.add(x[k], md.mul(t, P.Q[d0 + k]));
 }
 
 // ---- batches: every workgroup takes one (record, index) item of a work list
