@@ -246,7 +246,8 @@ typedef enum {
     TFT_K_ROW_INV,         /* inverse row pass */
     TFT_K_COL_INV_SHORT,   /* inverse columns c >= b (single transforms with b > 0: every column on
                               its first a values), re-deriving the extra evaluations */
-    TFT_K_LAST_INV,        /* inverse of the partial last row */
+    TFT_K_LAST_INV,        /* inverse of the partial last row (or, for b = W - 1 with a + 1 a
+                              power of two, the one short column and the last row's fix) */
     TFT_K_COL_INV_LONG,    /* inverse columns c < b (batches) */
     TFT_K_POINTWISE,       /* pointwise product */
     TFT_K_COPY,            /* zero-extending copy, counter reset, signed-to-residue */
