@@ -519,13 +519,15 @@ __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename M
 
 // Inverse stages 2^d0 .. 2^(d1-1) (0 <= d0 < d1 <= lg Sz) of the block of size
 // Sz at offset off with global block index g, in groups of at most three.
-template <class Mod, bool HALF = true>
+// RADIX8: always three stages per pass (a latency-bound single workgroup
+// prefers fewer barriers to more busy lanes).
+template <class Mod, bool HALF = true, bool RADIX8 = false>
 __device__ __forceinline__ void dit_stages(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                            uint32_t off, uint32_t Sz, int d0, int d1, uint64_t g) {
     const int L = __builtin_ctz(Sz);
     const uint32_t words = Sz << logC;
     for (int done = d0; done < d1;) {    // stages 2^d0 .. 2^(done-1) finished
-        const int S = group_stages(words, d1 - done);
+        const int S = RADIX8 ? (d1 - done < 3 ? d1 - done : 3) : group_stages(words, d1 - done);
         const uint32_t h = 1u << (done + S - 1);
         if (g == 0) {   // block 0: twiddles as in dif_stages; the last group skips twiddle 1
             const bool lds = T.nli >= (Sz >> 1);
@@ -552,10 +554,10 @@ __device__ __forceinline__ void dit_stages(const Mod& md, const Tables<typename 
 // Full inverse of the forward stages on the block of size Sz at offset off with
 // global block index g: stages 1, 2, ..., Sz/2.  HALF = false leaves every
 // value multiplied by Sz (the caller scales by 1/Sz, e.g. on its store).
-template <class Mod, bool HALF = true>
+template <class Mod, bool HALF = true, bool RADIX8 = false>
 __device__ __forceinline__ void full_inverse(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
                              uint32_t off, uint32_t Sz, uint64_t g) {
-    if (Sz >= 2) dit_stages<Mod, HALF>(md, T, buf, logC, off, Sz, 0, __builtin_ctz(Sz), g);
+    if (Sz >= 2) dit_stages<Mod, HALF, RADIX8>(md, T, buf, logC, off, Sz, 0, __builtin_ctz(Sz), g);
 }
 
 // 2^-L in twiddle form.
@@ -762,9 +764,17 @@ constexpr uint32_t kRightBit = 1u << 31;
 //   down = true: the known-coefficient steps (C1_j = C0_j - 2 w hi_j on the
 //     right, C0_j = lo_j + w hi_j on the left) for j in the level's range;
 //   down = false: the upward steps, deepest level first.
-template <class Mod, int S>
+// The upward steps write their results through sink(position, lane, value)
+// (LdsSink: back into the tile).
+template <class Word>
+struct LdsSink {
+    Word* buf;
+    uint32_t C;
+    __device__ __forceinline__ void operator()(uint32_t p, uint32_t c, Word v) const { buf[pad(p * C + c)] = v; }
+};
+template <class Mod, int S, class Sink>
 __device__ __forceinline__ void walk_group(const Mod& md, typename Mod::Word* buf, int logC, int d0,
-                           const WalkTable<typename Mod::Word>& L, bool down) {
+                           const WalkTable<typename Mod::Word>& L, bool down, const Sink& sink) {
     using Word = typename Mod::Word;
     constexpr int R = 1 << S;
     const uint32_t C = 1u << logC;
@@ -833,23 +843,26 @@ __device__ __forceinline__ void walk_group(const Mod& md, typename Mod::Word* bu
                 }
             }
 #pragma unroll
-            for (int k = 0; k < R; k++) buf[pad((off + j + (k ^ rmask) * u) * C + c)] = x[k];
+            for (int k = 0; k < R; k++) sink(off + j + (k ^ rmask) * u, c, x[k]);
         }
     }
     lds_sync();
 }
 
-template <class Mod>
+template <class Mod, class Sink>
 __device__ __forceinline__ void walk_levels(const Mod& md, typename Mod::Word* buf, int logC, int d0, int S,
-                            const WalkTable<typename Mod::Word>& L, bool down) {
-    if (S == 3) walk_group<Mod, 3>(md, buf, logC, d0, L, down);
-    else if (S == 2) walk_group<Mod, 2>(md, buf, logC, d0, L, down);
-    else walk_group<Mod, 1>(md, buf, logC, d0, L, down);
+                            const WalkTable<typename Mod::Word>& L, bool down, const Sink& sink) {
+    if (S == 3) walk_group<Mod, 3>(md, buf, logC, d0, L, down, sink);
+    else if (S == 2) walk_group<Mod, 2>(md, buf, logC, d0, L, down, sink);
+    else walk_group<Mod, 1>(md, buf, logC, d0, L, down, sink);
 }
 
-template <class Mod>
+// final (optional): where the last upward pass writes the finished block
+// (position, lane, value) instead of the tile; without a walk the block is
+// copied to it from the tile.
+template <class Mod, class Sink = LdsSink<typename Mod::Word>>
 __device__ __forceinline__ void gitft(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf, int logC,
-                      uint32_t M, uint32_t m, uint64_t g0, bool skip_full = false) {
+                      uint32_t M, uint32_t m, uint64_t g0, bool skip_full = false, const Sink* final = nullptr) {
     using Word = typename Mod::Word;
     __shared__ WalkTable<Word> L;
     const int depth = gitft_depth(M, m);
@@ -864,10 +877,16 @@ __device__ __forceinline__ void gitft(const Mod& md, const Tables<typename Mod::
     }
     if (!skip_full && (m >> 1) != 0) pieces_inverse(md, T, buf, logC, M, m, g0);   // ends with a barrier
     else lds_sync();
-    for (int d = 0; d < depth; d += 3) walk_levels(md, buf, logC, d, depth - d < 3 ? depth - d : 3, L, true);
+    const LdsSink<Word> tile{buf, 1u << logC};
+    for (int d = 0; d < depth; d += 3) walk_levels(md, buf, logC, d, depth - d < 3 ? depth - d : 3, L, true, tile);
     for (int e = depth; e > 0; e -= 3) {
         const int S = e < 3 ? e : 3;
-        walk_levels(md, buf, logC, e - S, S, L, false);
+        if (final && e == S) walk_levels(md, buf, logC, e - S, S, L, false, *final);
+        else walk_levels(md, buf, logC, e - S, S, L, false, tile);
+    }
+    if (final && depth == 0) {
+        for (uint32_t it = threadIdx.x; it < (M << logC); it += nthreads())
+            (*final)(it >> logC, it & ((1u << logC) - 1), buf[pad(it)]);
     }
 }
 

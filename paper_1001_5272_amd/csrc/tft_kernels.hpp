@@ -663,6 +663,15 @@ __device__ __forceinline__ void col_inv_body(const Mod& md, const Tables<typenam
         }
         for (uint32_t it = threadIdx.x; it < Mg * C; it += nthreads()) buf[pad(it)] = md.mul_tw(buf[pad(it)], sc);
         __syncthreads();
+    } else if (!(phase == 0 && P.b)) {
+        // nothing is evaluated afterwards: the walk's last upward pass writes
+        // the column values straight to HBM
+        auto out = [&](uint32_t d, uint32_t c, Word v) {
+            const uint32_t col = c0 + c;
+            if (d < len && mine_col(col)) P.X[col + (uint64_t)d * W] = v;
+        };
+        gitft(md, T, buf, LOGC, Mg, len, 0, false, &out);
+        return;
     } else {
         gitft(md, T, buf, LOGC, Mg, len, 0);
     }
@@ -700,32 +709,63 @@ template <class Mod>
 __device__ __forceinline__ void tail_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0,
                               const TwoPass<typename Mod::Word>& P) {
     using Word = typename Mod::Word;
+    constexpr uint32_t kRowPer = 8;   // last-row words per thread held from the start
     __shared__ Word tsh;
     Word* buf = lds_buf<Word>();
     const uint32_t Mg = P.a + 1, W = 1u << P.logW, nt = nthreads();
-    const Tables<Word> T = local_tables<Word, false, true>(T0, buf + padded_words(Mg), Mg / 2);
-    const uint32_t maskK = (1u << T.K) - 1;
+    const uint32_t maskK = (1u << T0.K) - 1;
     const uint64_t c = W - 1;
+    Word* row = P.X + (uint64_t)P.a * W;
+    // everything that does not depend on the column's inverse is loaded first,
+    // so that its memory latency overlaps the column work: the last row's
+    // words, r'_{W-1}, and the powers used below
+    const uint32_t Ea = __builtin_bitreverse32(P.a) >> (32 - T0.K);                   // w_a = w[K]^Ea
+    const uint64_t zi = (uint64_t)P.a * W + (W - 1);
+    const uint32_t Ez = __builtin_bitreverse32((uint32_t)zi) >> (32 - T0.K);          // z = w[K]^Ez
+    const bool held = W - 1 <= kRowPer * nt;
+    Word rv[kRowPer];
+    if (held) {
+#pragma unroll
+        for (uint32_t k = 0; k < kRowPer; k++) {
+            const uint32_t d = threadIdx.x + k * nt;
+            rv[k] = d + 1 < W ? row[d] : Word(0);
+        }
+    }
+    const Word rlast = P.V[W - 1];
+    const Word waa = root_pow(md, T0, (P.a * Ea) & maskK);                               // w_a^a
+    Word f = root_pow(md, T0, ((P.a - threadIdx.x) * Ea) & maskK);                      // w_a^(a-d)
+    const Word fs = root_pow(md, T0, ((0u - nt) * Ea) & maskK);                         // w_a^-nt
+    const Word gz = root_pow(md, T0, ((W - 1 - threadIdx.x) * Ez) & maskK);             // z^(W-1-d)
+    const Word gs = root_pow(md, T0, ((0u - nt) * Ez) & maskK);                         // z^-nt
+    const Tables<Word> T = local_tables<Word, false, true>(T0, buf + padded_words(Mg), Mg / 2);
     staged_copy<8>(Mg, [&](uint32_t d) { return d < P.a ? P.X[c + (uint64_t)d * W] : Word(0); },
                    [&](uint32_t d, Word v) { buf[pad(d)] = v; });
     __syncthreads();
-    full_inverse<Mod, false>(md, T, buf, 0, 0, Mg, 0);
-    const uint32_t Ea = __builtin_bitreverse32(P.a) >> (32 - T.K);    // w_a = w[K]^Ea
+    full_inverse<Mod, false, true>(md, T, buf, 0, 0, Mg, 0);
     if (threadIdx.x == 0) tsh = buf[pad(P.a)];
     __syncthreads();
     const Word Ba = tsh;
     const Word sc = inv_pow2_tw(md, __builtin_ctz(Mg));
     for (uint32_t d = threadIdx.x; d < P.a; d += nt) {
-        const Word wd = root_pow(md, T, ((P.a - d) * Ea) & maskK);      // w_a^(a-d)
-        P.X[c + (uint64_t)d * W] = md.mul_tw(md.sub(buf[pad(d)], md.mul_tw(Ba, wd)), sc);
+        P.X[c + (uint64_t)d * W] = md.mul_tw(md.sub(buf[pad(d)], md.mul_tw(Ba, f)), sc);
+        f = md.tw_mul_tw(f, fs);
     }
-    const Word t = md.sub(Word(0), md.mul_tw(Ba, root_pow(md, T, (P.a * Ea) & maskK)));
-    const Word D = md.sub(t, P.V[W - 1]);
-    const uint64_t zi = (uint64_t)P.a * W + (W - 1);
-    const uint32_t Ez = __builtin_bitreverse32((uint32_t)zi) >> (32 - T.K);   // z = w[K]^Ez
-    Word* row = P.X + (uint64_t)P.a * W;
-    for (uint32_t d = threadIdx.x; d + 1 < W; d += nt)
-        row[d] = md.add(row[d], md.mul_tw(D, root_pow(md, T, ((W - 1 - d) * Ez) & maskK)));
+    const Word t = md.sub(Word(0), md.mul_tw(Ba, waa));
+    const Word D = md.sub(t, rlast);
+    Word g = md.mul_tw(D, gz);                                                          // D z^(W-1-d)
+    if (held) {
+#pragma unroll
+        for (uint32_t k = 0; k < kRowPer; k++) {
+            const uint32_t d = threadIdx.x + k * nt;
+            if (d + 1 < W) row[d] = md.add(rv[k], g);
+            g = md.mul_tw(g, gs);
+        }
+    } else {
+        staged_copy<8>(W - 1, [&](uint32_t d) { return row[d]; }, [&](uint32_t d, Word v) {
+            row[d] = md.add(v, g);
+            g = md.mul_tw(g, gs);
+        });
+    }
 }
 
 // Inverse of the last row after its pieces were inverted by the row pass: the
