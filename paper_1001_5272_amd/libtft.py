@@ -240,8 +240,9 @@ def tft_plan_info(ctx: Context, n: int) -> dict:
 
 
 def tft_autotune(ctx: Context, n: int) -> dict:
-    """Time the candidate column widths for length n and cache the fastest
-    for every length with the same ceil(lg n); returns the resulting plan."""
+    """Time the candidate row widths W = 2^logW for length n (the planner's
+    choice and its neighbours) and cache the fastest for every length in the
+    same quarter octave (tft_plan_bucket); returns the resulting plan."""
     d = PlanDesc()
     _check(load().tft_autotune(ctx.handle, n, ctypes.byref(d)), "tft_autotune")
     return {f: getattr(d, f) for f, _ in PlanDesc._fields_}
