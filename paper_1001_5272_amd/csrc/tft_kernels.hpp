@@ -267,6 +267,34 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
             for (int t = 0; t < 8; t++) buf[pad((u + t * M8) * C + c)] = x[t];
         }
         __syncthreads();
+        if (P.M >= 64) {
+            // the last group (stages 4, 2, 1 on eight consecutive rows) straight
+            // to HBM, for the blocks of eight that meet [0, Lout)
+            dif_stages(md, T, buf, LOGC, P.M, P.M >> 4, 8, 0, P.Lout, 0);
+            const uint32_t blocks = (P.Lout + 7) >> 3;
+            for (uint32_t it = threadIdx.x; it < blocks * C; it += nthreads()) {
+                const uint32_t c = it & (C - 1), i = it >> LOGC;
+                Word x[8];
+#pragma unroll
+                for (int t = 0; t < 8; t++) x[t] = buf[pad((8 * i + t) * C + c)];
+                Unit<Mod, 3> un;
+                un.load0(T.lf, 0, i);
+                un.forward(md, x);
+#pragma unroll
+                for (int t = 0; t < 8; t++) {
+                    const uint32_t d = 8 * i + t;
+                    const uint64_t idx = (c0 + c) + (uint64_t)d * W;
+                    if (d >= P.Lout) break;
+                    if (idx < P.n)
+                        P.X[idx] = x[t];
+                    else if (P.b && d == P.a)
+                        P.V[c0 + c] = x[t];
+                    if (share && d == P.a) zterm[c] = md.mul_tw(x[t], ypow[c]);
+                }
+            }
+            if (share) put_share();
+            return;
+        }
         dif_stages(md, T, buf, LOGC, P.M, P.M >> 4, 1, 0, P.Lout, 0);
     } else {
         staged_copy<8>(P.M * C, [&](uint32_t it) {
