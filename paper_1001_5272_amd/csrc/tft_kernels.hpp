@@ -219,6 +219,35 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
                 for (int t = 0; t < 8; t++) buf[pad((u + t * M8) * C + c)] = x[t];
             }
             reduce_lanes(md, acc, LOGC, red, extra);   // its barriers also publish the tile
+            if (H >= 64) {
+                // the last group straight to HBM (outputs d < H), then output H
+                dif_stages(md, T, buf, LOGC, H, H >> 4, 8, 0, H, 0);
+                for (uint32_t it = threadIdx.x; it < M8 * C; it += nthreads()) {
+                    const uint32_t c = it & (C - 1), i = it >> LOGC;
+                    Word x[8];
+#pragma unroll
+                    for (int t = 0; t < 8; t++) x[t] = buf[pad((8 * i + t) * C + c)];
+                    Unit<Mod, 3> un;
+                    un.load0(T.lf, 0, i);
+                    un.forward(md, x);
+#pragma unroll
+                    for (int t = 0; t < 8; t++) {
+                        const uint64_t idx = (c0 + c) + (uint64_t)(8 * i + t) * W;
+                        if (idx < P.n) P.X[idx] = x[t];
+                    }
+                }
+                for (uint32_t c = threadIdx.x; c < C; c += nthreads()) {
+                    const uint64_t idx = (c0 + c) + (uint64_t)H * W;
+                    const Word v = md.sub(md.sub(extra[c], hi0[c]), hi0[c]);
+                    if (idx < P.n)
+                        P.X[idx] = v;
+                    else if (P.b && H == P.a)
+                        P.V[c0 + c] = v;
+                    if (share) zterm[c] = md.mul_tw(v, ypow[c]);
+                }
+                if (share) put_share();
+                return;
+            }
             dif_stages(md, T, buf, LOGC, H, H >> 4, 1, 0, H, 0);
         } else {
             eval_scales(md, LOGC, H, tw_fwd(md, T, H), zp);
