@@ -258,6 +258,11 @@ typedef enum {
     TFT_K_COUNT
 } tft_kernel_id;
 tft_status tft_timing_enable(tft_ctx* ctx, int on);
+/* Restrict measurement mode to the kernels whose bit (1u << tft_kernel_id)
+ * is set in kernel_mask (default: every kernel).  Each bracketed launch adds
+ * two event records to the stream, which cost time of their own; a benchmark
+ * that times one kernel class brackets only that one. */
+tft_status tft_timing_select(tft_ctx* ctx, uint32_t kernel_mask);
 tft_status tft_timing_read(tft_ctx* ctx, int id, uint64_t* launches, double* total_ms);
 tft_status tft_timing_reset(tft_ctx* ctx);
 const char* tft_kernel_name(int id);

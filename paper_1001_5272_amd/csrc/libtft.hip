@@ -93,8 +93,10 @@ struct tft_ctx {
     void* tables;        // f1 | f2 | i1 | i2
     size_t n1, n2;       // entries per level
     void* scratch;       // V_c area and column polynomial (kScratchWords words)
-    // measurement mode (tft_timing_*): events bracketing each launch
+    // measurement mode (tft_timing_*): events bracketing each launch of the
+    // kernels selected in timing_mask (bit = tft_kernel_id)
     bool timing;
+    uint32_t timing_mask;
     struct Rec { int kid; hipEvent_t e0, e1; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
@@ -137,7 +139,7 @@ template <typename Kernel, typename... Args>
 void launch(tft_ctx* ctx, int kid, Kernel kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st,
             Args... args) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->timing) {
+    if (ctx->timing && ((ctx->timing_mask >> kid) & 1u)) {
         e0 = take_event(ctx);
         e1 = take_event(ctx);
         if (e0 && e1) (void)hipEventRecord(e0, st);
@@ -1151,6 +1153,7 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
     c->override_logW = 0;
     for (unsigned i = 0; i < kPlanBuckets; i++) c->tuned_logW[i] = 0;
     c->timing = false;
+    c->timing_mask = ~0u;
     c->last_batch = nullptr;
     c->last_done = nullptr;
     for (int i = 0; i < TFT_K_COUNT; i++) { c->launches[i] = 0; c->total_ms[i] = 0.0; }
@@ -1512,6 +1515,12 @@ void tft_queue_destroy(tft_queue* q) {
 tft_status tft_timing_enable(tft_ctx* ctx, int on) {
     if (!ctx) return TFT_EINVAL;
     ctx->timing = on != 0;
+    return TFT_OK;
+}
+
+tft_status tft_timing_select(tft_ctx* ctx, uint32_t kernel_mask) {
+    if (!ctx) return TFT_EINVAL;
+    ctx->timing_mask = kernel_mask;
     return TFT_OK;
 }
 

@@ -73,6 +73,7 @@ SIGNATURES = {
     "tft_plan_cache_set": (_st, [_vp, ctypes.c_uint, ctypes.c_uint]),
     "tft_plan_bucket": (ctypes.c_uint, [_sz]),
     "tft_timing_enable": (_st, [_vp, ctypes.c_int]),
+    "tft_timing_select": (_st, [_vp, ctypes.c_uint32]),
     "tft_timing_read": (_st, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
     "tft_timing_reset": (_st, [_vp]),
     "tft_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -292,6 +293,12 @@ def tft_calibrate(ctx: Context) -> dict:
 
 def tft_timing_enable(ctx: Context, on: bool = True):
     _check(load().tft_timing_enable(ctx.handle, 1 if on else 0), "tft_timing_enable")
+
+
+def tft_timing_select(ctx: Context, names=None):
+    """Bracket only the launches of the named kernels (None: every kernel)."""
+    mask = 0xFFFFFFFF if names is None else sum(1 << KERNEL_NAMES.index(n) for n in names)
+    _check(load().tft_timing_select(ctx.handle, mask), "tft_timing_select")
 
 
 def tft_timing_reset(ctx: Context):
