@@ -44,7 +44,7 @@ extern "C" {
 typedef enum {
     TFT_OK = 0,
     TFT_EINVAL = -1,   /* null pointer, zero length, bad generator */
-    TFT_ERANGE = -2,   /* length above 2^v (v = 2-adic order of p-1) or above this build's limit; unsupported p */
+    TFT_ERANGE = -2,   /* length above 2^v (v = 2-adic order of p-1) or above the library's limit; unsupported p */
     TFT_ENOMEM = -3,   /* context or queue allocation failed */
     TFT_EDEVICE = -4,  /* a HIP call failed */
     TFT_EAGAIN = -5    /* queue: the request does not fit the free pool now */
@@ -60,7 +60,7 @@ typedef struct tft_ctx tft_ctx;
 tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out);
 void tft_ctx_destroy(tft_ctx* ctx);
 
-/* v = 2-adic order of p-1, capped at this build's limit: every length n must
+/* v = 2-adic order of p-1, capped at 28 (the library's limit): every length n must
  * satisfy n <= 2^v (section 6: a root of order 2^ceil(lg n) is needed). */
 unsigned tft_ctx_max_log2(const tft_ctx* ctx);
 /* 4 (uint32_t words) or 8 (uint64_t words). */

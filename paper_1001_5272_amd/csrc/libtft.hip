@@ -236,7 +236,7 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
             return P;
         }
     }
-    P.kind = -1;   // beyond this build's two-pass limit
+    P.kind = -1;   // beyond the two-pass limit of the library
     return P;
 }
 
