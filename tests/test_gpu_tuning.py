@@ -62,3 +62,35 @@ def test_autotune_then_parity(name):
         assert libtft.tft_plan_cache_get(ctx, bk) == plan["logW"]
     finally:
         ctx.close()
+
+
+@pytest.mark.gpu
+def test_timing_select_brackets_only_selected_kernels():
+    # measurement mode with a kernel mask: only the selected kernels' launches
+    # are timed, the others run untimed, and results are unchanged
+    p, g = PRIMES["goldilocks"]
+    ctx = libtft.Context(p, g, 0)
+    try:
+        n = (1 << 20) + 3
+        F = synth.residues(p, n, 5)
+        X = torch.from_numpy(F).cuda()
+        print(f"[gpu] timing select n={n}", flush=True)
+        libtft.tft_timing_reset(ctx)
+        libtft.tft_timing_enable(ctx, True)
+        libtft.tft_forward(ctx, X)
+        libtft.tft_inverse(ctx, X)
+        torch.cuda.synchronize()
+        every = libtft.tft_timing_read(ctx)
+        assert {"col_fwd", "row_fwd", "row_inv"} <= set(every)
+        libtft.tft_timing_reset(ctx)
+        libtft.tft_timing_select(ctx, ["row_fwd"])
+        libtft.tft_forward(ctx, X)
+        libtft.tft_inverse(ctx, X)
+        torch.cuda.synchronize()
+        only = libtft.tft_timing_read(ctx)
+        assert set(only) == {"row_fwd"} and only["row_fwd"][0] == 1
+        libtft.tft_timing_select(ctx, None)
+        libtft.tft_timing_enable(ctx, False)
+        assert (X.cpu().numpy() == F).all()
+    finally:
+        ctx.close()
