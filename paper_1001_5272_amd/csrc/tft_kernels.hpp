@@ -1038,7 +1038,16 @@ __global__ __launch_bounds__(kThreads) void k_fold(Mod md, Tables<typename Mod::
     const uint64_t t1 = t0 + chunk < terms ? t0 + chunk : terms;
     const Word c = tw_fwd(md, T, g);
     Word acc = 0;
-    for (uint64_t t = t1; t > t0; t--) acc = md.add(md.mul_tw(acc, c), A[j + (t - 1) * L]);
+    // Horner from the top term down, eight terms' loads in flight at a time
+    uint64_t t = t1;
+    for (; t >= t0 + 8; t -= 8) {
+        Word v[8];
+#pragma unroll
+        for (int k8 = 0; k8 < 8; k8++) v[k8] = A[j + (t - 1 - k8) * L];
+#pragma unroll
+        for (int k8 = 0; k8 < 8; k8++) acc = md.add(md.mul_tw(acc, c), v[k8]);
+    }
+    for (; t > t0; t--) acc = md.add(md.mul_tw(acc, c), A[j + (t - 1) * L]);
     if (t0 > 0 && t0 < t1) {
         // c^t0 by square and multiply over the bits of t0
         Word z = c, e = md.one_tw();
