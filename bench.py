@@ -98,7 +98,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="plan with the built-in planner only")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the served Poisson stream")
     ap.add_argument("--plain-seconds", type=float, default=1.0, help="length of the plain FIFO comparison")
-    ap.add_argument("--skip", default="", help="comma list of extras to skip: products,small,sweep,batched,served,crt")
+    ap.add_argument("--skip", default="", help="comma list of extras to skip: products,small,walk,sweep,batched,served,crt")
     return ap.parse_args()
 
 
@@ -321,6 +321,8 @@ def extras(ctx, bufs, host, p, skip=frozenset()):
         out["poly_mul"] = products(ctx, p, dev)
     if "small" not in skip:
         out["small_c1"] = small_c1(dev)
+    if "walk" not in skip:
+        out["walk_vs_batch"] = walk_vs_batch(ctx, p)
     return out
 
 
@@ -356,6 +358,50 @@ def products(ctx, p, dev):
         del X3
         del Ap, Bp, X2
     return prods
+
+
+def walk_vs_batch(ctx, p):
+    """The paper's Algorithm 1 run literally, one wavefront per instance
+    (tft_walk_batch), against the layer-parallel small-instance kernel of the
+    batched path, on batches of short instances (kernel time from HIP events;
+    both give the same outputs)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1001_5272_amd import libtft
+
+    print("[bench] walk vs batch", file=sys.stderr, flush=True)
+    rows = []
+    for lo, hi, count in [(8, 64, 16384), (32, 256, 16384), (256, 1024, 4096)]:
+        ns = synth.log_uniform_lengths(lo, hi, count, 6000).astype(np.int64)
+        base = torch.from_numpy(synth.residues(p, int(ns.sum()), 6001)).cuda()
+        offs = np.concatenate([[0], np.cumsum(ns)[:-1]])
+        xs = [base[o:o + n] for o, n in zip(offs, ns)]
+        ref = base.clone()
+        us = {}
+        outs = {}
+        for name, fn in [("walk", lambda: libtft.tft_walk_batch(ctx, xs)),
+                         ("batch", lambda: libtft.tft_forward_batch(ctx, xs))]:
+            base.copy_(ref)
+            fn()
+            torch.cuda.synchronize()
+            outs[name] = base.clone()
+            libtft.tft_timing_reset(ctx)
+            libtft.tft_timing_enable(ctx, True)
+            for _ in range(3):
+                base.copy_(ref)
+                fn()
+            torch.cuda.synchronize()
+            t = libtft.tft_timing_read(ctx)
+            libtft.tft_timing_enable(ctx, False)
+            us[name] = round(t["small_list"][1] * 1e3 / t["small_list"][0], 1)
+        base.copy_(ref)
+        rows.append({"lengths": f"log-uniform [{lo}, {hi})", "instances": count, "words": int(ns.sum()),
+                     "walk_kernel_us": us["walk"], "batch_kernel_us": us["batch"],
+                     "walk_over_batch": round(us["walk"] / us["batch"], 2),
+                     "same_outputs": bool(torch.equal(outs["walk"], outs["batch"]))})
+    return {"workload": "forward TFT of batches of short instances, p=2^64-2^32+1 (seed 6001)", "rows": rows}
 
 
 def small_c1(dev):

@@ -152,6 +152,19 @@ void tft_batch_destroy(tft_batch* batch);
 tft_status poly_mul_batch(tft_ctx* ctx, const tft_mul_desc* d, size_t count, void* hip_stream);
 tft_status tft_forward_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t count, void* hip_stream);
 
+/* The paper's Algorithm 1 (inverse = 0) or Algorithm 2 (inverse = 1) run as
+ * written (section 3: the in-place TFT as a post-order walk of the even/odd
+ * tree with a constant number of scalars, including the odd-length
+ * correction; section 4: the ITFT walking the same path backwards), one
+ * wavefront per instance: every lane follows the same node and the 64 lanes
+ * share each node's butterflies and the correction's sum.  An alternative to
+ * the layer-parallel small-instance kernels for batches of short instances.
+ * X[k] (device, n[k] words, in place), 1 <= n[k] <= 1024 and n[k] <= 2^v, else
+ * TFT_EINVAL / TFT_ERANGE before any work.  The call uploads the two arrays,
+ * enqueues one kernel on hip_stream and waits for it (synchronous).  Results
+ * equal tft_forward / tft_inverse bit for bit. */
+tft_status tft_walk_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t count, int inverse, void* hip_stream);
+
 /* ---------------------------------------------------------------- serving
  * A request queue with continuous batching.  tft_queue_create allocates a
  * device pool of pool_words words and starts a worker thread.

@@ -1118,6 +1118,37 @@ void queue_worker(tft_queue* q) {
 }  // namespace
 
 // ============================================================== C entry points
+template <class Mod>
+tft_status walk_impl(tft_ctx* ctx, void* const* X, const size_t* n, size_t count, int inverse, hipStream_t st) {
+    using Word = typename Mod::Word;
+    const Mod& md = mod_of<Mod>(ctx);
+    const auto T = tables_of<Word>(ctx);
+    std::vector<uint64_t> host(2 * count);
+    for (size_t k = 0; k < count; k++) {
+        host[k] = (uint64_t)(uintptr_t)X[k];
+        host[count + k] = n[k];
+    }
+    void* dmem = nullptr;
+    if (hipMalloc(&dmem, host.size() * 8) != hipSuccess) return TFT_ENOMEM;
+    tft_status s = TFT_OK;
+    if (hipMemcpy(dmem, host.data(), host.size() * 8, hipMemcpyHostToDevice) != hipSuccess) s = TFT_EDEVICE;
+    if (s == TFT_OK) {
+        Word* const* ptrs = reinterpret_cast<Word* const*>(dmem);
+        const uint64_t* lens = reinterpret_cast<const uint64_t*>(dmem) + count;
+        const dim3 grid((uint32_t)((count + tft::kWalkWaves - 1) / tft::kWalkWaves));
+        if (inverse)
+            launch(ctx, TFT_K_SMALL_LIST, tft::k_walk<Mod, true>, grid, dim3(64 * tft::kWalkWaves), 0, st, md, T, ptrs,
+                   lens, (uint32_t)count);
+        else
+            launch(ctx, TFT_K_SMALL_LIST, tft::k_walk<Mod, false>, grid, dim3(64 * tft::kWalkWaves), 0, st, md, T, ptrs,
+                   lens, (uint32_t)count);
+        s = launch_status();
+        if (hipStreamSynchronize(st) != hipSuccess && s == TFT_OK) s = TFT_EDEVICE;
+    }
+    (void)hipFree(dmem);
+    return s;
+}
+
 extern "C" {
 
 const char* tft_strerror(tft_status s) {
@@ -1367,6 +1398,18 @@ tft_status tft_forward_batch(tft_ctx* ctx, void* const* X, const size_t* n, size
     }
     DeviceGuard guard(ctx->device);
     return batch_once(ctx, d.data(), count, 0, (hipStream_t)stream);
+}
+
+tft_status tft_walk_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t count, int inverse, void* stream) {
+    if (!ctx || (count && (!X || !n)) || count > (size_t)UINT32_MAX) return TFT_EINVAL;
+    for (size_t k = 0; k < count; k++) {
+        if (!X[k] || n[k] == 0) return TFT_EINVAL;
+        if (n[k] > tft::kWalkMax || n[k] > (size_t(1) << ctx->v)) return TFT_ERANGE;
+    }
+    if (!count) return TFT_OK;
+    DeviceGuard guard(ctx->device);
+    if (ctx->wbytes == 4) return walk_impl<tft::ModU32>(ctx, X, n, count, inverse, (hipStream_t)stream);
+    return walk_impl<tft::ModGL>(ctx, X, n, count, inverse, (hipStream_t)stream);
 }
 
 tft_status tft_from_signed(tft_ctx* ctx, const int64_t* src, size_t n, void* dst, void* stream) {

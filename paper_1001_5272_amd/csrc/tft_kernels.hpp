@@ -1261,4 +1261,137 @@ __global__ __launch_bounds__(kThreads) void k_crt3(Crt3 c, const uint32_t* r1, c
     }
 }
 
+// ---- the paper's Algorithms 1 and 2, one wavefront per instance ---------
+// The in-place TFT walks the even/odd tree of section 3 in post order with a
+// constant number of scalars (node S = (q, r): offset q, stride 2^r, length
+// ceil((n - q) / 2^r)), doing at each node either the butterflies of eq. (1)
+// over its pairs or, before descending into the odd child of an odd-length
+// node, the correction S_{m-1} += H(w_{(m-1)/2}) w_{m-1}; the ITFT walks the
+// same path backwards with the inverse steps.  Here the walk is uniform per
+// wavefront (every lane holds the same node) and the 64 lanes share each
+// node's butterflies and the correction's sum; the instance sits in the
+// wavefront's LDS slice (at most kWalkMax words), loaded and stored once.
+constexpr uint32_t kWalkMax = 1024;
+constexpr uint32_t kWalkWaves = 4;   // wavefronts (instances) per workgroup
+
+struct WalkNode {
+    uint32_t q, r;
+};
+__device__ __forceinline__ uint32_t walk_len(uint32_t n, WalkNode s) { return (n - s.q + (1u << s.r) - 1) >> s.r; }
+__device__ __forceinline__ WalkNode walk_even(WalkNode s) { return WalkNode{s.q, s.r + 1}; }
+__device__ __forceinline__ WalkNode walk_odd(WalkNode s) { return WalkNode{s.q + (1u << s.r), s.r + 1}; }
+__device__ __forceinline__ WalkNode walk_parent(WalkNode s) {
+    const uint32_t h = 1u << (s.r - 1);
+    return WalkNode{s.q < h ? s.q : s.q - h, s.r - 1};
+}
+__device__ __forceinline__ WalkNode walk_first_leaf(uint32_t n, WalkNode s) {
+    while (walk_len(n, s) > 1) s = walk_even(s);
+    return s;
+}
+__device__ __forceinline__ bool walk_same(WalkNode a, WalkNode b) { return a.q == b.q && a.r == b.r; }
+// orders the wavefront's LDS accesses across lanes (one wavefront, no barrier)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// v = sum_{i <= (m-3)/2} S_{2i+1} w_{(m-1)/2}^i over the lanes (every lane gets v)
+template <class Mod>
+__device__ __forceinline__ typename Mod::Word walk_odd_sum(const Mod& md, const Tables<typename Mod::Word>& T,
+                                                          const typename Mod::Word* x, uint32_t n, WalkNode s,
+                                                          uint32_t m, uint32_t lane) {
+    using Word = typename Mod::Word;
+    const uint32_t maskK = (1u << T.K) - 1;
+    const uint32_t e = __builtin_bitreverse32((m - 1) >> 1) >> (32 - T.K);   // w_{(m-1)/2} = w[K]^e
+    Word acc = 0;
+    for (uint32_t i = lane; 2 * i + 1 < m - 1; i += 64)
+        acc = md.add(acc, md.mul_tw(x[s.q + ((2 * i + 1) << s.r)], root_pow(md, T, (i * e) & maskK)));
+    for (int o = 1; o < 64; o <<= 1) acc = md.add(acc, shfl_xor_word(acc, o));
+    return acc;
+}
+
+template <class Mod, bool INV>
+__global__ __launch_bounds__(64 * kWalkWaves) void k_walk(Mod md, Tables<typename Mod::Word> T,
+                                                         typename Mod::Word* const* X, const uint64_t* lens,
+                                                         uint32_t count) {
+    using Word = typename Mod::Word;
+    __shared__ Word slice[kWalkWaves][kWalkMax];
+    const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t inst = blockIdx.x * kWalkWaves + wv;
+    if (inst >= count) return;   // whole wavefront
+    const uint32_t n = (uint32_t)lens[inst];
+    Word* g = X[inst];
+    Word* x = slice[wv];
+    for (uint32_t i = lane; i < n; i += 64) x[i] = g[i];
+    wave_sync();
+    const WalkNode root{0, 0};
+    const WalkNode first = walk_first_leaf(n, root);
+    if (!INV) {
+        // Algorithm 1
+        WalkNode s = first, prev{~0u, ~0u};
+        while (true) {
+            const uint32_t m = walk_len(n, s);
+            if (m == 1 || walk_same(prev, walk_odd(s))) {
+                for (uint32_t j = lane; j < (m >> 1); j += 64) {
+                    const Word th = tw_fwd(md, T, 2 * (uint64_t)j);
+                    Word& a = x[s.q + ((2 * j) << s.r)];
+                    Word& b = x[s.q + ((2 * j + 1) << s.r)];
+                    const Word t = md.mul_tw(b, th), u = a;
+                    a = md.add(u, t);
+                    b = md.sub(u, t);
+                }
+                wave_sync();
+                if (walk_same(s, root)) break;
+                prev = s;
+                s = walk_parent(s);
+            } else {   // prev is the even child
+                if (m & 1u) {
+                    const Word v = walk_odd_sum(md, T, x, n, s, m, lane);
+                    if (lane == 0) {
+                        Word& last = x[s.q + ((m - 1) << s.r)];
+                        last = md.add(last, md.mul_tw(v, tw_fwd(md, T, m - 1)));
+                    }
+                    wave_sync();
+                }
+                prev = s;
+                s = walk_first_leaf(n, walk_odd(s));
+            }
+        }
+    } else {
+        // Algorithm 2
+        WalkNode s = root;
+        while (!walk_same(s, first)) {
+            if (walk_len(n, s) == 1) {
+                // s = parent(rp(s)): climb while s is an even child, then once more
+                while (s.r > 0 && s.q < (1u << (s.r - 1))) s = walk_parent(s);
+                s = walk_parent(s);
+                const uint32_t m = walk_len(n, s);
+                if (m & 1u) {
+                    const Word v = walk_odd_sum(md, T, x, n, s, m, lane);
+                    if (lane == 0) {
+                        Word& last = x[s.q + ((m - 1) << s.r)];
+                        last = md.sub(last, md.mul_tw(v, tw_fwd(md, T, m - 1)));
+                    }
+                    wave_sync();
+                }
+                s = walk_even(s);
+            } else {
+                const uint32_t m = walk_len(n, s);
+                for (uint32_t j = lane; j < (m >> 1); j += 64) {
+                    const Word th = tw_inv(md, T, 2 * (uint64_t)j);
+                    Word& a = x[s.q + ((2 * j) << s.r)];
+                    Word& b = x[s.q + ((2 * j + 1) << s.r)];
+                    const Word u = a, w = b;
+                    a = md.half(md.add(u, w));
+                    b = md.mul_tw(md.half(md.sub(u, w)), th);
+                }
+                wave_sync();
+                s = walk_odd(s);
+            }
+        }
+    }
+    for (uint32_t i = lane; i < n; i += 64) g[i] = x[i];
+}
+
 }  // namespace tft

@@ -74,6 +74,7 @@ SIGNATURES = {
     "tft_plan_bucket": (ctypes.c_uint, [_sz]),
     "tft_timing_enable": (_st, [_vp, ctypes.c_int]),
     "tft_timing_select": (_st, [_vp, ctypes.c_uint32]),
+    "tft_walk_batch": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_sz), _sz, ctypes.c_int, _vp]),
     "tft_timing_read": (_st, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
     "tft_timing_reset": (_st, [_vp]),
     "tft_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -392,6 +393,15 @@ def tft_forward_batch(ctx: Context, xs, stream=None):
     ptrs = (_vp * len(xs))(*[ctx._t(x, "X").value for x in xs])
     ns = (_sz * len(xs))(*[x.numel() for x in xs])
     _check(load().tft_forward_batch(ctx.handle, ptrs, ns, len(xs), _stream(stream)), "tft_forward_batch")
+
+
+def tft_walk_batch(ctx: Context, xs, inverse: bool = False, stream=None):
+    """The paper's Algorithm 1 (or 2 with inverse) on each tensor of xs in place,
+    one wavefront per instance (at most 1024 words each); synchronous."""
+    ptrs = (_vp * len(xs))(*[ctx._t(x, "X").value for x in xs])
+    ns = (_sz * len(xs))(*[x.numel() for x in xs])
+    _check(load().tft_walk_batch(ctx.handle, ptrs, ns, len(xs), 1 if inverse else 0, _stream(stream)),
+           "tft_walk_batch")
 
 
 def tft_from_signed(ctx: Context, src, dst, stream=None):
