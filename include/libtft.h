@@ -130,8 +130,9 @@ tft_status poly_mul_padded(tft_ctx* ctx, const void* A, size_t m, const void* B,
  * so a run can be captured in a HIP graph and replayed.  The descriptors'
  * buffers must stay valid while runs are in flight; one batch must not run
  * concurrently with itself.  poly_mul_batch and tft_forward_batch plan and
- * run in one call (allocating per call); the batch is kept by the context
- * until its next such call. */
+ * run in one call, with work-list memory the context keeps and grows (each
+ * call first waits for the previous such call's batch to finish on the
+ * device); the batch is kept by the context until its next such call. */
 typedef struct {
     const void* a;
     size_t la;
@@ -175,7 +176,9 @@ tft_status tft_walk_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t 
  * words, the in-place footprint -- not 2^ceil(lg r)) fits in the pool and
  * fewer than max_inflight requests are on the device; each group admitted
  * together runs as one batch, and consecutive batches run on two streams so
- * that they overlap on the device.  Submit returns TFT_ERANGE for a request
+ * that they overlap on the device; each stream keeps the device and pinned
+ * host memory of its batches' work lists, grown as needed, so a batch in
+ * steady state allocates and frees nothing.  Submit returns TFT_ERANGE for a request
  * that could never fit and TFT_EAGAIN when the pending list is full
  * (2^20 requests).  poll reports completion without blocking; wait blocks;
  * completion_ns gives the steady-clock time (ns) at which the worker saw the

@@ -81,6 +81,21 @@ struct Plan {
 
 }  // namespace
 
+// Memory and streams that consecutive batches reuse (each slot of the serving
+// queue, the convenience batch calls): a device area and a pinned host
+// staging area that grow geometrically and are kept, so that a batch in steady
+// state allocates nothing, uploads its work lists with an asynchronous copy on
+// its own stream and never waits on a free.  One batch at a time uses an
+// arena, and only once the batch before it has finished on the device.
+struct BatchArena {
+    void* dmem = nullptr;
+    size_t dcap = 0;
+    void* hmem = nullptr;   // pinned
+    size_t hcap = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, done = nullptr;
+};
+
 struct tft_ctx {
     int device;
     uint64_t p, g;
@@ -104,6 +119,7 @@ struct tft_ctx {
     double total_ms[TFT_K_COUNT];
     struct tft_batch* last_batch;   // kept alive for the convenience batch calls
     hipEvent_t last_done;
+    BatchArena once_arena;          // reused by the convenience batch calls
 };
 
 namespace {
@@ -696,12 +712,55 @@ struct tft_batch {
     uint32_t small_grid;
     hipStream_t side;          // the single-workgroup jobs run here, beside the two-pass phases
     hipEvent_t fork, join;
+    BatchArena* arena;         // borrowed memory, stream and events (nullptr: the batch owns its own)
 };
 
 namespace {
 
+hipError_t arena_init(BatchArena* A) {
+    hipError_t e = hipStreamCreateWithFlags(&A->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&A->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&A->join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&A->done, hipEventDisableTiming);
+    return e;
+}
+
+// grows the arena to at least `bytes` (only while no batch of it is on the device)
+hipError_t arena_reserve(BatchArena* A, size_t bytes) {
+    if (bytes > A->dcap) {
+        const size_t c = std::max<size_t>({bytes, 2 * A->dcap, size_t(1) << 20});
+        if (A->dmem) (void)hipFree(A->dmem);
+        A->dmem = nullptr;
+        A->dcap = 0;
+        const hipError_t e = hipMalloc(&A->dmem, c);
+        if (e != hipSuccess) return e;
+        A->dcap = c;
+    }
+    if (bytes > A->hcap) {
+        const size_t c = std::max<size_t>({bytes, 2 * A->hcap, size_t(1) << 20});
+        if (A->hmem) (void)hipHostFree(A->hmem);
+        A->hmem = nullptr;
+        A->hcap = 0;
+        const hipError_t e = hipHostMalloc(&A->hmem, c, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        A->hcap = c;
+    }
+    return hipSuccess;
+}
+
+void arena_free(BatchArena* A) {
+    if (A->dmem) (void)hipFree(A->dmem);
+    if (A->hmem) (void)hipHostFree(A->hmem);
+    if (A->side) (void)hipStreamDestroy(A->side);
+    if (A->fork) (void)hipEventDestroy(A->fork);
+    if (A->join) (void)hipEventDestroy(A->join);
+    if (A->done) (void)hipEventDestroy(A->done);
+    *A = BatchArena();
+}
+
 template <class Mod>
-tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, tft_batch* B) {
+tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, tft_batch* B,
+                       hipStream_t upload) {
     using Word = typename Mod::Word;
     const unsigned w = ctx->wbytes;
     std::vector<tft::SmallJob<Word>> jobs;
@@ -790,20 +849,34 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
     const size_t o_ctr = off;
     off = align(off + 256);
     B->dbytes = off;
-    hipError_t e = hipMalloc(&B->dmem, off);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? TFT_ENOMEM : TFT_EDEVICE;
+    // the V areas are written before they are read and the counter is reset
+    // by every run, so only the lists in front of them are uploaded
+    std::vector<char> own;
+    char* host;
+    if (B->arena) {
+        const hipError_t e = arena_reserve(B->arena, off);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? TFT_ENOMEM : TFT_EDEVICE;
+        B->dmem = B->arena->dmem;
+        host = (char*)B->arena->hmem;
+        std::memset(host, 0, o_v);
+    } else {
+        const hipError_t e = hipMalloc(&B->dmem, off);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? TFT_ENOMEM : TFT_EDEVICE;
+        own.assign(o_v, 0);
+        host = own.data();
+    }
     char* base = (char*)B->dmem;
     size_t vo = 0;
     for (size_t i = 0; i < recs.size(); i++) {
         recs[i].V = (Word*)(base + o_v) + vo;
         vo += vwords[i];
     }
-    std::vector<char> host(off, 0);
-    std::memcpy(host.data() + o_recs, recs.data(), recs.size() * sizeof(tft::TwoPass<Word>));
+    std::memcpy(host + o_recs, recs.data(), recs.size() * sizeof(tft::TwoPass<Word>));
     for (int ph = 0; ph < PH_COUNT; ph++)
-        std::memcpy(host.data() + o_items[ph], items[ph].data(), items[ph].size() * sizeof(tft::Item));
-    std::memcpy(host.data() + o_jobs, jobs.data(), jobs.size() * sizeof(tft::SmallJob<Word>));
-    e = hipMemcpy(B->dmem, host.data(), off, hipMemcpyHostToDevice);
+        std::memcpy(host + o_items[ph], items[ph].data(), items[ph].size() * sizeof(tft::Item));
+    std::memcpy(host + o_jobs, jobs.data(), jobs.size() * sizeof(tft::SmallJob<Word>));
+    const hipError_t e = B->arena ? hipMemcpyAsync(B->dmem, host, o_v, hipMemcpyHostToDevice, upload)
+                                  : hipMemcpy(B->dmem, host, o_v, hipMemcpyHostToDevice);
     if (e != hipSuccess) return TFT_EDEVICE;
     B->recs = base + o_recs;
     for (int ph = 0; ph < PH_COUNT; ph++) {
@@ -816,8 +889,7 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
     uint32_t per_cu = B->lds_small ? (uint32_t)std::max<size_t>(1, kLdsHard / B->lds_small) : 1;
     per_cu = std::min<uint32_t>(per_cu, 8);
     int ncu = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) ncu = prop.multiProcessorCount;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) ncu = 256;
     B->small_grid = (uint32_t)std::min<size_t>(jobs.size(), (size_t)ncu * per_cu);
     return TFT_OK;
 }
@@ -872,14 +944,20 @@ tft_status batch_run(tft_batch* B, hipStream_t st) {
 void batch_free(tft_batch* B) {
     if (!B) return;
     DeviceGuard guard(B->ctx->device);
-    if (B->dmem) (void)hipFree(B->dmem);
-    if (B->side) (void)hipStreamDestroy(B->side);
-    if (B->fork) (void)hipEventDestroy(B->fork);
-    if (B->join) (void)hipEventDestroy(B->join);
+    if (!B->arena) {
+        if (B->dmem) (void)hipFree(B->dmem);
+        if (B->side) (void)hipStreamDestroy(B->side);
+        if (B->fork) (void)hipEventDestroy(B->fork);
+        if (B->join) (void)hipEventDestroy(B->join);
+    }
     delete B;
 }
 
-tft_status batch_create(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, tft_batch** out) {
+// arena == nullptr: the batch allocates its own memory and uploads its lists
+// synchronously (it can then be run many times, also under graph capture);
+// otherwise it borrows the arena and uploads on `upload`, the stream it runs on
+tft_status batch_create(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, tft_batch** out,
+                        BatchArena* arena = nullptr, hipStream_t upload = nullptr) {
     if (!ctx || !out || (count && !d)) return TFT_EINVAL;
     *out = nullptr;
     DeviceGuard guard(ctx->device);
@@ -888,9 +966,15 @@ tft_status batch_create(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int p
     B->ctx = ctx;
     B->products = products;
     B->count = count;
-    tft_status s = ctx->wbytes == 4 ? batch_build<tft::ModU32>(ctx, d, count, products, B)
-                                    : batch_build<tft::ModGL>(ctx, d, count, products, B);
-    if (s == TFT_OK) {
+    B->arena = arena;
+    if (arena) {
+        B->side = arena->side;
+        B->fork = arena->fork;
+        B->join = arena->join;
+    }
+    tft_status s = ctx->wbytes == 4 ? batch_build<tft::ModU32>(ctx, d, count, products, B, upload)
+                                    : batch_build<tft::ModGL>(ctx, d, count, products, B, upload);
+    if (s == TFT_OK && !arena) {
         if (hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&B->join, hipEventDisableTiming) != hipSuccess)
@@ -913,8 +997,12 @@ tft_status batch_once(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pro
         ctx->last_batch = nullptr;
     }
     if (count == 0) return TFT_OK;
+    if (!ctx->once_arena.side && arena_init(&ctx->once_arena) != hipSuccess) {
+        arena_free(&ctx->once_arena);
+        return TFT_EDEVICE;
+    }
     tft_batch* B = nullptr;
-    tft_status s = batch_create(ctx, d, count, products, &B);
+    tft_status s = batch_create(ctx, d, count, products, &B, &ctx->once_arena, st);
     if (s != TFT_OK) return s;
     DeviceGuard guard(ctx->device);
     s = ctx->wbytes == 4 ? batch_run<tft::ModU32>(B, st) : batch_run<tft::ModGL>(B, st);
@@ -933,8 +1021,9 @@ tft_status batch_once(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pro
 // in order while their workspace (r words, the in-place footprint of B's
 // transform) fits in the queue's device pool and fewer than max_inflight
 // requests are on the device; each group of newly admitted requests becomes
-// one batch, launched on one of two streams in turn so that consecutive
-// batches overlap on the device.  The worker polls the batches' completion
+// one batch, launched with whichever of two slots (a stream and a reusable
+// batch arena) is free, so that consecutive batches overlap on the device and
+// a batch in steady state neither allocates nor frees device memory.  The worker polls the batches' completion
 // events, releases their workspace, records completion times and admits more.
 namespace {
 
@@ -947,7 +1036,7 @@ struct QReq {
 
 struct QBatch {
     tft_batch* B;
-    hipEvent_t done;
+    int slot;   // the stream and arena it runs with; its arena's `done` event follows it
     std::vector<QReq> reqs;
 };
 
@@ -1016,7 +1105,8 @@ struct tft_queue {
     bool stop;
     std::thread worker;
     hipStream_t streams[2];
-    int next_stream;
+    BatchArena arenas[2];
+    bool slot_busy[2];
     uint64_t n_submitted, n_completed, n_batches, n_deferred, max_pool_used;
     tft_status error;
 };
@@ -1031,7 +1121,7 @@ void queue_worker(tft_queue* q) {
         bool progress = false;
         // retire finished batches
         for (auto it = q->inflight.begin(); it != q->inflight.end();) {
-            const hipError_t e = hipEventQuery(it->done);
+            const hipError_t e = hipEventQuery(q->arenas[it->slot].done);
             if (e == hipErrorNotReady) {
                 ++it;
                 continue;
@@ -1045,14 +1135,16 @@ void queue_worker(tft_queue* q) {
             q->inflight_reqs -= it->reqs.size();
             q->n_completed += it->reqs.size();
             if (e != hipSuccess) q->error = TFT_EDEVICE;
-            (void)hipEventDestroy(it->done);
             tft_batch_destroy(it->B);
+            q->slot_busy[it->slot] = false;
             it = q->inflight.erase(it);
             progress = true;
         }
         if (progress) q->cv_done.notify_all();
-        // admit in arrival order and launch one batch (at most two batches in flight)
-        if (!q->pending.empty() && q->inflight.size() < 2) {
+        // admit in arrival order and launch one batch (at most two batches in
+        // flight, one per slot)
+        const int slot = !q->slot_busy[0] ? 0 : !q->slot_busy[1] ? 1 : -1;
+        if (!q->pending.empty() && slot >= 0) {
             std::vector<QReq> group;
             while (!q->pending.empty() && group.size() < q->max_batch && q->inflight_reqs + group.size() < q->max_inflight) {
                 QReq rq = q->pending.front();
@@ -1079,19 +1171,17 @@ void queue_worker(tft_queue* q) {
                 std::vector<tft_mul_desc> ds(group.size());
                 for (size_t i = 0; i < group.size(); i++) ds[i] = group[i].d;
                 tft_batch* B = nullptr;
-                hipEvent_t ev = nullptr;
-                const hipStream_t st = q->streams[q->next_stream];
-                q->next_stream ^= 1;
-                tft_status s = tft_batch_create(q->ctx, ds.data(), ds.size(), 1, &B);
+                const hipStream_t st = q->streams[slot];
+                BatchArena* A = &q->arenas[slot];
+                tft_status s = batch_create(q->ctx, ds.data(), ds.size(), 1, &B, A, st);
                 if (s == TFT_OK) s = tft_batch_run(B, st);
-                if (s == TFT_OK && (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-                                    hipEventRecord(ev, st) != hipSuccess))
-                    s = TFT_EDEVICE;
+                if (s == TFT_OK && hipEventRecord(A->done, st) != hipSuccess) s = TFT_EDEVICE;
                 lk.lock();
                 if (s != TFT_OK) {
-                    // fail the group now; its workspace is released immediately
-                    if (B) { (void)hipStreamSynchronize(st); tft_batch_destroy(B); }
-                    if (ev) (void)hipEventDestroy(ev);
+                    // fail the group now; its workspace is released once the stream has drained
+                    (void)hipStreamSynchronize(st);
+                    (void)hipStreamSynchronize(A->side);
+                    if (B) tft_batch_destroy(B);
                     const uint64_t t = now_ns();
                     for (const QReq& rq : group) {
                         q->done_ns[rq.ticket] = t;
@@ -1103,7 +1193,8 @@ void queue_worker(tft_queue* q) {
                     q->error = s;
                     q->cv_done.notify_all();
                 } else {
-                    q->inflight.push_back(QBatch{B, ev, std::move(group)});
+                    q->slot_busy[slot] = true;
+                    q->inflight.push_back(QBatch{B, slot, std::move(group)});
                     q->n_batches++;
                 }
                 continue;
@@ -1232,6 +1323,7 @@ void tft_ctx_destroy(tft_ctx* ctx) {
         batch_free(ctx->last_batch);
     }
     if (ctx->last_done) (void)hipEventDestroy(ctx->last_done);
+    arena_free(&ctx->once_arena);
     (void)hipFree(ctx->tables);
     (void)hipFree(ctx->scratch);
     for (auto& r : ctx->recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
@@ -1465,15 +1557,21 @@ tft_status tft_queue_create(tft_ctx* ctx, size_t pool_words, size_t max_inflight
     q->inflight_reqs = 0;
     q->next_ticket = 1;
     q->stop = false;
-    q->next_stream = 0;
+    q->slot_busy[0] = q->slot_busy[1] = false;
     q->n_submitted = q->n_completed = q->n_batches = q->n_deferred = q->max_pool_used = 0;
     q->error = TFT_OK;
     q->alloc.init(pool_words);
     hipError_t e = hipMalloc(&q->pool, pool_words * ctx->wbytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->streams[0], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->streams[1], hipStreamNonBlocking);
+    if (e == hipSuccess) e = arena_init(&q->arenas[0]);
+    if (e == hipSuccess) e = arena_init(&q->arenas[1]);
     if (e != hipSuccess) {
         if (q->pool) (void)hipFree(q->pool);
+        for (int i = 0; i < 2; i++) {
+            if (q->streams[i]) (void)hipStreamDestroy(q->streams[i]);
+            arena_free(&q->arenas[i]);
+        }
         delete q;
         return e == hipErrorOutOfMemory ? TFT_ENOMEM : TFT_EDEVICE;
     }
@@ -1551,6 +1649,8 @@ void tft_queue_destroy(tft_queue* q) {
     DeviceGuard guard(q->ctx->device);
     (void)hipStreamDestroy(q->streams[0]);
     (void)hipStreamDestroy(q->streams[1]);
+    arena_free(&q->arenas[0]);
+    arena_free(&q->arenas[1]);
     (void)hipFree(q->pool);
     delete q;
 }

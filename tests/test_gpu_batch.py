@@ -135,6 +135,35 @@ def test_forward_batch(ctx998, ctxgl, which):
         assert (X.cpu().numpy().astype(np.uint64) == oracle.fft_padded(p, g, F)).all(), len(F)
 
 
+def test_convenience_calls_reuse_work_list_memory(ctxgl):
+    """Consecutive convenience calls share the context's work-list memory: a
+    call that grows it (40000 instances) between smaller ones, and a product
+    batch after the transforms, all still match the oracle."""
+    p, g = PRIMES["goldilocks"]
+
+    def forward(ns, seed, sample):
+        host = [synth.residues(p, int(n), seed + i) for i, n in enumerate(ns)]
+        xs = [torch.from_numpy(h).cuda() for h in host]
+        libtft.tft_forward_batch(ctxgl, xs)
+        torch.cuda.synchronize()
+        for i in sample:
+            got = xs[i].cpu().numpy().astype(np.uint64)
+            assert (got == oracle.fft_padded(p, g, host[i])).all(), (seed, i, len(host[i]))
+
+    ns = synth.log_uniform_lengths(1, 30000, 20, 61).tolist()
+    forward(ns, 600, range(len(ns)))
+    many = synth.log_uniform_lengths(1, 64, 40000, 62).tolist()
+    forward(many, 700, list(range(0, 40000, 97)) + [39999])
+    few = [1, 5, 4096, 4097, 12345, 3, 64]
+    forward(few, 800, range(len(few)))
+    lens = seeded_lengths(12, 1, 9000, 63)
+    jobs, host = make_jobs(ctxgl, p, lens, 900)
+    libtft.poly_mul_batch(ctxgl, jobs)
+    torch.cuda.synchronize()
+    for (A, B), (_, _, X, _) in zip(host, jobs):
+        assert (X.cpu().numpy().astype(np.uint64) == expected(p, g, A, B)).all()
+
+
 def test_exact_integer_product_crt():
     ctxs = [libtft.Context(p, g) for p, g in synth.CRT_PRIMES]
     try:
