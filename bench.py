@@ -593,10 +593,24 @@ def served_c4(ctx, seconds, plain_seconds):
               "mean_r": int(np.mean([r for _, _, r in tickets])), "batches": st["batches"],
               "deferred": st["deferred"], "pool_words": st["pool_words"], "pool_used_max": st["pool_used_max"],
               "submitter_waits": blocked}
+    # every output slot the stream wrote holds its pair's product: compare
+    # with the plain path's poly_mul of the same pair (outside the timings)
+    Y = torch.empty(1 << 22, dtype=torch.uint64, device="cuda")
+    Z = torch.empty(1 << 22, dtype=torch.uint64, device="cuda")
+    used = {key for key in last}
+    same = True
+    for k, (A, B, Xs) in enumerate(pairs):
+        r = Xs[0].numel()
+        libtft.poly_mul(ctx, A, B, Z[:r], Y[:r])
+        for slot in range(SLOTS):
+            if (k, slot) in used:
+                same &= bool(torch.equal(Xs[slot], Z[:r]))
+    torch.cuda.synchronize()
+    served["outputs_checked"] = len(used)
+    served["served_equals_plain"] = same
     # plain FIFO path on a prefix of the same stream
     print(f"[bench] plain FIFO stream {plain_seconds} s", file=sys.stderr, flush=True)
     sub = arrivals[arrivals < plain_seconds]
-    Y = torch.empty(1 << 22, dtype=torch.uint64, device="cuda")
     torch.cuda.synchronize()
     base = time.monotonic_ns() + 20_000_000
     lat_p = []
