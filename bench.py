@@ -24,6 +24,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -565,6 +566,11 @@ def served_c4(ctx, seconds, plain_seconds):
     last = {}
     tickets = []
     torch.cuda.synchronize()
+    # the submitting loop is this benchmark's client, not the system under
+    # test: a garbage-collection pause in it (tens of ms after the earlier
+    # extras left many objects) would delay every arrival in its window
+    gc.collect()
+    gc.disable()
     base = time.monotonic_ns() + 20_000_000
     blocked = 0
     for i, ta in enumerate(arrivals.tolist()):
@@ -583,6 +589,7 @@ def served_c4(ctx, seconds, plain_seconds):
         tickets.append((t, t_arr, int(rs[k])))
     for t, _, _ in tickets:
         q.wait(t)
+    gc.enable()
     end = max(q.completion_ns(t) for t, _, _ in tickets)
     lat = np.array([(q.completion_ns(t) - ta) / 1e3 for t, ta, _ in tickets])
     st = q.stats()
@@ -612,6 +619,8 @@ def served_c4(ctx, seconds, plain_seconds):
     print(f"[bench] plain FIFO stream {plain_seconds} s", file=sys.stderr, flush=True)
     sub = arrivals[arrivals < plain_seconds]
     torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
     base = time.monotonic_ns() + 20_000_000
     lat_p = []
     for i, ta in enumerate(sub.tolist()):
@@ -624,6 +633,7 @@ def served_c4(ctx, seconds, plain_seconds):
         torch.cuda.synchronize()
         lat_p.append((time.monotonic_ns() - t_arr) / 1e3)
     end_p = time.monotonic_ns()
+    gc.enable()
     lat_p = np.array(lat_p)
     plain = {"requests": len(sub), "duration_s": round((end_p - base) / 1e9, 3),
              "mults_per_s": round(len(sub) / ((end_p - base) / 1e9), 1),
