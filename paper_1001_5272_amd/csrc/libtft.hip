@@ -202,7 +202,11 @@ auto col_inv_list_kernel(int logC) {
     return logC == 3 ? tft::k_col_inv_list<Mod, 3> : tft::k_col_inv_list<Mod, 4>;
 }
 
-Plan make_plan(const tft_ctx* ctx, uint64_t n) {
+// wide: prefer rows one step wider than the balanced split (W = 2^(floor(k/2)+1)
+// rather than 2^floor(k/2) at k = floor(lg n) even); the batches use it: their
+// many small tiles pay a latency per tile, and fewer, taller column tiles with
+// longer rows measured 6-7 % faster batches.
+Plan make_plan(const tft_ctx* ctx, uint64_t n, bool wide = false) {
     Plan P{};
     P.n = n;
     const unsigned w = ctx->wbytes;
@@ -245,7 +249,8 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n) {
         for (unsigned logW = logC; logW <= 16 && (1ull << logW) < n; logW++) {
             fill(logW);
             if (P.lds_col > lim || P.lds_row > lim) continue;
-            if (best < 0 || std::abs(2 * (int)logW - (int)k) <= std::abs(2 * best - (int)k)) best = (int)logW;
+            const int t = (int)k + (wide ? 1 : 0);
+            if (best < 0 || std::abs(2 * (int)logW - t) <= std::abs(2 * best - t)) best = (int)logW;
         }
         if (best >= 0) {
             fill((unsigned)best);
@@ -780,7 +785,7 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
         if (!D.a || !D.out || D.la == 0 || (products && (!D.b || D.lb == 0))) return TFT_EINVAL;
         const uint64_t r = products ? D.la + D.lb - 1 : D.la;
         if (log2u(r) > ctx->v) return TFT_ERANGE;
-        const Plan P = make_plan(ctx, r);
+        const Plan P = make_plan(ctx, r, true);
         if (P.kind < 0) return TFT_ERANGE;
         const size_t Mr = pow2ceil(r);
         const size_t small_lds = ((products ? 2 : 1) * (size_t)tft::padded_words((uint32_t)Mr) + Mr) * w;   // data + twiddles
