@@ -837,11 +837,6 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
             }
         }
     }
-    // the column lists: a multiple of 8 items, so that their launches can
-    // keep consecutive items on one XCD (padding items do nothing)
-    for (int ph : {PH_COL_FWD, PH_COL_INV_SHORT, PH_COL_INV_LONG})
-        if (items[ph].size() >= 16)
-            while (items[ph].size() & 7u) items[ph].push_back({tft::kNoRec, 0});
     // longest single-workgroup jobs first
     std::stable_sort(jobs.begin(), jobs.end(), [](const tft::SmallJob<Word>& x, const tft::SmallJob<Word>& y) {
         return (uint64_t)x.m + x.nb > (uint64_t)y.m + y.nb;

@@ -1131,15 +1131,11 @@ struct Item {
     uint32_t rec;
     uint32_t idx;
 };
-// a padding item (the column lists are padded to a multiple of 8 for xcd_remap)
-constexpr uint32_t kNoRec = 0xffffffffu;
 template <class Mod, int LOGC>
 __global__ __launch_bounds__(kColThreads) void k_col_fwd_list(Mod md, Tables<typename Mod::Word> T,
                                                            const TwoPass<typename Mod::Word>* recs,
                                                            const Item* items) {
-    // consecutive items (adjacent tiles, sharing 128-byte lines) on one XCD
-    const Item it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    if (it.rec == kNoRec) return;
+    const Item it = items[blockIdx.x];
     col_fwd_body<Mod, LOGC>(md, T, recs[it.rec], it.idx);
 }
 template <class Mod>
@@ -1160,8 +1156,7 @@ template <class Mod, int LOGC>
 __global__ __launch_bounds__(kColThreads) void k_col_inv_list(Mod md, Tables<typename Mod::Word> T,
                                                            const TwoPass<typename Mod::Word>* recs,
                                                            const Item* items, int phase) {
-    const Item it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    if (it.rec == kNoRec) return;
+    const Item it = items[blockIdx.x];
     col_inv_body<Mod, LOGC>(md, T, recs[it.rec], phase, it.idx);
 }
 template <class Mod>
