@@ -30,6 +30,10 @@ MUTATIONS = {
     # schoolbook: transposed index
     "schoolbook_index": ("C[i + j] = or_addmod(C[i + j], or_mulmod(A[i] % p, B[j] % p, p), p);",
                          "C[i + j] = or_addmod(C[i + j], or_mulmod(A[j % m] % p, B[i % nb] % p, p), p);"),
+    # operation counts: the final multiply of the correction is not counted
+    "counts_drop_final_multiply": ("if (m & 1) *corr += (m - 1) / 2 + 1;", "if (m & 1) *corr += (m - 1) / 2;"),
+    # operation counts: a node of length m counts ceil(m/2) butterflies
+    "counts_butterfly_ceil": ("*bf += m / 2;", "*bf += (m + 1) / 2;"),
     # interpolation: sign slip in building M
     "lagrange_sign": ("M[0] = or_submod(0, or_mulmod(M[0], w[s], p), p);", "M[0] = or_mulmod(M[0], w[s], p);"),
 }
@@ -82,6 +86,14 @@ def pins_pass(so):
         Xp = np.zeros(len(c["F"]), dtype=np.uint64)
         L.or_fft_padded(17, 3, arr(c["F"]).ctypes.data_as(P), len(c["F"]), 0, Xp.ctypes.data_as(P))
         if [int(x) for x in Xp] != c["X"]:
+            return False
+    # operation counts of Algorithm 1 derived by hand (tests/test_oracle_transform.py)
+    L.or_paper_counts.restype = ctypes.c_int
+    L.or_paper_counts.argtypes = [u64, P, P]
+    for n, want in ((3, (2, 2)), (5, (5, 5)), (6, (7, 4)), (7, (9, 6))):
+        bf, corr = np.zeros(1, dtype=np.uint64), np.zeros(1, dtype=np.uint64)
+        L.or_paper_counts(u64(n), bf.ctypes.data_as(P), corr.ctypes.data_as(P))
+        if (int(bf[0]), int(corr[0])) != want:
             return False
     rng = np.random.default_rng(0)
     A, B = rng.integers(0, 1000, 9), rng.integers(0, 1000, 5)

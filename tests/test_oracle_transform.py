@@ -172,6 +172,46 @@ def test_paper_operation_counts():
         assert b == k * (1 << (k - 1)) + 1
 
 
+# Operation counts of Algorithm 1 (section 3), derived by hand from the tree
+# of section 3 (node (q, r) = the strided subarray X_{q + i 2^r}, length
+# m = ceil((n - q) / 2^r), even child (q, r+1), odd child (q + 2^r, r+1)).  A
+# node of length m >= 2 does floor(m / 2) butterflies (eq. 1); a node of odd
+# length m >= 3 does the odd-length correction v = sum_{i <= (m-3)/2}
+# S_{2i+1} w_{(m-1)/2}^i, S_{m-1} += v w_{m-1}, counted as one mulmod per term
+# of the sum ((m-1)/2 terms) plus the final multiply by w_{m-1}.
+#
+# n = 3: root (0,0) m=3: 1 butterfly, correction 1+1 = 2; (0,1) m=2: 1
+#        butterfly; (1,1) m=1.                      -> 2 butterflies, 2 mulmods
+# n = 5: root m=5: 2 bf, corr 2+1 = 3; (0,1) m=3: 1 bf, corr 2; (0,2) m=2: 1 bf;
+#        (2,2) m=1; (1,1) m=2: 1 bf.               -> 5 butterflies, 5 mulmods
+# n = 6 (the tree of Figure 1): root m=6: 3 bf; (0,1) = {X0,X2,X4} m=3: 1 bf,
+#        corr 2; (0,2) = {X0,X4} m=2: 1 bf; (2,2) = {X2} leaf; (1,1) =
+#        {X1,X3,X5} m=3: 1 bf, corr 2; (1,2) = {X1,X5} m=2: 1 bf; (3,2) = {X3}
+#        leaf.                                     -> 7 butterflies, 4 mulmods
+# n = 7: root m=7: 3 bf, corr 3+1 = 4; (0,1) m=4: 2 bf; (0,2) m=2: 1 bf;
+#        (2,2) m=2: 1 bf; (1,1) m=3: 1 bf, corr 2; (1,2) m=2: 1 bf; (3,2) m=1.
+#                                                  -> 9 butterflies, 6 mulmods
+HAND_COUNTS = {3: (2, 2), 5: (5, 5), 6: (7, 4), 7: (9, 6)}
+
+
+def test_paper_operation_counts_by_hand():
+    for n, (bf, corr) in HAND_COUNTS.items():
+        assert oracle.paper_counts(n) == (bf, corr), n
+
+
+def test_paper_butterflies_closed_form():
+    # Every position x < n sits, at tree depth r >= 1, in an odd child exactly
+    # when bit r-1 of x is set (odd children at depth r are the nodes
+    # (q, r) with 2^(r-1) <= q < 2^r), and a node's butterflies are the length
+    # of its odd child (floor(m / 2) = ceil((n - q - 2^r) / 2^(r+1))).  So the
+    # butterflies of Algorithm 1 number sum_{x < n} popcount(x) for every n;
+    # this gives 13,646 at n = 2499.
+    for n in list(range(1, 300)) + [2499, 4097, 12345]:
+        b, _ = oracle.paper_counts(n)
+        assert b == sum(bin(x).count("1") for x in range(n)), n
+    assert oracle.paper_counts(2499)[0] == 13646
+
+
 def test_sample_and_eval():
     p, g = PRIMES["goldilocks"]
     F = rnd(p, 1000, 4)
