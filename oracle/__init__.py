@@ -78,6 +78,9 @@ def lib():
             "or_itft_paper": (ctypes.c_int, [_u64, _u64, _P, _u64]),
             "or_node_len": (_u64, [_u64, _u64, ctypes.c_uint]),
             "or_paper_counts": (ctypes.c_int, [_u64, _P, _P]),
+            "or_tft_inplace": (ctypes.c_int, [_u64, _u64, _P, _u64]),
+            "or_itft_inplace": (ctypes.c_int, [_u64, _u64, _P, _u64]),
+            "or_mul_restricted": (ctypes.c_int, [_u64, _u64, _P, _u64, _P, _u64, _P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -173,6 +176,28 @@ def itft_paper(p, g, Y):
     F = _vec(Y).copy()
     _check(lib().or_itft_paper(p, g, _ptr(F), len(F)), "itft_paper")
     return F
+
+
+def tft_inplace(p, g, F):
+    """Algorithm 1 with O(1) auxiliary space (no root table, no recursion)."""
+    X = _vec(F).copy()
+    _check(lib().or_tft_inplace(p, g, _ptr(X), len(X)), "tft_inplace")
+    return X
+
+
+def itft_inplace(p, g, Y):
+    """Algorithm 2 with O(1) auxiliary space."""
+    F = _vec(Y).copy()
+    _check(lib().or_itft_inplace(p, g, _ptr(F), len(F)), "itft_inplace")
+    return F
+
+
+def mul_restricted(p, g, A, B):
+    """Algorithm 3: the product written into its r-word output only."""
+    A, B = _vec(A), _vec(B)
+    X = np.zeros(len(A) + len(B) - 1, dtype=np.uint64)
+    _check(lib().or_mul_restricted(p, g, _ptr(A), len(A), _ptr(B), len(B), _ptr(X)), "mul_restricted")
+    return X
 
 
 def paper_counts(n):

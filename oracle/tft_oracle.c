@@ -442,3 +442,202 @@ int or_paper_counts(u64 n, u64 *butterflies, u64 *corrections)
     count_node(n, 0, 0, butterflies, corrections);
     return 0;
 }
+
+/* ------------------- the paper's algorithms with O(1) auxiliary space (CPU) */
+/* The same transforms as or_tft_paper / or_itft_paper (sections 3 and 4), now
+ * with a constant number of scalars besides X: no root table and no
+ * recursion.  This is the plain CPU TFT that the benchmark times beside the
+ * GPU path; it must agree with or_tft_direct and or_itft_lagrange.
+ *
+ * Roots on the fly.  From w_s = w[k]^(rev_k s) (section 2.2) and
+ * w[k]^(2^(k-1-i)) = w[i+1], a root is the product over the set bits i of s of
+ * w[i+1].  The butterflies of a node need w_{2j} for j = 0, 1, ...: stepping
+ * j -> j+1 clears the trailing ones of j (bits 0..t-1) and sets bit t, so
+ * w_{2j+2} = w_{2j} w[t+2] / (w[2] ... w[t+1]): amortised O(1) products from
+ * the chain w[1..v] and its inverses (at most 65 words each, independent of
+ * n).
+ *
+ * Traversal.  A node (q, r) of the tree of section 3 has length
+ * ceil((n - q) / 2^r); its parent is (q with bit r-1 cleared, r-1), and it is
+ * the odd child exactly when bit r-1 of q is set, so the walk needs no stack:
+ * the state is the current node and whether it was just entered or just
+ * returned to from its even or its odd child.  Forward: enter a node of
+ * length m > 1 -> enter its even child; back from the even child -> if m is
+ * odd apply the correction (the raw odd coefficients evaluated at
+ * w_{(m-1)/2}, times w_{m-1}, added into S_{m-1}) and enter the odd child;
+ * back from the odd child -> the butterflies of eq. (1), then return to the
+ * parent.  Inverse (section 4): enter -> inverse butterflies, then enter the
+ * odd child; back from the odd child -> remove the correction (its odd
+ * coefficients are raw again) and enter the even child; back from the even
+ * child -> return to the parent. */
+typedef struct {
+    u64 p;
+    unsigned v;
+    u64 w[65], wi[65];   /* w[j], w[j]^-1, j <= v */
+} chain_ctx;
+
+static void chain_init(chain_ctx *c, u64 p, u64 g)
+{
+    c->p = p;
+    c->v = or_two_adic(p);
+    for (unsigned j = 0; j <= c->v && j <= 64; j++) {
+        c->w[j] = or_root_chain(p, g, j);
+        c->wi[j] = or_invmod(c->w[j], p);
+    }
+}
+
+/* w_s (inverse: w_s^-1) from the set bits of s */
+static u64 chain_root(const chain_ctx *c, u64 s, int inverse)
+{
+    u64 r = 1 % c->p;
+    for (unsigned i = 0; s; i++, s >>= 1)
+        if (s & 1) r = or_mulmod(r, inverse ? c->wi[i + 1] : c->w[i + 1], c->p);
+    return r;
+}
+
+/* the odd-length correction of node (q, r), length m odd: w_{m-1} H(w_{(m-1)/2})
+ * with H(y) = sum_i S_{2i+1} y^i over the node's (raw) odd entries */
+static u64 inplace_correction(const chain_ctx *c, const u64 *X, u64 q, unsigned r, u64 m)
+{
+    const u64 st = (u64)1 << r, p = c->p;
+    const u64 z = chain_root(c, (m - 1) / 2, 0);
+    u64 h = 0;
+    for (u64 i = (m - 1) / 2; i-- > 0;) h = or_addmod(or_mulmod(h, z, p), X[q + (2 * i + 1) * st], p);
+    return or_mulmod(h, chain_root(c, m - 1, 0), p);
+}
+
+/* eq. (1) at node (q, r) of length m: S_{2j}, S_{2j+1} <- S_{2j} +/- w_{2j} S_{2j+1};
+ * inverse: S_{2j}, S_{2j+1} <- (S_{2j} + S_{2j+1}) / 2, w_{2j}^-1 (S_{2j} - S_{2j+1}) / 2.
+ * w_{2j} runs over the even indices: the product over the set bits i of j of w[i+2]. */
+static void inplace_butterflies(const chain_ctx *c, u64 *X, u64 q, unsigned r, u64 m, int inverse)
+{
+    const u64 st = (u64)1 << r, p = c->p, half = (p + 1) / 2;
+    u64 tw = 1 % p;   /* w_{2j} (inverse: its inverse) */
+    for (u64 j = 0; j < m / 2; j++) {
+        u64 *e = &X[q + 2 * j * st], *o = &X[q + (2 * j + 1) * st];
+        if (!inverse) {
+            u64 t = or_mulmod(tw, *o, p), a = *e;
+            *e = or_addmod(a, t, p);
+            *o = or_submod(a, t, p);
+        } else {
+            u64 a = *e, b = *o;
+            *e = or_mulmod(or_addmod(a, b, p), half, p);
+            *o = or_mulmod(or_mulmod(or_submod(a, b, p), half, p), tw, p);
+        }
+        /* w_{2(j+1)}: step j -> j+1 in the chain shifted by one level */
+        unsigned t = 0;
+        while ((j >> t) & 1) {
+            tw = or_mulmod(tw, inverse ? c->w[t + 2] : c->wi[t + 2], p);
+            t++;
+        }
+        if (j + 1 < m / 2) tw = or_mulmod(tw, inverse ? c->wi[t + 2] : c->w[t + 2], p);
+    }
+}
+
+enum { ENTER = 0, FROM_EVEN = 1, FROM_ODD = 2 };
+
+static void inplace_walk(const chain_ctx *c, u64 *X, u64 n, int inverse)
+{
+    const u64 p = c->p;
+    u64 q = 0;
+    unsigned r = 0;
+    int state = ENTER;
+    for (;;) {
+        const u64 m = or_node_len(n, q, r), st = (u64)1 << r;
+        if (state == ENTER && m > 1) {
+            if (!inverse) {
+                r++;                              /* even child (q, r+1) */
+                continue;
+            }
+            inplace_butterflies(c, X, q, r, m, 1);
+            q += st;                              /* odd child (q + 2^r, r+1) */
+            r++;
+            continue;
+        }
+        if (state == FROM_EVEN && !inverse) {
+            if (m & 1) {
+                u64 *last = &X[q + (m - 1) * st];
+                *last = or_addmod(*last, inplace_correction(c, X, q, r, m), p);
+            }
+            q += st;
+            r++;
+            state = ENTER;
+            continue;
+        }
+        if (state == FROM_ODD && inverse) {
+            if (m & 1) {
+                u64 *last = &X[q + (m - 1) * st];
+                *last = or_submod(*last, inplace_correction(c, X, q, r, m), p);
+            }
+            r++;                                  /* even child */
+            state = ENTER;
+            continue;
+        }
+        if (state == FROM_ODD && !inverse) inplace_butterflies(c, X, q, r, m, 0);
+        /* this node is finished (a leaf, or its last step is done): back to the parent */
+        if (r == 0) return;
+        const u64 bit = (u64)1 << (r - 1);
+        state = (q & bit) ? FROM_ODD : FROM_EVEN;
+        q &= ~bit;
+        r--;
+    }
+}
+
+static int inplace_run(u64 p, u64 g, u64 *X, u64 n, int inverse)
+{
+    if (!n_ok(p, n) || !X) return -1;
+    chain_ctx c;
+    chain_init(&c, p, g);
+    for (u64 s = 0; s < n; s++) X[s] %= p;
+    inplace_walk(&c, X, n, inverse);
+    return 0;
+}
+
+int or_tft_inplace(u64 p, u64 g, u64 *X, u64 n) { return inplace_run(p, g, X, n, 0); }
+int or_itft_inplace(u64 p, u64 g, u64 *X, u64 n) { return inplace_run(p, g, X, n, 1); }
+
+/* Section 5, Algorithm 3 (Proposition 5.1): C = A B into X (r = m + nb - 1
+ * words) with X the only memory written besides O(1) scalars.  The blocks:
+ * q = 0, then q += L, with L the largest power of two such that q + 2L <= r
+ * (so L | q).  For each block the coefficients of A(w_q x) mod x^L - 1 (the
+ * terms w_q^i A_i summed into slot i mod L) are transformed in
+ * X[q, q+L): since L | q, w_q w_i = w_{q+i}, so the slots then hold
+ * A(w_{q+i}); the same for B in X[q+L, q+2L); the products go to X[q, q+L).
+ * The last point w_{r-1} has no room for two values: X[r-1] = A(w_{r-1})
+ * B(w_{r-1}) by direct evaluation.  Then the in-place inverse of length r. */
+int or_mul_restricted(u64 p, u64 g, const u64 *A, u64 m, const u64 *B, u64 nb, u64 *X)
+{
+    if (!A || !B || !X || m == 0 || nb == 0) return -1;
+    const u64 r = m + nb - 1;
+    if (!n_ok(p, r)) return -2;
+    chain_ctx c;
+    chain_init(&c, p, g);
+    u64 q = 0;
+    while (q + 1 < r) {
+        unsigned l = 0;
+        while (q + ((u64)4 << l) <= r) l++;    /* largest L = 2^l with q + 2L <= r */
+        const u64 L = (u64)1 << l;
+        const u64 wq = chain_root(&c, q, 0);
+        for (int side = 0; side < 2; side++) {
+            const u64 *P = side ? B : A;
+            const u64 len = side ? nb : m;
+            u64 *blk = X + q + (side ? L : 0);
+            for (u64 i = 0; i < L; i++) blk[i] = 0;
+            u64 zi = 1 % p;   /* w_q^i */
+            for (u64 i = 0; i < len; i++) {
+                blk[i % L] = or_addmod(blk[i % L], or_mulmod(zi, P[i] % p, p), p);
+                zi = or_mulmod(zi, wq, p);
+            }
+            inplace_walk(&c, blk, L, 0);     /* a full transform: L is a power of two */
+        }
+        for (u64 i = 0; i < L; i++) X[q + i] = or_mulmod(X[q + i], X[q + L + i], p);
+        q += L;
+    }
+    const u64 z = chain_root(&c, r - 1, 0);
+    u64 a = 0, b = 0;
+    for (u64 i = m; i-- > 0;) a = or_addmod(or_mulmod(a, z, p), A[i] % p, p);
+    for (u64 i = nb; i-- > 0;) b = or_addmod(or_mulmod(b, z, p), B[i] % p, p);
+    X[r - 1] = or_mulmod(a, b, p);
+    inplace_walk(&c, X, r, 1);
+    return 0;
+}

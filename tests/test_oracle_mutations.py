@@ -34,6 +34,18 @@ MUTATIONS = {
     "counts_drop_final_multiply": ("if (m & 1) *corr += (m - 1) / 2 + 1;", "if (m & 1) *corr += (m - 1) / 2;"),
     # operation counts: a node of length m counts ceil(m/2) butterflies
     "counts_butterfly_ceil": ("*bf += m / 2;", "*bf += (m + 1) / 2;"),
+    # in-place walk (O(1) space): the odd-length correction is skipped
+    "inplace_no_correction": ("*last = or_addmod(*last, inplace_correction(c, X, q, r, m), p);", "(void)last;"),
+    # in-place walk: the on-the-fly root steps one level too low (w_j instead of w_{2j})
+    "inplace_root_step": ("if (j + 1 < m / 2) tw = or_mulmod(tw, inverse ? c->wi[t + 2] : c->w[t + 2], p);",
+                          "if (j + 1 < m / 2) tw = or_mulmod(tw, inverse ? c->wi[t + 1] : c->w[t + 1], p);"),
+    # in-place inverse: the correction is added back instead of removed
+    "inplace_inverse_sign": ("*last = or_submod(*last, inplace_correction(c, X, q, r, m), p);",
+                             "*last = or_addmod(*last, inplace_correction(c, X, q, r, m), p);"),
+    # Algorithm 3: the fold leaves out the twist by w_q
+    "restricted_no_twist": ("                zi = or_mulmod(zi, wq, p);\n", ""),
+    # Algorithm 3: the last point keeps only A's value
+    "restricted_last_point": ("X[r - 1] = or_mulmod(a, b, p);", "X[r - 1] = a;"),
     # interpolation: sign slip in building M
     "lagrange_sign": ("M[0] = or_submod(0, or_mulmod(M[0], w[s], p), p);", "M[0] = or_mulmod(M[0], w[s], p);"),
 }
@@ -55,7 +67,8 @@ def pins_pass(so):
     import json
     L = ctypes.CDLL(str(so))
     u64, P = ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)
-    for f in ("or_tft_direct", "or_itft_lagrange", "or_tft_paper", "or_mul_schoolbook"):
+    for f in ("or_tft_direct", "or_itft_lagrange", "or_tft_paper", "or_mul_schoolbook", "or_tft_inplace",
+              "or_itft_inplace", "or_mul_restricted"):
         getattr(L, f).restype = ctypes.c_int
     L.or_fft_padded.restype = ctypes.c_int
     L.or_fft_padded.argtypes = [u64, u64, P, u64, ctypes.c_uint, P]
@@ -83,6 +96,13 @@ def pins_pass(so):
         L.or_tft_paper(u64(17), u64(3), X.ctypes.data_as(P), u64(len(X)))
         if [int(x) for x in X] != c["X"]:
             return False
+        X = arr(c["F"]).copy()
+        L.or_tft_inplace(u64(17), u64(3), X.ctypes.data_as(P), u64(len(X)))
+        if [int(x) for x in X] != c["X"]:
+            return False
+        L.or_itft_inplace(u64(17), u64(3), X.ctypes.data_as(P), u64(len(X)))
+        if [int(x) for x in X] != c["F"]:
+            return False
         Xp = np.zeros(len(c["F"]), dtype=np.uint64)
         L.or_fft_padded(17, 3, arr(c["F"]).ctypes.data_as(P), len(c["F"]), 0, Xp.ctypes.data_as(P))
         if [int(x) for x in Xp] != c["X"]:
@@ -102,6 +122,13 @@ def pins_pass(so):
                         C.ctypes.data_as(P))
     if [int(c) for c in C] != [int(x) for x in np.convolve(A, B) % 998244353]:
         return False
+    for m, nb in ((1, 1), (2, 1), (3, 4), (9, 5), (7, 7), (16, 17)):   # r = 1 .. 32: one to five blocks
+        A, B = rng.integers(0, 1000, m), rng.integers(0, 1000, nb)
+        C = np.zeros(m + nb - 1, dtype=np.uint64)
+        L.or_mul_restricted(u64(998244353), u64(3), arr(A).ctypes.data_as(P), u64(m), arr(B).ctypes.data_as(P),
+                            u64(nb), C.ctypes.data_as(P))
+        if [int(c) for c in C] != [int(x) for x in np.convolve(A, B) % 998244353]:
+            return False
     return True
 
 

@@ -57,6 +57,30 @@ def test_product_through_tft_and_interpolation():
         assert (oracle.itft_lagrange(p, g, XC) == oracle.mul_schoolbook(p, A[:m], B[:nb])).all()
 
 
+@pytest.mark.parametrize("name", ["p257", "p998244353", "goldilocks"])
+def test_space_restricted_product(name):
+    """Algorithm 3 (section 5) gives the unique product: against the schoolbook
+    product for every shape up to 24 x 24 (r = 1 .. 47: one to several
+    blocks, r a power of two and one either side), against numpy.convolve on
+    small values, and against the padded product at larger r."""
+    p, g = PRIMES[name]
+    rng = random.Random(31)
+    for m in range(1, 25):
+        for nb in range(1, 25):
+            if (m + nb - 2).bit_length() > oracle.two_adic(p):
+                continue
+            A = np.array([rng.randrange(p) for _ in range(m)], dtype=np.uint64)
+            B = np.array([rng.randrange(p) for _ in range(nb)], dtype=np.uint64)
+            assert (oracle.mul_restricted(p, g, A, B) == oracle.mul_schoolbook(p, A, B)).all(), (m, nb)
+    A, B = np.arange(1, 40), np.arange(7, 20)
+    assert [int(c) for c in oracle.mul_restricted(p, g, A, B)] == [int(x) % p for x in np.convolve(A, B)]
+    if p > 2**20:
+        for m, nb in [(1000, 1500), (4096, 4097), (3000, 1)]:
+            A = np.array([rng.randrange(p) for _ in range(m)], dtype=np.uint64)
+            B = np.array([rng.randrange(p) for _ in range(nb)], dtype=np.uint64)
+            assert (oracle.mul_restricted(p, g, A, B) == oracle.mul_padded(p, g, A, B)).all(), (m, nb)
+
+
 def test_exact_signed_product_against_python():
     rng = random.Random(4)
     for m, nb in [(1, 1), (5, 3), (64, 64), (200, 17)]:

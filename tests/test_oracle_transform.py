@@ -9,6 +9,9 @@
   ways and, at n = 2^k, agree with the closed-form inverse DFT.
 - tft_paper / itft_paper (Algorithms 1 and 2 in recursive form) must agree
   with the definition; the tree they walk is pinned to Figure 1.
+- tft_inplace / itft_inplace (the same algorithms with O(1) auxiliary space:
+  roots on the fly, a stackless walk) must agree with the definition and
+  invert each other.
 """
 import json
 import os
@@ -42,6 +45,8 @@ def test_golden_cases():
         assert [int(x) for x in oracle.tft_paper(17, 3, c["F"])] == c["X"]
         assert [int(x) for x in oracle.itft_lagrange(17, 3, c["X"])] == c["F"]
         assert [int(x) for x in oracle.itft_paper(17, 3, c["X"])] == c["F"]
+        assert [int(x) for x in oracle.tft_inplace(17, 3, c["F"])] == c["X"]
+        assert [int(x) for x in oracle.itft_inplace(17, 3, c["X"])] == c["F"]
 
 
 @pytest.mark.parametrize("name", ["p17", "p998244353", "goldilocks"])
@@ -157,6 +162,21 @@ def test_paper_algorithms_match_definition(name):
         X = oracle.tft_direct(p, g, F) if n <= 700 else oracle.fft_padded(p, g, F)
         assert (oracle.tft_paper(p, g, F) == X).all(), n
         assert (oracle.itft_paper(p, g, X) == F).all(), n
+        assert (oracle.tft_inplace(p, g, F) == X).all(), n
+        assert (oracle.itft_inplace(p, g, X) == F).all(), n
+
+
+@pytest.mark.parametrize("name", ["p257", "p7681", "p998244353", "goldilocks"])
+def test_inplace_algorithms_every_length(name):
+    """Every length up to 300 (or 2^v): the O(1)-space walks equal the
+    definition F^_s = F(w_s) and invert each other."""
+    p, g = PRIMES[name]
+    v = oracle.two_adic(p)
+    for n in range(1, min(300, 1 << v) + 1):
+        F = rnd(p, n, 11 * n + 5)
+        X = oracle.tft_direct(p, g, F)
+        assert (oracle.tft_inplace(p, g, F) == X).all(), n
+        assert (oracle.itft_inplace(p, g, X) == F).all(), n
 
 
 def test_paper_operation_counts():
