@@ -85,6 +85,23 @@ tft_status tft_pointwise_mul(tft_ctx* ctx, void* X, const void* Y, size_t n, voi
 tft_status poly_mul(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X, void* Y,
                     void* hip_stream);
 
+/* poly_mul for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same product C = A B into X (r = m + nb - 1 words), bit-identical to
+ * poly_mul's, with B's transform held in a fixed library-owned device array
+ * of 32 MiB per device (allocated when the library is loaded, kept until the
+ * process ends) instead of the caller's workspace Y.  The call allocates and
+ * frees nothing (outside measurement mode, tft_timing_enable).  Limit: r <= 2^22 words for 8-byte contexts and r <= 2^23
+ * for 4-byte contexts; a longer product returns TFT_ERANGE before any work is
+ * enqueued.  Every call on one device shares that device's array and leaves
+ * its contents behind (each call overwrites the r words it uses before reading
+ * them): calls on one device must not overlap -- issue them on one stream, or
+ * synchronise between streams; overlapping calls race and give wrong results.
+ * TFT_EDEVICE if the array's device address could not be obtained when the
+ * context was created.  Other errors as for poly_mul. */
+tft_status poly_mul_noalloc(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X,
+                            void* hip_stream);
+
 /* Space-restricted product (section 5, Algorithm 3; Proposition 5.1): the same
  * C = A B with X (r = m + nb - 1 words) as the only memory written -- no
  * workspace.  For q = 0, L_0, L_0 + L_1, ... (L the largest power of two with

@@ -25,6 +25,32 @@
 using tft::kB1;
 using tft::kThreads;
 
+// Workspace of poly_mul_noalloc: B's transform (the r words that poly_mul takes
+// from the caller) lives in this fixed device array instead.  Every device the
+// library runs on holds its own copy from module load until the process ends.
+// In host code the name is only a handle: the array's address on a device
+// comes from hipGetSymbolAddress with that device current (noalloc_setup).
+constexpr size_t kNoAllocBytes = size_t(32) << 20;   // 32 MiB: 2^22 words of 8 bytes, 2^23 of 4
+static __device__ __align__(256) uint64_t scratch[kNoAllocBytes / 8];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+std::atomic<void*> g_noalloc_ptr[kMaxDevices];
+
+// Once per device, with that device current: the device address of scratch.
+hipError_t noalloc_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipSuccess;   // poly_mul_noalloc reports TFT_EDEVICE
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[device].load(std::memory_order_acquire)) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_noalloc_ptr[device].store(ptr, std::memory_order_release);
+    return hipSuccess;
+}
+}  // namespace
+
 namespace {
 
 constexpr uint64_t kGoldilocks = 0xFFFFFFFF00000001ull;
@@ -107,7 +133,7 @@ struct tft_ctx {
     tft::ModGL m64;
     void* tables;        // f1 | f2 | i1 | i2
     size_t n1, n2;       // entries per level
-    void* scratch;       // V_c area and column polynomial (kScratchWords words)
+    void* varea;         // V_c area and column polynomial (kScratchWords words)
     // measurement mode (tft_timing_*): events bracketing each launch of the
     // kernels selected in timing_mask (bit = tft_kernel_id)
     bool timing;
@@ -357,7 +383,7 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
         return launch_status();
     }
     if (g0 && P.b) return TFT_EINVAL;   // a block at g0 != 0 is a whole power-of-two block
-    Word* V = reinterpret_cast<Word*>(ctx->scratch);
+    Word* V = reinterpret_cast<Word*>(ctx->varea);
     auto G = two_pass_of<Word>(P, X, src, n_src, nullptr, V);
     G.g0 = g0;
     const uint32_t tiles = (uint32_t)(P.W >> P.logC);
@@ -387,7 +413,7 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
                            P.M);
         return launch_status();
     }
-    Word* V = reinterpret_cast<Word*>(ctx->scratch);
+    Word* V = reinterpret_cast<Word*>(ctx->varea);
     auto G = two_pass_of<Word>(P, X, X, n, Y, V);
     // With b > 0 the columns c < b (a + 1 values) run with the columns c >= b on
     // their first a values and are finished after the last row: in split mode
@@ -501,7 +527,7 @@ tft_status fold_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, type
     uint64_t K = std::max<uint64_t>(1, std::min<uint64_t>(terms, (uint64_t(1) << 16) >> logL));
     const uint64_t chunk = (terms + K - 1) / K;
     K = (terms + chunk - 1) / chunk;
-    Word* part = reinterpret_cast<Word*>(ctx->scratch) + kVWords;   // two areas of 2^16 words
+    Word* part = reinterpret_cast<Word*>(ctx->varea) + kVWords;   // two areas of 2^16 words
     tft::FoldArgs<Word> F;
     F.A[0] = A;
     F.A[1] = B;
@@ -565,7 +591,7 @@ tft_status mul_restricted_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64
     }
     if (s != TFT_OK) return s;
     // the last point w_{r-1}: A(w_{r-1}) into X[r-1], B(w_{r-1}) into a scratch word
-    Word* tmp = reinterpret_cast<Word*>(ctx->scratch) + kVWords + 2 * size_t(tft::kQStride);
+    Word* tmp = reinterpret_cast<Word*>(ctx->varea) + kVWords + 2 * size_t(tft::kQStride);
     s = fold_impl<Mod>(ctx, A, m, X + (r - 1), B, nb, tmp, 0, r - 1, st);
     if (s != TFT_OK) return s;
     launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3(1), dim3(kThreads), 0, st, md, X + (r - 1),
@@ -1297,7 +1323,11 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
     c->n2 = c->v > (unsigned)kB1 ? size_t(1) << (c->v - kB1) : 1;
     DeviceGuard guard(device);
     size_t bytes = 0;
-    hipError_t e;
+    hipError_t e = noalloc_setup(device);
+    if (e != hipSuccess) {
+        delete c;
+        return TFT_EDEVICE;
+    }
     if (wide) {
         auto t = build_tables<uint64_t>(p, g, c->v, c->n1, c->n2, false);
         bytes = t.size() * 8;
@@ -1311,7 +1341,7 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
         if (e == hipSuccess) e = hipMemcpy(c->tables, t.data(), bytes, hipMemcpyHostToDevice);
         if (e == hipSuccess && !set_lds_limits<tft::ModU32>()) e = hipErrorInvalidValue;
     }
-    if (e == hipSuccess) e = hipMalloc(&c->scratch, kScratchWords * c->wbytes);
+    if (e == hipSuccess) e = hipMalloc(&c->varea, kScratchWords * c->wbytes);
     if (e != hipSuccess) {
         if (c->tables) (void)hipFree(c->tables);
         delete c;
@@ -1331,7 +1361,7 @@ void tft_ctx_destroy(tft_ctx* ctx) {
     if (ctx->last_done) (void)hipEventDestroy(ctx->last_done);
     arena_free(&ctx->once_arena);
     (void)hipFree(ctx->tables);
-    (void)hipFree(ctx->scratch);
+    (void)hipFree(ctx->varea);
     for (auto& r : ctx->recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -1385,6 +1415,24 @@ tft_status poly_mul(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t
     if (!ctx || !A || !B || !X || m == 0 || nb == 0) return TFT_EINVAL;
     tft_status s = check_len(ctx, m + nb - 1);
     if (s != TFT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    return dispatch(ctx, [&] {
+        if (ctx->wbytes == 4)
+            return mul_impl<tft::ModU32>(ctx, (const uint32_t*)A, m, (const uint32_t*)B, nb, (uint32_t*)X, (uint32_t*)Y,
+                                         st);
+        return mul_impl<tft::ModGL>(ctx, (const uint64_t*)A, m, (const uint64_t*)B, nb, (uint64_t*)X, (uint64_t*)Y, st);
+    });
+}
+
+tft_status poly_mul_noalloc(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X,
+                            void* stream) {
+    if (!ctx || !A || !B || !X || m == 0 || nb == 0) return TFT_EINVAL;
+    const size_t r = m + nb - 1;
+    tft_status s = check_len(ctx, r);
+    if (s != TFT_OK) return s;
+    if (r > kNoAllocBytes / ctx->wbytes) return TFT_ERANGE;   // beyond the fixed workspace
+    void* Y = ctx->device < kMaxDevices ? g_noalloc_ptr[ctx->device].load(std::memory_order_acquire) : nullptr;
+    if (!Y) return TFT_EDEVICE;
     hipStream_t st = (hipStream_t)stream;
     return dispatch(ctx, [&] {
         if (ctx->wbytes == 4)

@@ -47,6 +47,7 @@ SIGNATURES = {
     "tft_pointwise_mul": (_st, [_vp, _vp, _vp, _sz, _vp]),
     "poly_mul": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp, _vp]),
     "poly_mul_restricted": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp]),
+    "poly_mul_noalloc": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp]),
     "tft_padded_forward": (_st, [_vp, _vp, _sz, _vp, _vp]),
     "tft_padded_inverse": (_st, [_vp, _vp, _sz, _vp, _vp]),
     "poly_mul_padded": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp, _vp, _vp]),
@@ -203,6 +204,15 @@ def poly_mul(ctx: Context, A, B, X, Y=None, stream=None):
     y = ctx._t(Y, "Y") if Y is not None else _vp(0)
     _check(load().poly_mul(ctx.handle, ctx._t(A, "A"), A.numel(), ctx._t(B, "B"), B.numel(), ctx._t(X, "X"), y,
                            _stream(stream)), "poly_mul")
+    return X
+
+
+def poly_mul_noalloc(ctx: Context, A, B, X, stream=None):
+    """poly_mul with B's transform in the library's fixed device array (no
+    workspace argument, nothing allocated; r <= 2^22 words of 8 bytes or 2^23
+    of 4).  Calls on one device must not overlap."""
+    _check(load().poly_mul_noalloc(ctx.handle, ctx._t(A, "A"), A.numel(), ctx._t(B, "B"), B.numel(),
+                                   ctx._t(X, "X"), _stream(stream)), "poly_mul_noalloc")
     return X
 
 
