@@ -97,7 +97,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="only the timed step, roofline and baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-autotune", action="store_true", help="plan with the built-in planner only")
-    ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the served Poisson stream")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the served Poisson stream")
     ap.add_argument("--plain-seconds", type=float, default=1.0, help="length of the plain FIFO comparison")
     ap.add_argument("--skip", default="", help="comma list of extras to skip: products,small,walk,sweep,batched,served,crt")
     return ap.parse_args()
@@ -220,6 +220,12 @@ def main():
         "avg_launch_us": round(avg_ms * 1e3, 2), "launches": dcount,
         "hbm": {"achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(hbm_bytes)},
+        # the whole TFT+ITFT step: algorithmic bytes (each of the n words read
+        # and written once per transform) over the step time
+        "step_hbm": {"achieved": round(4 * 8 * words_per_step / (ms_per_step * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(4 * 8 * words_per_step / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "alg_bytes_per_step": 4 * 8 * words_per_step},
     }
     # the same device's register-only and copy-only ceilings (outside the timed steps)
     try:
@@ -436,9 +442,11 @@ def small_c1(dev):
     return res
 
 
-def length_sweep(ctx, p, per_octave=8):
+def length_sweep(ctx, p, per_octave=16):
     """TFT+ITFT time at lengths spread through [2^21, 2^23] (the jump-free
-    curve) next to the padded comparator."""
+    curve) next to the padded comparator; the summary gives the mean rate,
+    the largest time step between adjacent lengths and the lengths where the
+    padded comparator is faster."""
     import torch
 
     import synth
@@ -455,7 +463,12 @@ def length_sweep(ctx, p, per_octave=8):
         out.append({"n": n, "tft_itft_us": round(t * 1e3, 1), "padded_us": round(tp * 1e3, 1),
                     "gbfly_s": round(2 * nominal_butterflies(n) / (t * 1e-3) / 1e9, 1)})
         del X
-    return out
+    steps = [(b["tft_itft_us"] / a["tft_itft_us"], a["n"], b["n"]) for a, b in zip(out, out[1:])]
+    worst = max(steps)
+    summary = {"points": len(out), "mean_gbfly_s": round(sum(d["gbfly_s"] for d in out) / len(out), 1),
+               "max_adjacent_step": {"ratio": round(worst[0], 3), "from_n": worst[1], "to_n": worst[2]},
+               "slower_than_padded": [d["n"] for d in out if d["tft_itft_us"] > d["padded_us"]]}
+    return {"points": out, "summary": summary}
 
 
 def batched_c3():
@@ -535,111 +548,196 @@ def batched_c3():
             "total_output_words": total, "batch": info, "plan_ms": round(plan_ms, 1),
             "graph_ms": round(t_graph, 3), "run_ms": round(t_run, 3), "plain_ms": round(t_plain, 3),
             "mults_per_s_graph": round(count / (t_graph * 1e-3), 0), "mults_per_s_plain": round(count / (t_plain * 1e-3), 0),
-            "speedup_vs_plain": round(t_plain / t_graph, 2), "batched_equals_plain": same}
+            "speedup_vs_plain": round(t_plain / t_graph, 2), "batched_equals_plain": same,
+            # algorithmic bytes of a product: three transforms (each word read
+            # and written once) plus the pointwise read of Y: 7 r words
+            "hbm": {"alg_bytes": 7 * 4 * total, "achieved_gbs": round(7 * 4 * total / (t_graph * 1e-3) / 1e9, 1),
+                    "frac": round(7 * 4 * total / (t_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
-def served_c4(ctx, seconds, plain_seconds):
-    """Poisson stream (mean 20k requests/s) of products mod 2^64-2^32+1 with
-    product length r log-uniform in [2^8, 2^22]; operands resident in HBM; the
-    queue admits by in-place footprint.  Latency runs from the scheduled
-    arrival to the completion seen by the queue's worker.  The plain path
-    serves the same stream one request at a time (FIFO, poly_mul + wait)."""
+def served_stream(ctx, q, rate, seconds, seed, pool, ring, verify=0):
+    """One Poisson stream of products mod 2^64-2^32+1 through the queue: r
+    log-uniform in [2^8, 2^22], split la = ceil((r+1)/2), lb = r+1-la; the
+    operands of request i are windows of the resident random array `pool` at
+    seeded offsets (so every request multiplies its own polynomials) and its
+    output a window of the ring buffer `ring`, reused in order once the
+    request that held it has completed.  Latency runs from the scheduled
+    arrival to the completion seen by the queue's worker.  A submit refused for
+    footprint (TFT_EAGAIN) is retried after the oldest outstanding request
+    completes.  verify: the last `verify` requests are recomputed with
+    poly_mul (GPU, outside the timings) and compared word for word."""
     import numpy as np
     import torch
 
     import synth
     from paper_1001_5272_amd import libtft
-    print(f"[bench] served stream {seconds} s", file=sys.stderr, flush=True)
-    p = synth.GOLDILOCKS[0]
-    K, SLOTS = 256, 4
-    rs = synth.log_uniform_lengths(1 << 8, 1 << 22, K, 4001)
-    pairs = []
-    for i, r in enumerate(rs.tolist()):
-        la = (r + 2) // 2
-        lb = r + 1 - la
-        A = torch.from_numpy(synth.residues(p, la, 4100 + 2 * i)).cuda()
-        B = torch.from_numpy(synth.residues(p, lb, 4101 + 2 * i)).cuda()
-        Xs = [torch.empty(r, dtype=torch.uint64, device="cuda") for _ in range(SLOTS)]
-        pairs.append((A, B, Xs))
-    arrivals = synth.poisson_arrivals(20000.0, seconds, 4002)
-    q = libtft.Queue(ctx, 1 << 27, 4096)
-    last = {}
-    tickets = []
+    arrivals = synth.poisson_arrivals(rate, seconds, seed)
+    cnt = len(arrivals)
+    rs = synth.log_uniform_lengths(1 << 8, 1 << 22, cnt, seed + 1)
+    la = (rs + 2) // 2
+    lb = rs + 1 - la
+    P = pool.numel()
+    offa = (synth.uniform01(cnt, seed + 2) * (P - la)).astype(np.int64)
+    offb = (synth.uniform01(cnt, seed + 3) * (P - lb)).astype(np.int64)
+    R = ring.numel()
+    # output windows: consecutive in the ring, wrapping to 0 when one would cross the end
+    outs = np.zeros(cnt, dtype=np.int64)
+    cur = 0
+    for i in range(cnt):
+        if cur + rs[i] > R:
+            cur = 0
+        outs[i] = cur
+        cur += int(rs[i])
     torch.cuda.synchronize()
-    # the submitting loop is this benchmark's client, not the system under
-    # test: a garbage-collection pause in it (tens of ms after the earlier
-    # extras left many objects) would delay every arrival in its window
     gc.collect()
-    gc.disable()
+    gc.disable()   # the client's collection pauses would delay every arrival in their window
     base = time.monotonic_ns() + 20_000_000
-    blocked = 0
-    for i, ta in enumerate(arrivals.tolist()):
-        k = i % K
-        slot = (i // K) % SLOTS
-        prev = last.get((k, slot))
-        if prev is not None and not q.poll(prev):
-            blocked += 1
-            q.wait(prev)
-        t_arr = base + int(ta * 1e9)
-        while time.monotonic_ns() < t_arr:
+    tickets = [0] * cnt
+    t_arr = (base + (arrivals * 1e9).astype(np.int64)).tolist()
+    outstanding = []     # (ticket, lo, hi) in submission order
+    head = 0
+    retries = ring_waits = 0
+    for i in range(cnt):
+        lo, hi = int(outs[i]), int(outs[i] + rs[i])
+        # the ring window must be free: wait for earlier requests whose window overlaps it
+        while head < len(outstanding):
+            t0, l0, h0 = outstanding[head]
+            if h0 <= lo or l0 >= hi:
+                if q.poll(t0):
+                    head += 1
+                    continue
+                break
+            if not q.poll(t0):
+                ring_waits += 1
+                q.wait(t0)
+            head += 1
+        while time.monotonic_ns() < t_arr[i]:
             pass
-        A, B, Xs = pairs[k]
-        t = q.submit(A, B, Xs[slot])
-        last[(k, slot)] = t
-        tickets.append((t, t_arr, int(rs[k])))
-    for t, _, _ in tickets:
+        A = pool[int(offa[i]):int(offa[i] + la[i])]
+        B = pool[int(offb[i]):int(offb[i] + lb[i])]
+        X = ring[lo:hi]
+        t = q.try_submit(A, B, X)
+        while t is None:
+            retries += 1
+            k = head
+            while k < len(outstanding) and q.poll(outstanding[k][0]):
+                k += 1
+            if k < len(outstanding):
+                q.wait(outstanding[k][0])
+            t = q.try_submit(A, B, X)
+        tickets[i] = t
+        outstanding.append((t, lo, hi))
+    for t in tickets:
         q.wait(t)
     gc.enable()
-    end = max(q.completion_ns(t) for t, _, _ in tickets)
-    lat = np.array([(q.completion_ns(t) - ta) / 1e3 for t, ta, _ in tickets])
+    done = np.array([q.completion_ns(t) for t in tickets], dtype=np.int64)
+    end = int(done.max())
+    lat = (done - np.array(t_arr, dtype=np.int64)) / 1e3
+    res = {"rate_offered": rate, "requests": cnt, "duration_s": round((end - base) / 1e9, 3),
+           "mults_per_s": round(cnt / ((end - base) / 1e9), 1),
+           "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+           "mean_r": int(rs.mean()), "footprint_retries": retries, "ring_waits": ring_waits}
+    if verify:
+        # the last `verify` requests' windows are intact (no later request reused them)
+        Y = torch.empty(1 << 22, dtype=torch.uint64, device=ring.device)
+        Z = torch.empty(1 << 22, dtype=torch.uint64, device=ring.device)
+        same, checked, words = True, 0, 0
+        lo_all = None
+        for i in range(cnt - 1, -1, -1):
+            lo, hi = int(outs[i]), int(outs[i] + rs[i])
+            if lo_all is not None and not (hi <= lo_all[0] or lo >= lo_all[1]):
+                break        # overwritten by a later request
+            r = int(rs[i])
+            libtft.poly_mul(ctx, pool[int(offa[i]):int(offa[i] + la[i])], pool[int(offb[i]):int(offb[i] + lb[i])],
+                            Z[:r], Y[:r])
+            same &= bool(torch.equal(ring[lo:hi], Z[:r]))
+            checked += 1
+            words += r
+            lo_all = (lo, hi) if lo_all is None else (min(lo_all[0], lo), max(lo_all[1], hi))
+            if checked >= verify:
+                break
+        torch.cuda.synchronize()
+        res["outputs_checked"] = checked
+        res["words_checked"] = words
+        res["served_equals_plain"] = same
+    return res
+
+
+def served_c4(ctx, seconds, plain_seconds, capacity=True):
+    """Config 4: a Poisson stream (mean 20k requests/s) of products mod
+    2^64-2^32+1, r log-uniform in [2^8, 2^22], operands resident in HBM, the
+    queue admitting by in-place footprint; then the same stream served one
+    request at a time (plain FIFO: poly_mul + wait); then the served capacity:
+    the highest offered rate of a short stream that the queue holds at
+    p99 < 2 ms."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1001_5272_amd import libtft
+    p = synth.GOLDILOCKS[0]
+    print(f"[bench] served stream {seconds} s", file=sys.stderr, flush=True)
+    pool = torch.from_numpy(synth.residues(p, 1 << 26, 4100)).cuda()   # 512 MiB of operand words
+    ring = torch.empty(1 << 27, dtype=torch.uint64, device="cuda")     # 1 GiB of output windows
+    q = libtft.Queue(ctx, 1 << 27, 4096)
+    served = served_stream(ctx, q, 20000.0, seconds, 4001, pool, ring, verify=256)
     st = q.stats()
+    served.update({"batches": st["batches"], "rejected": st["rejected"], "pool_words": st["pool_words"],
+                   "pool_used_max": st["pool_used_max"]})
+    cap = None
+    if capacity:
+        print("[bench] served capacity", file=sys.stderr, flush=True)
+        cap = {"criterion": "p99 < 2000 us over a 2 s stream", "runs": []}
+        best = None
+        for rate in (20000.0, 25000.0, 30000.0, 35000.0, 40000.0, 50000.0):
+            r = served_stream(ctx, q, rate, 2.0, 4500 + int(rate) // 1000, pool, ring)
+            cap["runs"].append({k: r[k] for k in ("rate_offered", "mults_per_s", "p50_us", "p99_us")})
+            if r["p99_us"] < 2000.0:
+                best = rate
+            else:
+                break
+        cap["capacity_req_per_s"] = best
     q.close()
-    served = {"requests": len(tickets), "duration_s": round((end - base) / 1e9, 3),
-              "mults_per_s": round(len(tickets) / ((end - base) / 1e9), 1),
-              "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
-              "mean_r": int(np.mean([r for _, _, r in tickets])), "batches": st["batches"],
-              "deferred": st["deferred"], "pool_words": st["pool_words"], "pool_used_max": st["pool_used_max"],
-              "submitter_waits": blocked}
-    # every output slot the stream wrote holds its pair's product: compare
-    # with the plain path's poly_mul of the same pair (outside the timings)
-    Y = torch.empty(1 << 22, dtype=torch.uint64, device="cuda")
-    Z = torch.empty(1 << 22, dtype=torch.uint64, device="cuda")
-    used = {key for key in last}
-    same = True
-    for k, (A, B, Xs) in enumerate(pairs):
-        r = Xs[0].numel()
-        libtft.poly_mul(ctx, A, B, Z[:r], Y[:r])
-        for slot in range(SLOTS):
-            if (k, slot) in used:
-                same &= bool(torch.equal(Xs[slot], Z[:r]))
-    torch.cuda.synchronize()
-    served["outputs_checked"] = len(used)
-    served["served_equals_plain"] = same
-    # plain FIFO path on a prefix of the same stream
+    # plain FIFO path on a prefix of the same stream (same operands)
     print(f"[bench] plain FIFO stream {plain_seconds} s", file=sys.stderr, flush=True)
+    arrivals = synth.poisson_arrivals(20000.0, seconds, 4001)
     sub = arrivals[arrivals < plain_seconds]
+    cnt = len(sub)
+    rs = synth.log_uniform_lengths(1 << 8, 1 << 22, len(arrivals), 4002)[:cnt]
+    la = (rs + 2) // 2
+    lb = rs + 1 - la
+    P = pool.numel()
+    offa = (synth.uniform01(len(arrivals), 4003)[:cnt] * (P - la)).astype(np.int64)
+    offb = (synth.uniform01(len(arrivals), 4004)[:cnt] * (P - lb)).astype(np.int64)
+    Y = torch.empty(1 << 22, dtype=torch.uint64, device="cuda")
     torch.cuda.synchronize()
     gc.collect()
     gc.disable()
     base = time.monotonic_ns() + 20_000_000
     lat_p = []
     for i, ta in enumerate(sub.tolist()):
-        k = i % K
-        A, B, Xs = pairs[k]
+        r = int(rs[i])
         t_arr = base + int(ta * 1e9)
         while time.monotonic_ns() < t_arr:
             pass
-        libtft.poly_mul(ctx, A, B, Xs[0], Y[:Xs[0].numel()])
+        libtft.poly_mul(ctx, pool[int(offa[i]):int(offa[i] + la[i])], pool[int(offb[i]):int(offb[i] + lb[i])],
+                        ring[:r], Y[:r])
         torch.cuda.synchronize()
         lat_p.append((time.monotonic_ns() - t_arr) / 1e3)
     end_p = time.monotonic_ns()
     gc.enable()
     lat_p = np.array(lat_p)
-    plain = {"requests": len(sub), "duration_s": round((end_p - base) / 1e9, 3),
-             "mults_per_s": round(len(sub) / ((end_p - base) / 1e9), 1),
+    plain = {"requests": cnt, "duration_s": round((end_p - base) / 1e9, 3),
+             "mults_per_s": round(cnt / ((end_p - base) / 1e9), 1),
              "p50_us": round(float(np.percentile(lat_p, 50)), 1), "p99_us": round(float(np.percentile(lat_p, 99)), 1)}
-    return {"workload": f"Poisson 20k req/s for {seconds} s, p=2^64-2^32+1, r log-uniform [2^8, 2^22] "
-                        f"({K} operand pairs reused round-robin)", "served": served, "plain_fifo": plain}
+    del pool, ring
+    torch.cuda.empty_cache()
+    out = {"workload": f"Poisson 20k req/s for {seconds} s, p=2^64-2^32+1, r log-uniform [2^8, 2^22], "
+                       "operands: windows of a resident 2^26-word random array at seeded offsets (every request "
+                       "its own pair)", "served": served, "plain_fifo": plain}
+    if cap is not None:
+        out["capacity"] = cap
+    return out
 
 
 def crt_c5():
@@ -705,10 +803,27 @@ def crt_c5():
 
 
 def cpu_baseline(p, g, host):
-    """The oracle as it stands: its textbook padded radix-2 FFT and the
-    inverse, on one core, at the two power-of-two lengths of the sweep
-    (2^22 and 2^23), where the padded and truncated transforms coincide."""
+    """CPU timings on this host, beside the GPU numbers (reported baselines,
+    not targets):
+
+    - value: the oracle as it stands -- its textbook padded radix-2 FFT and the
+      inverse, one thread, at 2^22 and 2^23 (where padded and truncated
+      transforms coincide);
+    - plain_cpu_tft: the paper's Algorithms 1 and 2 with O(1) auxiliary space
+      (oracle.tft_inplace / itft_inplace), one thread, forward + inverse at
+      2^22 and 2^22 + 1;
+    - c1_product: the 1000 x 1500 product mod 998244353 on one thread, by
+      Algorithm 3 (the space-restricted product on Algorithms 1 and 2) and by
+      the schoolbook definition;
+    - c3_all_cores: the 4096 products of the batched workload by Algorithm 3,
+      spread over every core this process may use (threads; the oracle
+      releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
     import oracle
+    import synth
     t_all, bfly, parts = 0.0, 0.0, []
     for n in (SWEEP[0], SWEEP[4]):
         F = host[n]
@@ -721,9 +836,66 @@ def cpu_baseline(p, g, host):
         t_all += t1 - t0
         bfly += 2 * nominal_butterflies(n)
         parts.append(f"n={n}: {t1 - t0:.2f} s")
-    return {"value": round(bfly / t_all / 1e9, 5), "unit": "Gbutterfly/s", "cores": 1, "kind": "oracle",
-            "sample": "forward + inverse (textbook padded radix-2, one thread) at n=2^22 and n=2^23, "
-                      "p=2^64-2^32+1; " + ", ".join(parts)}
+    out = {"value": round(bfly / t_all / 1e9, 5), "unit": "Gbutterfly/s", "cores": 1, "kind": "oracle",
+           "sample": "forward + inverse (textbook padded radix-2, one thread) at n=2^22 and n=2^23, "
+                     "p=2^64-2^32+1; " + ", ".join(parts)}
+    # the paper's in-place algorithms, one thread
+    plain = {}
+    for n in (SWEEP[0], SWEEP[1]):
+        print(f"[bench] cpu baseline (Algorithms 1 and 2 in place, n={n})", file=sys.stderr, flush=True)
+        F = host[n]
+        t0 = time.perf_counter()
+        X = oracle.tft_inplace(p, g, F)
+        t1 = time.perf_counter()
+        back = oracle.itft_inplace(p, g, X)
+        t2 = time.perf_counter()
+        assert (back == F).all()
+        plain[str(n)] = {"fwd_s": round(t1 - t0, 3), "inv_s": round(t2 - t1, 3),
+                         "gbfly_s": round(2 * nominal_butterflies(n) / (t2 - t0) / 1e9, 5)}
+    out["plain_cpu_tft"] = {"kind": "Algorithms 1 and 2, O(1) auxiliary space", "cores": 1, "unit": "Gbutterfly/s",
+                            "p": "2^64-2^32+1", "per_length": plain}
+    # config 1 on one thread
+    p1, g1 = synth.P998
+    A = synth.residues(p1, 1000, 1001)
+    B = synth.residues(p1, 1500, 1002)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        C = oracle.mul_restricted(p1, g1, A, B)
+    t1 = time.perf_counter()
+    C2 = oracle.mul_schoolbook(p1, A, B)
+    t2 = time.perf_counter()
+    assert (C == C2).all()
+    out["c1_product"] = {"cores": 1, "algorithm3_us": round((t1 - t0) / 20 * 1e6, 1),
+                         "schoolbook_us": round((t2 - t1) * 1e6, 1), "workload": "998244353, 1000 x 1500 -> r=2499"}
+    # config 3 over every usable core
+    count = 4096
+    la = synth.log_uniform_lengths(32, 32768, count, 3001)
+    lb = synth.log_uniform_lengths(32, 32768, count, 3002)
+    pairs = [(synth.residues(p1, int(la[i]), 10_000 + 2 * i), synth.residues(p1, int(lb[i]), 10_001 + 2 * i))
+             for i in range(count)]
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    print(f"[bench] cpu baseline (4096 products, Algorithm 3, {cores} threads)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        res = list(ex.map(lambda ab: oracle.mul_restricted(p1, g1, ab[0], ab[1]), pairs))
+    t1 = time.perf_counter()
+    assert len(res) == count
+    out["c3_all_cores"] = {"kind": "Algorithm 3 (space-restricted product on Algorithms 1 and 2)", "cores": cores,
+                           "products": count, "seconds": round(t1 - t0, 3),
+                           "mults_per_s": round(count / (t1 - t0), 1),
+                           "cpu_model": _cpu_model()}
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

@@ -47,7 +47,7 @@ typedef enum {
     TFT_ERANGE = -2,   /* length above 2^v (v = 2-adic order of p-1) or above the library's limit; unsupported p */
     TFT_ENOMEM = -3,   /* context or queue allocation failed */
     TFT_EDEVICE = -4,  /* a HIP call failed */
-    TFT_EAGAIN = -5    /* queue: the request does not fit the free pool now */
+    TFT_EAGAIN = -5    /* queue: the request does not fit the free pool now (or the pending list is full) */
 } tft_status;
 
 typedef struct tft_ctx tft_ctx;
@@ -170,13 +170,14 @@ void tft_batch_destroy(tft_batch* batch);
 tft_status poly_mul_batch(tft_ctx* ctx, const tft_mul_desc* d, size_t count, void* hip_stream);
 tft_status tft_forward_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t count, void* hip_stream);
 
-/* The paper's Algorithm 1 (inverse = 0) or Algorithm 2 (inverse = 1) run as
- * written (section 3: the in-place TFT as a post-order walk of the even/odd
- * tree with a constant number of scalars, including the odd-length
- * correction; section 4: the ITFT walking the same path backwards), one
- * wavefront per instance: every lane follows the same node and the 64 lanes
- * share each node's butterflies and the correction's sum.  An alternative to
- * the layer-parallel small-instance kernels for batches of short instances.
+/* The paper's Algorithm 1 (inverse = 0) or Algorithm 2 (inverse = 1) as a
+ * sequential walk (section 3: the in-place TFT visits the even/odd tree in
+ * post order with a constant number of scalars, applying the odd-length
+ * correction before each odd child of an odd-length node; section 4: the ITFT
+ * undoes the same steps in reverse order), one wavefront per instance: every
+ * lane follows the same node and the 64 lanes share each node's butterflies
+ * and the correction's sum.  An alternative to the layer-parallel
+ * small-instance kernels for batches of short instances.
  * X[k] (device, n[k] words, in place), 1 <= n[k] <= 1024 and n[k] <= 2^v, else
  * TFT_EINVAL / TFT_ERANGE before any work.  The call uploads the two arrays,
  * enqueues one kernel on hip_stream and waits for it (synchronous).  Results
@@ -184,29 +185,41 @@ tft_status tft_forward_batch(tft_ctx* ctx, void* const* X, const size_t* n, size
 tft_status tft_walk_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t count, int inverse, void* hip_stream);
 
 /* ---------------------------------------------------------------- serving
- * A request queue with continuous batching.  tft_queue_create allocates a
- * device pool of pool_words words and starts a worker thread.
- * tft_queue_submit appends a product (a tft_mul_desc; its work field is
- * ignored: workspace comes from the pool) and returns a ticket at once; the
- * operands must stay valid and untouched until the ticket completes.
- * Requests are admitted in arrival order while their workspace (r = la + lb - 1
- * words, the in-place footprint -- not 2^ceil(lg r)) fits in the pool and
- * fewer than max_inflight requests are on the device; each group admitted
- * together runs as one batch, and consecutive batches run on two streams so
- * that they overlap on the device; each stream keeps the device and pinned
- * host memory of its batches' work lists, grown as needed, so a batch in
- * steady state allocates and frees nothing.  Submit returns TFT_ERANGE for a request
- * that could never fit and TFT_EAGAIN when the pending list is full
- * (2^20 requests).  poll reports completion without blocking; wait blocks;
+ * A request queue with continuous batching (products as in poly_mul, section
+ * 5, arriving one at a time).  tft_queue_create allocates a device pool of
+ * pool_words words and starts a worker thread.
+ *
+ * tft_queue_submit offers a product (a tft_mul_desc; its work field is
+ * ignored: workspace comes from the pool).  Admission is by in-place
+ * footprint: a product that needs workspace (one too long for the
+ * single-workgroup path) reserves r = la + lb - 1 words of the pool -- not
+ * 2^ceil(lg r) -- at submit, and submit returns TFT_EAGAIN at once, leaving
+ * nothing queued, when those words do not fit in the pool's free space now
+ * (retry after earlier tickets complete), TFT_ERANGE when they could never
+ * fit (r > pool_words) or r > 2^v, and TFT_EAGAIN also when 2^20 requests are
+ * pending.  On success it returns a ticket without waiting.  hip_stream is
+ * the stream that produces the operands (NULL: the default stream): submit
+ * records an event on it, and the batch that runs the request waits for that
+ * event on the device, so operands still being written by earlier work on
+ * that stream are read only once it has finished.  A, B and out must stay
+ * valid and untouched by other work until the ticket completes.
+ *
+ * The worker takes pending requests in arrival order while fewer than
+ * max_inflight are on the device; each group taken together runs as one
+ * batch, and consecutive batches run on two streams so that they overlap on
+ * the device; each stream keeps the device and pinned host memory of its
+ * batches' work lists, grown as needed, so a batch in steady state allocates
+ * and frees nothing.  poll reports completion without blocking; wait blocks;
  * completion_ns gives the steady-clock time (ns) at which the worker saw the
  * request complete (0 while pending).  A request whose batch failed reports
- * TFT_EDEVICE.  destroy waits for all submitted requests. */
+ * TFT_EDEVICE.  stats: `rejected` counts submits refused for footprint.
+ * destroy waits for all submitted requests. */
 typedef struct tft_queue tft_queue;
 typedef struct {
-    uint64_t submitted, completed, batches, deferred, pending, inflight, pool_words, pool_used_max;
+    uint64_t submitted, completed, batches, rejected, pending, inflight, pool_words, pool_used_max;
 } tft_queue_desc;
 tft_status tft_queue_create(tft_ctx* ctx, size_t pool_words, size_t max_inflight, tft_queue** out);
-tft_status tft_queue_submit(tft_queue* q, const tft_mul_desc* d, uint64_t* ticket);
+tft_status tft_queue_submit(tft_queue* q, const tft_mul_desc* d, void* hip_stream, uint64_t* ticket);
 tft_status tft_queue_poll(tft_queue* q, uint64_t ticket, int* done);
 tft_status tft_queue_wait(tft_queue* q, uint64_t ticket);
 tft_status tft_queue_completion_ns(tft_queue* q, uint64_t ticket, uint64_t* ns);

@@ -127,8 +127,9 @@ struct tft_ctx {
     uint64_t p, g;
     unsigned v;          // usable log2 length
     unsigned wbytes;     // 4 or 8
-    unsigned override_logW;
-    unsigned tuned_logW[kPlanBuckets];   // plan cache by floor(4 lg n): 0 = planner's choice
+    // plan state, read by every caller's thread and the serving queue's worker
+    std::atomic<unsigned> override_logW;
+    std::atomic<unsigned> tuned_logW[kPlanBuckets];   // plan cache by floor(4 lg n): 0 = planner's choice
     tft::ModU32 m32;
     tft::ModGL m64;
     void* tables;        // f1 | f2 | i1 | i2
@@ -136,8 +137,9 @@ struct tft_ctx {
     void* varea;         // V_c area and column polynomial (kScratchWords words)
     // measurement mode (tft_timing_*): events bracketing each launch of the
     // kernels selected in timing_mask (bit = tft_kernel_id)
-    bool timing;
-    uint32_t timing_mask;
+    std::atomic<bool> timing;
+    std::atomic<uint32_t> timing_mask;
+    std::mutex timing_mu;   // recs, pool, launches, total_ms (launches from several threads)
     struct Rec { int kid; hipEvent_t e0, e1; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
@@ -180,16 +182,20 @@ hipEvent_t take_event(tft_ctx* ctx) {
 template <typename Kernel, typename... Args>
 void launch(tft_ctx* ctx, int kid, Kernel kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st,
             Args... args) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->timing && ((ctx->timing_mask >> kid) & 1u)) {
-        e0 = take_event(ctx);
-        e1 = take_event(ctx);
-        if (e0 && e1) (void)hipEventRecord(e0, st);
+    if (!(ctx->timing.load(std::memory_order_relaxed) && ((ctx->timing_mask.load(std::memory_order_relaxed) >> kid) & 1u))) {
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+        return;
     }
+    std::lock_guard<std::mutex> lk(ctx->timing_mu);
+    hipEvent_t e0 = take_event(ctx), e1 = take_event(ctx);
+    if (e0 && e1) (void)hipEventRecord(e0, st);
     hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
     if (e0 && e1) {
         (void)hipEventRecord(e1, st);
         ctx->recs.push_back({kid, e0, e1});
+    } else {
+        if (e0) ctx->pool.push_back(e0);
+        if (e1) ctx->pool.push_back(e1);
     }
 }
 
@@ -233,11 +239,19 @@ auto col_inv_list_kernel(int logC) {
 // longer rows and shorter columns their many small column tiles each finish
 // sooner (a batch of 4096 products with lengths up to 2^16 measured 20 %
 // faster).
+// The autotuner times candidate widths on its own thread: a width forced here
+// applies to that thread's calls only, so other threads (the serving queue's
+// worker, other callers) keep planning from the context's state meanwhile.
+thread_local unsigned tl_force_logW = 0;      // 0: none
+thread_local bool tl_ignore_cache = false;   // plan without the tuned widths
+
 Plan make_plan(const tft_ctx* ctx, uint64_t n, bool wide = false) {
     Plan P{};
     P.n = n;
     const unsigned w = ctx->wbytes;
-    if (log2u(n) <= small_max_log2(w) && !(ctx->override_logW && (1ull << ctx->override_logW) < n)) {
+    const unsigned ovr = tl_force_logW ? tl_force_logW
+                                       : (tl_ignore_cache ? 0u : ctx->override_logW.load(std::memory_order_relaxed));
+    if (log2u(n) <= small_max_log2(w) && !(ovr && (1ull << ovr) < n)) {
         P.kind = 0;
         P.M = (uint32_t)pow2ceil(n);
         P.lds_row = (size_t)tft::padded_words(P.M) * w;   // data tile; the kernels add M words of twiddles
@@ -258,15 +272,16 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n, bool wide = false) {
         P.lds_row = (size_t)tft::padded_words((uint32_t)P.W) * w;
     };
     const unsigned logC = (unsigned)P.logC;
-    if (ctx->override_logW) {
-        fill(ctx->override_logW);
+    if (ovr) {
+        fill(ovr);
         if (P.W < (1ull << logC) || P.a < 1 || P.lds_col > kLdsDynMax || P.lds_row > kLdsDynMax) P.kind = -1;
         return P;
     }
     const unsigned k = log2u(n);
     const unsigned bk = plan_bucket(n);
-    if (bk < kPlanBuckets && ctx->tuned_logW[bk] && (1ull << ctx->tuned_logW[bk]) < n) {   // tft_autotune
-        fill(ctx->tuned_logW[bk]);
+    const unsigned tuned = (bk < kPlanBuckets && !tl_ignore_cache) ? ctx->tuned_logW[bk].load(std::memory_order_relaxed) : 0u;
+    if (tuned && (1ull << tuned) < n) {   // tft_autotune
+        fill(tuned);
         if (P.W >= (1ull << logC) && P.a >= 1 && P.lds_col <= kLdsDynMax && P.lds_row <= kLdsDynMax) return P;
     }
     // balanced split: W close to sqrt(n), within the LDS budget (preferred
@@ -790,6 +805,25 @@ void arena_free(BatchArena* A) {
     *A = BatchArena();
 }
 
+// LDS of a single-workgroup batch job of length r (data blocks + twiddles).
+size_t small_job_lds(unsigned w, uint64_t r, int products) {
+    const size_t Mr = pow2ceil(r);
+    return ((products ? 2 : 1) * (size_t)tft::padded_words((uint32_t)Mr) + Mr) * w;
+}
+
+// A batch runs instance r in one workgroup (no workspace) when the planner
+// keeps it in LDS and both operands' blocks fit beside its twiddles.
+bool batch_small(const tft_ctx* ctx, const Plan& P, uint64_t r, int products) {
+    return P.kind == 0 && small_job_lds(ctx->wbytes, r, products) <= kLdsHard - 32 * 1024;
+}
+
+// Whether a batched product of length r needs the r-word workspace (the same
+// decision batch_build takes, so the serving queue reserves exactly that).
+bool needs_workspace(const tft_ctx* ctx, uint64_t r, int products) {
+    const Plan P = make_plan(ctx, r, true);
+    return products && !batch_small(ctx, P, r, products);
+}
+
 template <class Mod>
 tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, tft_batch* B,
                        hipStream_t upload) {
@@ -803,7 +837,6 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
     B->lds_col = B->lds_row = B->lds_small = 0;
     B->row_thr = B->col_thr = 64;
     B->logC = col_log_width(w);
-    const size_t small_lds_cap = kLdsHard - 32 * 1024;
     for (size_t k = 0; k < count; k++) {
         const tft_mul_desc& D = d[k];
         if (!D.a || !D.out || D.la == 0 || (products && (!D.b || D.lb == 0))) return TFT_EINVAL;
@@ -811,9 +844,8 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
         if (log2u(r) > ctx->v) return TFT_ERANGE;
         const Plan P = make_plan(ctx, r, true);
         if (P.kind < 0) return TFT_ERANGE;
-        const size_t Mr = pow2ceil(r);
-        const size_t small_lds = ((products ? 2 : 1) * (size_t)tft::padded_words((uint32_t)Mr) + Mr) * w;   // data + twiddles
-        if (P.kind == 0 && small_lds <= small_lds_cap) {
+        if (batch_small(ctx, P, r, products)) {
+            const size_t small_lds = small_job_lds(w, r, products);
             tft::SmallJob<Word> J;
             J.A = (const Word*)D.a;
             J.B = products ? (const Word*)D.b : nullptr;
@@ -1063,7 +1095,8 @@ struct QReq {
     uint64_t ticket;
     tft_mul_desc d;
     uint64_t r;
-    uint64_t off;      // workspace offset in the pool (words), ~0 if none needed
+    uint64_t off;        // workspace offset in the pool (words), ~0 if none needed
+    hipStream_t src;     // the stream the operands were produced on
 };
 
 struct QBatch {
@@ -1139,8 +1172,11 @@ struct tft_queue {
     hipStream_t streams[2];
     BatchArena arenas[2];
     bool slot_busy[2];
-    uint64_t n_submitted, n_completed, n_batches, n_deferred, max_pool_used;
+    uint64_t n_submitted, n_completed, n_batches, n_rejected, max_pool_used;
     tft_status error;
+    // one event per producer stream, recorded by every submit on that stream;
+    // a batch waits for the latest record of each stream its requests name
+    std::unordered_map<hipStream_t, hipEvent_t> src_events;
 };
 
 namespace {
@@ -1179,33 +1215,27 @@ void queue_worker(tft_queue* q) {
         if (!q->pending.empty() && slot >= 0) {
             std::vector<QReq> group;
             while (!q->pending.empty() && group.size() < q->max_batch && q->inflight_reqs + group.size() < q->max_inflight) {
-                QReq rq = q->pending.front();
-                const bool need_ws = rq.r > ((w == 4) ? 8192u : 4096u);
-                if (need_ws) {
-                    uint64_t off;
-                    if (!q->alloc.alloc(rq.r, &off)) {
-                        q->n_deferred++;
-                        break;   // keep FIFO order: wait for space
-                    }
-                    rq.off = off;
-                    rq.d.work = (char*)q->pool + off * w;
-                } else {
-                    rq.off = ~0ull;
-                    rq.d.work = nullptr;
-                }
+                group.push_back(q->pending.front());   // workspace was reserved at submit
                 q->pending.pop_front();
-                group.push_back(rq);
             }
-            q->max_pool_used = std::max<uint64_t>(q->max_pool_used, q->alloc.used);
             if (!group.empty()) {
                 q->inflight_reqs += group.size();
+                const hipStream_t st = q->streams[slot];
+                // the batch starts after the work that produced its operands:
+                // the latest record of each producer stream's event (records
+                // and waits both happen under the queue's lock)
+                tft_status s = TFT_OK;
+                std::vector<hipStream_t> srcs;
+                for (const QReq& rq : group)
+                    if (std::find(srcs.begin(), srcs.end(), rq.src) == srcs.end()) srcs.push_back(rq.src);
+                for (hipStream_t src : srcs)
+                    if (hipStreamWaitEvent(st, q->src_events[src], 0) != hipSuccess) s = TFT_EDEVICE;
                 lk.unlock();
                 std::vector<tft_mul_desc> ds(group.size());
                 for (size_t i = 0; i < group.size(); i++) ds[i] = group[i].d;
                 tft_batch* B = nullptr;
-                const hipStream_t st = q->streams[slot];
                 BatchArena* A = &q->arenas[slot];
-                tft_status s = batch_create(q->ctx, ds.data(), ds.size(), 1, &B, A, st);
+                if (s == TFT_OK) s = batch_create(q->ctx, ds.data(), ds.size(), 1, &B, A, st);
                 if (s == TFT_OK) s = tft_batch_run(B, st);
                 if (s == TFT_OK && hipEventRecord(A->done, st) != hipSuccess) s = TFT_EDEVICE;
                 lk.lock();
@@ -1304,10 +1334,10 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
     c->g = g;
     c->v = v < kMaxLog2 ? v : kMaxLog2;
     c->wbytes = wide ? 8 : 4;
-    c->override_logW = 0;
-    for (unsigned i = 0; i < kPlanBuckets; i++) c->tuned_logW[i] = 0;
-    c->timing = false;
-    c->timing_mask = ~0u;
+    c->override_logW.store(0);
+    for (unsigned i = 0; i < kPlanBuckets; i++) c->tuned_logW[i].store(0);
+    c->timing.store(false);
+    c->timing_mask.store(~0u);
     c->last_batch = nullptr;
     c->last_done = nullptr;
     for (int i = 0; i < TFT_K_COUNT; i++) { c->launches[i] = 0; c->total_ms[i] = 0.0; }
@@ -1612,7 +1642,7 @@ tft_status tft_queue_create(tft_ctx* ctx, size_t pool_words, size_t max_inflight
     q->next_ticket = 1;
     q->stop = false;
     q->slot_busy[0] = q->slot_busy[1] = false;
-    q->n_submitted = q->n_completed = q->n_batches = q->n_deferred = q->max_pool_used = 0;
+    q->n_submitted = q->n_completed = q->n_batches = q->n_rejected = q->max_pool_used = 0;
     q->error = TFT_OK;
     q->alloc.init(pool_words);
     hipError_t e = hipMalloc(&q->pool, pool_words * ctx->wbytes);
@@ -1634,18 +1664,43 @@ tft_status tft_queue_create(tft_ctx* ctx, size_t pool_words, size_t max_inflight
     return TFT_OK;
 }
 
-tft_status tft_queue_submit(tft_queue* q, const tft_mul_desc* d, uint64_t* ticket) {
+tft_status tft_queue_submit(tft_queue* q, const tft_mul_desc* d, void* hip_stream, uint64_t* ticket) {
     if (!q || !d || !ticket || !d->a || !d->b || !d->out || d->la == 0 || d->lb == 0) return TFT_EINVAL;
     const uint64_t r = d->la + d->lb - 1;
     if (log2u(r) > q->ctx->v) return TFT_ERANGE;
-    if (r > q->pool_words) return TFT_ERANGE;   // could never be admitted
+    const bool need_ws = needs_workspace(q->ctx, r, true);
+    if (need_ws && r > q->pool_words) return TFT_ERANGE;   // could never be admitted
+    const hipStream_t src = (hipStream_t)hip_stream;
+    DeviceGuard guard(q->ctx->device);
     std::lock_guard<std::mutex> lk(q->mu);
     if (q->pending.size() >= q->max_pending) return TFT_EAGAIN;
     QReq rq;
-    rq.ticket = q->next_ticket++;
     rq.d = *d;
     rq.r = r;
     rq.off = ~0ull;
+    rq.src = src;
+    rq.d.work = nullptr;
+    // admission by in-place footprint: the r words of B's transform, reserved
+    // now or refused
+    if (need_ws) {
+        uint64_t off;
+        if (!q->alloc.alloc(r, &off)) {
+            q->n_rejected++;
+            return TFT_EAGAIN;
+        }
+        rq.off = off;
+        rq.d.work = (char*)q->pool + off * q->ctx->wbytes;
+        q->max_pool_used = std::max<uint64_t>(q->max_pool_used, q->alloc.used);
+    }
+    hipEvent_t& ev = q->src_events[src];
+    hipError_t e = hipSuccess;
+    if (!ev) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, src);
+    if (e != hipSuccess) {
+        if (rq.off != ~0ull) q->alloc.release(rq.off, r);
+        return TFT_EDEVICE;
+    }
+    rq.ticket = q->next_ticket++;
     q->pending.push_back(rq);
     q->n_submitted++;
     *ticket = rq.ticket;
@@ -1684,7 +1739,7 @@ tft_status tft_queue_stats(tft_queue* q, tft_queue_desc* out) {
     out->submitted = q->n_submitted;
     out->completed = q->n_completed;
     out->batches = q->n_batches;
-    out->deferred = q->n_deferred;
+    out->rejected = q->n_rejected;
     out->pending = q->pending.size();
     out->inflight = q->inflight_reqs;
     out->pool_words = q->pool_words;
@@ -1705,6 +1760,8 @@ void tft_queue_destroy(tft_queue* q) {
     (void)hipStreamDestroy(q->streams[1]);
     arena_free(&q->arenas[0]);
     arena_free(&q->arenas[1]);
+    for (auto& kv : q->src_events)
+        if (kv.second) (void)hipEventDestroy(kv.second);
     (void)hipFree(q->pool);
     delete q;
 }
@@ -1721,7 +1778,7 @@ tft_status tft_timing_select(tft_ctx* ctx, uint32_t kernel_mask) {
     return TFT_OK;
 }
 
-static tft_status timing_collect(tft_ctx* ctx) {
+static tft_status timing_collect(tft_ctx* ctx) {   // with timing_mu held
     tft_status s = TFT_OK;
     for (auto& r : ctx->recs) {
         float ms = 0.f;
@@ -1739,6 +1796,7 @@ static tft_status timing_collect(tft_ctx* ctx) {
 tft_status tft_timing_read(tft_ctx* ctx, int id, uint64_t* launches, double* total_ms) {
     if (!ctx || id < 0 || id >= TFT_K_COUNT || !launches || !total_ms) return TFT_EINVAL;
     DeviceGuard guard(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->timing_mu);
     tft_status s = timing_collect(ctx);
     *launches = ctx->launches[id];
     *total_ms = ctx->total_ms[id];
@@ -1748,6 +1806,7 @@ tft_status tft_timing_read(tft_ctx* ctx, int id, uint64_t* launches, double* tot
 tft_status tft_timing_reset(tft_ctx* ctx) {
     if (!ctx) return TFT_EINVAL;
     DeviceGuard guard(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->timing_mu);
     tft_status s = timing_collect(ctx);
     for (int i = 0; i < TFT_K_COUNT; i++) { ctx->launches[i] = 0; ctx->total_ms[i] = 0.0; }
     return s;
@@ -1771,9 +1830,8 @@ tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen) {
     if (n > (1ull << ctx->v)) return TFT_ERANGE;
     DeviceGuard dg(ctx->device);
     const unsigned k = plan_bucket(n);
-    const unsigned saved_override = ctx->override_logW, saved_tuned = ctx->tuned_logW[k];
-    ctx->override_logW = 0;
-    ctx->tuned_logW[k] = 0;
+    const unsigned saved_tuned = ctx->tuned_logW[k].load();
+    tl_ignore_cache = true;   // the planner's own choice, whatever the context holds
     const Plan base = make_plan(ctx, n);
     tft_status st = TFT_OK;
     unsigned best = 0;
@@ -1797,7 +1855,7 @@ tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen) {
         const int lo = std::max<int>((int)base.logW - 2, (int)base.logC), hi = std::min<int>((int)base.logW + 2, 16);
         for (int lw = lo; lw <= hi && st == TFT_OK; lw++) {
             if ((1ull << lw) >= n) break;
-            ctx->override_logW = (unsigned)lw;
+            tl_force_logW = (unsigned)lw;
             if (make_plan(ctx, n).kind != 1) continue;
             auto round_trip = [&]() {
                 tft_status a = tft_forward(ctx, X, n, nullptr);
@@ -1830,8 +1888,9 @@ tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen) {
         if (e1) (void)hipEventDestroy(e1);
         if (X) (void)hipFree(X);
     }
-    ctx->override_logW = saved_override;
-    ctx->tuned_logW[k] = st == TFT_OK ? best : saved_tuned;
+    tl_force_logW = 0;
+    tl_ignore_cache = false;
+    ctx->tuned_logW[k].store(st == TFT_OK ? best : saved_tuned);
     if (st == TFT_OK && chosen) st = tft_plan_info(ctx, n, chosen);
     return st;
 }

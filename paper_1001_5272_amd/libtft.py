@@ -62,7 +62,7 @@ SIGNATURES = {
     "tft_from_signed": (_st, [_vp, _vp, _sz, _vp, _vp]),
     "tft_crt3": (_st, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "tft_queue_create": (_st, [_vp, _sz, _sz, ctypes.POINTER(_vp)]),
-    "tft_queue_submit": (_st, [_vp, _vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "tft_queue_submit": (_st, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)]),
     "tft_queue_poll": (_st, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
     "tft_queue_wait": (_st, [_vp, ctypes.c_uint64]),
     "tft_queue_completion_ns": (_st, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
@@ -102,7 +102,7 @@ class BatchDesc(ctypes.Structure):
 
 
 class QueueDesc(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "batches", "deferred", "pending",
+    _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "batches", "rejected", "pending",
                                                  "inflight", "pool_words", "pool_used_max")]
 
 
@@ -434,28 +434,53 @@ def tft_crt3(ctxs, r1, r2, r3, out, stream=None):
 
 
 class Queue:
-    """Serving queue with continuous batching (tft_queue_*)."""
+    """Serving queue with continuous batching (tft_queue_*).
+
+    The queue holds a reference to each request's tensors until poll() or
+    wait() reports the ticket complete (or the queue is closed), so that
+    torch's allocator cannot hand their memory to other tensors while the
+    device may still read or write them."""
 
     def __init__(self, ctx: Context, pool_words: int, max_inflight: int = 4096):
         self.ctx = ctx
         h = _vp()
         _check(load().tft_queue_create(ctx.handle, pool_words, max_inflight, ctypes.byref(h)), "tft_queue_create")
         self.handle = h
+        self._live = {}
 
-    def submit(self, A, B, X) -> int:
+    def try_submit(self, A, B, X, stream=None):
+        """Submit C = A B into X; the operands are produced on `stream` (default:
+        the current stream).  Returns the ticket, or None when the request's
+        footprint does not fit the pool's free space now (TFT_EAGAIN)."""
         d = MulDesc(self.ctx._t(A, "A").value, A.numel(), self.ctx._t(B, "B").value, B.numel(),
                     self.ctx._t(X, "X").value, None)
         t = ctypes.c_uint64()
-        _check(load().tft_queue_submit(self.handle, ctypes.byref(d), ctypes.byref(t)), "tft_queue_submit")
+        st = load().tft_queue_submit(self.handle, ctypes.byref(d), _stream(stream), ctypes.byref(t))
+        if st == TFT_EAGAIN:
+            return None
+        _check(st, "tft_queue_submit")
+        self._live[int(t.value)] = (A, B, X)
         return int(t.value)
+
+    def submit(self, A, B, X, stream=None) -> int:
+        """As try_submit, raising TftError(TFT_EAGAIN) when the request does not fit now."""
+        t = self.try_submit(A, B, X, stream)
+        if t is None:
+            raise TftError(TFT_EAGAIN, "tft_queue_submit")
+        return t
 
     def poll(self, ticket: int) -> bool:
         done = ctypes.c_int()
-        _check(load().tft_queue_poll(self.handle, ticket, ctypes.byref(done)), "tft_queue_poll")
+        st = load().tft_queue_poll(self.handle, ticket, ctypes.byref(done))
+        if done.value:
+            self._live.pop(ticket, None)
+        _check(st, "tft_queue_poll")
         return bool(done.value)
 
     def wait(self, ticket: int):
-        _check(load().tft_queue_wait(self.handle, ticket), "tft_queue_wait")
+        st = load().tft_queue_wait(self.handle, ticket)
+        self._live.pop(ticket, None)
+        _check(st, "tft_queue_wait")
 
     def completion_ns(self, ticket: int) -> int:
         ns = ctypes.c_uint64()
@@ -469,8 +494,9 @@ class Queue:
 
     def close(self):
         if self.handle:
-            load().tft_queue_destroy(self.handle)
+            load().tft_queue_destroy(self.handle)   # waits for every submitted request
             self.handle = None
+        self._live = {}
 
     def __del__(self):
         try:
@@ -483,8 +509,8 @@ def tft_queue_create(ctx: Context, pool_words: int, max_inflight: int = 4096) ->
     return Queue(ctx, pool_words, max_inflight)
 
 
-def tft_queue_submit(q: Queue, A, B, X) -> int:
-    return q.submit(A, B, X)
+def tft_queue_submit(q: Queue, A, B, X, stream=None) -> int:
+    return q.submit(A, B, X, stream)
 
 
 def tft_queue_poll(q: Queue, ticket: int) -> bool:

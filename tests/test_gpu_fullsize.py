@@ -2,13 +2,15 @@
 
 - Goldilocks TFT at every length of the sweep: the whole output against the
   oracle's padded FFT; the inverse restores the input.
-- Products at r = n: sampled exact coefficients and the evaluation identity
-  C(z) = A(z) B(z) at random points (a wrong coefficient survives one point
-  with probability at most r/p).
-- The 4096-product batch: a sample of instances against the oracle.
+- Products at every r of the sweep (poly_mul, the space-restricted product and
+  the allocation-free product): every coefficient against the oracle's padded
+  product, plus exact coefficients and the evaluation identity
+  C(z) = A(z) B(z) from the oracle's direct formulas.
+- The 4096-product batch: every instance against the oracle.
 - The three-prime exact product at length 2^24+12345: sampled exact int128
   coefficients and C(z) = A(z) B(z) modulo 2^61-1.
 """
+import os
 import random
 
 import numpy as np
@@ -50,31 +52,52 @@ def test_sweep_lengths_full_output(ctxgl, n):
     assert (X.cpu().numpy() == F).all()
 
 
-@pytest.mark.parametrize("r", [(1 << 22) + 1, (1 << 23) - 1])
+@pytest.mark.parametrize("r", SWEEP)
 def test_products_at_full_size(ctxgl, r):
     p, g = synth.GOLDILOCKS
     la = (r + 2) // 2
     lb = r + 1 - la
+    print(f"[gpu] full-size products r={r}", flush=True)
     A = synth.residues(p, la, 3000 + r)
     B = synth.residues(p, lb, 4000 + r)
     dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     X = torch.empty(r, dtype=torch.uint64, device="cuda")
     Y = torch.empty(r, dtype=torch.uint64, device="cuda")
     libtft.poly_mul(ctxgl, dA, dB, X, Y)
-    C = X.cpu().numpy()
+    X2 = torch.full((r,), 5, dtype=torch.uint64, device="cuda")
+    libtft.poly_mul_restricted(ctxgl, dA, dB, X2)        # output buffer only
+    C, C2 = X.cpu().numpy(), X2.cpu().numpy()
+    ref = oracle.mul_padded(p, g, A, B)
+    bad = np.nonzero(C != ref)[0]
+    assert len(bad) == 0, f"poly_mul: {len(bad)} mismatches, first {bad[:5]}"
+    bad = np.nonzero(C2 != ref)[0]
+    assert len(bad) == 0, f"poly_mul_restricted: {len(bad)} mismatches, first {bad[:5]}"
     rng = random.Random(r)
     for s in [0, 1, r // 2, r - 2, r - 1] + [rng.randrange(r) for _ in range(3)]:
-        assert int(C[s]) == oracle.mul_coeff(p, A, B, s), s
-    for _ in range(2):
-        z = rng.randrange(p)
-        assert oracle.evaluate(p, C, z) == oracle.evaluate(p, A, z) * oracle.evaluate(p, B, z) % p
-    # the space-restricted product (output buffer only) gives the same words
-    X2 = torch.full((r,), 5, dtype=torch.uint64, device="cuda")
-    libtft.poly_mul_restricted(ctxgl, dA, dB, X2)
-    assert torch.equal(X2, X)
+        assert int(ref[s]) == oracle.mul_coeff(p, A, B, s), s
+    z = rng.randrange(p)
+    assert oracle.evaluate(p, ref, z) == oracle.evaluate(p, A, z) * oracle.evaluate(p, B, z) % p
+    if r <= 1 << 22:                                     # the allocation-free product's limit
+        X3 = torch.full((r,), 9, dtype=torch.uint64, device="cuda")
+        libtft.poly_mul_noalloc(ctxgl, dA, dB, X3)
+        assert (X3.cpu().numpy() == ref).all()
 
 
-def test_batch_4096_sampled():
+def _oracle_products(p, g, host):
+    """The oracle's product of every pair, on the host's cores (the oracle
+    releases the interpreter lock while it computes)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(ab):
+        A, B = ab
+        if len(A) * len(B) <= 1_000_000:
+            return oracle.mul_schoolbook(p, A, B)
+        return oracle.mul_padded(p, g, A, B)
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, host))
+
+
+def test_batch_4096_every_instance():
     p, g = synth.P998
     ctx = libtft.Context(p, g)
     count = 4096
@@ -87,17 +110,15 @@ def test_batch_4096_sampled():
         r = len(A) + len(B) - 1
         jobs.append((torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
                      torch.empty(r, dtype=torch.uint32, device="cuda"), torch.empty(r, dtype=torch.uint32, device="cuda")))
-        host.append((A, B))
+        host.append((A.astype(np.uint64), B.astype(np.uint64)))
+    print("[gpu] batch of 4096 products (998244353)", flush=True)
     b = libtft.Batch(ctx, jobs)
     b.run()
     torch.cuda.synchronize()
-    rng = random.Random(5)
-    sample = sorted(set([0, count - 1] + [rng.randrange(count) for _ in range(40)]))
-    big = max(range(count), key=lambda i: len(host[i][0]) + len(host[i][1]))
-    for i in sample + [big]:
-        A, B = host[i]
+    refs = _oracle_products(p, g, host)
+    for i, ref in enumerate(refs):
         got = jobs[i][2].cpu().numpy().astype(np.uint64)
-        assert (got == oracle.mul_padded(p, g, A, B)).all(), i
+        assert (got == ref).all(), f"instance {i}: {len(host[i][0])} x {len(host[i][1])}"
     b.close()
     ctx.close()
 
