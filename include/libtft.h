@@ -125,6 +125,20 @@ tft_status poly_mul_restricted(tft_ctx* ctx, const void* A, size_t m, const void
 tft_status tft_padded_forward(tft_ctx* ctx, void* X, size_t n, void* Xpad, void* hip_stream);
 tft_status tft_padded_inverse(tft_ctx* ctx, void* X, size_t n, void* Xpad, void* hip_stream);
 
+/* Comparator, not the method: van der Hoeven's buffered TFT and ITFT (section
+ * 1.2), which compute the same map as tft_forward / tft_inverse but operate in
+ * a buffer of 2^ceil(lg n) words and keep intermediate results in its
+ * 2^ceil(lg n) - n cells beyond the data.  Here the buffer holds the row /
+ * column schedule's extra evaluations of the partial last row (at
+ * Xbuf + a W, the cells after the data) instead of the context's area, and
+ * the inverse finishes the columns c < b after the last row.  Xbuf is a device
+ * pointer to 2^ceil(lg n) words: the first n hold the input on entry and the
+ * result on exit, the others are working space (unspecified on exit).
+ * Results are bit-identical to tft_forward / tft_inverse; the point of
+ * comparison is the memory (2^ceil(lg n) words instead of n). */
+tft_status tft_buffered_forward(tft_ctx* ctx, void* Xbuf, size_t n, void* hip_stream);
+tft_status tft_buffered_inverse(tft_ctx* ctx, void* Xbuf, size_t n, void* hip_stream);
+
 /* Padded product for comparison: A and B zero-extended to N = 2^ceil(lg r)
  * words in Apad and Bpad (caller-owned), N-point transforms, pointwise
  * product, N-point inverse, first r coefficients to X. */
@@ -206,8 +220,9 @@ tft_status tft_walk_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t 
  *
  * The worker takes pending requests in arrival order while fewer than
  * max_inflight are on the device; each group taken together runs as one
- * batch, and consecutive batches run on two streams so that they overlap on
- * the device; each stream keeps the device and pinned host memory of its
+ * batch, and up to three consecutive batches run on their own streams so
+ * that they overlap on the device; each stream keeps the device and pinned
+ * host memory of its
  * batches' work lists, grown as needed, so a batch in steady state allocates
  * and frees nothing.  poll reports completion without blocking; wait blocks;
  * completion_ns gives the steady-clock time (ns) at which the worker saw the
@@ -250,6 +265,8 @@ typedef struct {
     size_t col_block;      /* power-of-two LDS block per column */
     unsigned cols_per_tile;
     size_t lds_bytes_col, lds_bytes_row;
+    unsigned row_threads;      /* threads of a row workgroup (W/8: one radix-8 unit each; W/16: two) */
+    unsigned stages_per_pass;  /* most butterfly stages per LDS round trip (1..3) */
 } tft_plan_desc;
 tft_status tft_plan_info(tft_ctx* ctx, size_t n, tft_plan_desc* out);
 
@@ -261,19 +278,38 @@ tft_status tft_set_plan_override(tft_ctx* ctx, unsigned logW);
 
 /* Autotuner.  Times forward + inverse round trips of length n on the device
  * (on a buffer of n words the call allocates and frees, filled with i mod p;
- * synchronous) for each valid two-pass column width 2^logW within two of the
- * planner's choice, and records the fastest in the context's plan cache for
- * every length in the same bucket, floor(4 lg n) (quarter octaves).  Later
- * calls of every entry point (single, batched, served) plan with the cached
- * width; any width gives the same results.  Lengths the planner runs in one
+ * synchronous; median of five after a warm-up) for candidate plans, and
+ * records the fastest in the context's plan cache for every length in the
+ * same bucket, floor(4 lg n) (quarter octaves).  Candidates: first the column
+ * width 2^logW within two of the planner's choice, then, at that width, one
+ * knob at a time -- columns per tile (8 or 16), words per row thread (8 or 16:
+ * one or two radix-8 units, which changes how many rows share a CU) and
+ * butterfly stages per LDS round trip (3 or 2).  A candidate replaces the
+ * current choice only when it is 3 % faster.  Later single-transform calls
+ * (tft_forward, tft_inverse, poly_mul and the products built on them) plan
+ * with the cached choice; batches and the serving queue keep their own
+ * shape.  Any plan gives the same results.  Lengths the planner runs in one
  * workgroup are left to the planner (cache entry 0).  `chosen` (may be NULL)
  * receives the resulting plan.  The cache is plain data: tft_plan_cache_get /
- * set read and write the entry of a bucket (0 = the planner's choice), so that
- * a caller can store tuned plans and load them into a new context;
- * tft_plan_bucket gives the bucket of a length. */
+ * set read and write the entry of a bucket, a plan code with log2 W in bits
+ * 0-4 (0: the planner's choice), log2 columns per tile in bits 5-7, log2 words
+ * per row thread in bits 8-10 and stages per LDS round trip in bits 11-12 (0
+ * in a field: the default), so that a caller can store tuned plans and load
+ * them into a new context; tft_plan_bucket gives the bucket of a length. */
 tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen);
-tft_status tft_plan_cache_get(tft_ctx* ctx, unsigned bucket, unsigned* logW);
-tft_status tft_plan_cache_set(tft_ctx* ctx, unsigned bucket, unsigned logW);
+/* Batch autotuner.  Runs the batch of `count` descriptors (as tft_batch_create
+ * and tft_batch_run would: products if `products`, else forward transforms)
+ * with the rows of its two-pass instances at the balanced split of each
+ * length, one step wider (the default) and two steps wider, timing each (median
+ * of five runs after a warm-up; synchronous), and keeps the fastest -- a change
+ * from the default only when 3 % faster -- for every later batch of the context,
+ * the serving queue's included.  The descriptors' outputs are written by the
+ * runs (products: the products themselves; forward transforms: transformed
+ * several times over, so pass scratch copies).  *widen (may be NULL) receives
+ * the choice, 0..2.  Any choice gives the same results. */
+tft_status tft_autotune_batch(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, unsigned* widen);
+tft_status tft_plan_cache_get(tft_ctx* ctx, unsigned bucket, unsigned* code);
+tft_status tft_plan_cache_set(tft_ctx* ctx, unsigned bucket, unsigned code);
 unsigned tft_plan_bucket(size_t n);
 
 /* Measurement mode.  While enabled, each kernel a context launches is

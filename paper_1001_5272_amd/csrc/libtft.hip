@@ -101,9 +101,26 @@ struct Plan {
     uint64_t W, a, b;
     uint32_t Lout, M;    // column outputs and column LDS block (kind 1); LDS block (kind 0)
     uint32_t split;      // kind 1: Lout = M + 1, the column block holds M words (see col_fwd_body)
-    int logC;
+    int logC;            // columns per tile 2^logC
+    unsigned rlog;       // words per row thread 2^rlog (one or two radix-8 units)
+    unsigned smax;       // most stages per LDS round trip
+    unsigned ldstw;      // column tiles copy their twiddles to LDS (1) or read them from memory (0)
     size_t lds_col, lds_row;
 };
+
+// A tuned plan as one word (the plan cache's entries): bits 0-4 log2 W
+// (0: the planner's width), bits 5-7 log2 columns per tile, bits 8-10 log2
+// words per row thread, bits 11-12 stages per LDS round trip (0 in a field:
+// the default).
+struct PlanCode {
+    unsigned logW, logC, rlog, smax;
+};
+inline PlanCode decode_plan(unsigned code) {
+    return PlanCode{code & 31u, (code >> 5) & 7u, (code >> 8) & 7u, (code >> 11) & 3u};
+}
+inline unsigned encode_plan(const PlanCode& c) {
+    return (c.logW & 31u) | ((c.logC & 7u) << 5) | ((c.rlog & 7u) << 8) | ((c.smax & 3u) << 11);
+}
 
 }  // namespace
 
@@ -129,7 +146,8 @@ struct tft_ctx {
     unsigned wbytes;     // 4 or 8
     // plan state, read by every caller's thread and the serving queue's worker
     std::atomic<unsigned> override_logW;
-    std::atomic<unsigned> tuned_logW[kPlanBuckets];   // plan cache by floor(4 lg n): 0 = planner's choice
+    std::atomic<unsigned> tuned_logW[kPlanBuckets];   // plan cache by floor(4 lg n): plan codes, 0 = planner's choice
+    std::atomic<unsigned> batch_widen;                // batches: rows this many steps wider than balanced (0..2)
     tft::ModU32 m32;
     tft::ModGL m64;
     void* tables;        // f1 | f2 | i1 | i2
@@ -239,18 +257,45 @@ auto col_inv_list_kernel(int logC) {
 // longer rows and shorter columns their many small column tiles each finish
 // sooner (a batch of 4096 products with lengths up to 2^16 measured 20 %
 // faster).
+// LDS of a column tile (data and one twiddle table) for len values, as the
+// kernels lay it out: the forward (len = Lout) and the inverse of a class of
+// len values split at H when tft::col_split allows (H + S words per column),
+// else use the power-of-two block (the forward P.M; the inverse 2^ceil(lg len),
+// or P.M for the split mode's long class).
+size_t col_tile_lds(const Plan& P, uint32_t len, bool fwd, unsigned w) {
+    uint32_t H = 0, S = 0;
+    uint32_t blk;
+    const uint32_t tw = P.ldstw ? 1u : 0u;
+    if (fwd) {
+        if (!P.split && P.Lout != P.M && tft::col_split(P.Lout, &H, &S))
+            return ((size_t)tft::padded_words((H + S) << P.logC) + tw * (H / 2)) * w;
+        blk = P.M;
+    } else {
+        const uint32_t Mg = (uint32_t)pow2ceil(len);
+        const bool top = P.split && len == P.M + 1;
+        if (!top && len != Mg && tft::col_split(len, &H, &S))
+            return ((size_t)tft::padded_words((H + S) << P.logC) + tw * (H / 2)) * w;
+        blk = top ? P.M : Mg;
+    }
+    return ((size_t)tft::padded_words(blk << P.logC) + tw * (blk / 2)) * w;
+}
+
 // The autotuner times candidate widths on its own thread: a width forced here
 // applies to that thread's calls only, so other threads (the serving queue's
 // worker, other callers) keep planning from the context's state meanwhile.
-thread_local unsigned tl_force_logW = 0;      // 0: none
+thread_local unsigned tl_force_code = 0;      // 0: none
 thread_local bool tl_ignore_cache = false;   // plan without the tuned widths
+thread_local int tl_batch_widen = -1;        // the batch tuner's candidate (-1: the context's setting)
 
 Plan make_plan(const tft_ctx* ctx, uint64_t n, bool wide = false) {
     Plan P{};
     P.n = n;
     const unsigned w = ctx->wbytes;
-    const unsigned ovr = tl_force_logW ? tl_force_logW
-                                       : (tl_ignore_cache ? 0u : ctx->override_logW.load(std::memory_order_relaxed));
+    const PlanCode force = decode_plan(tl_force_code);
+    const unsigned ovr = force.logW ? force.logW
+                                    : (tl_ignore_cache ? 0u : ctx->override_logW.load(std::memory_order_relaxed));
+    P.smax = 3;
+    P.rlog = 3;
     if (log2u(n) <= small_max_log2(w) && !(ovr && (1ull << ovr) < n)) {
         P.kind = 0;
         P.M = (uint32_t)pow2ceil(n);
@@ -259,6 +304,15 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n, bool wide = false) {
     }
     P.kind = 1;
     P.logC = col_log_width(w);
+    // tile width, row threads and stages of a forced or tuned plan (single
+    // transforms only: a batch shares one tile width and one launch shape)
+    auto knobs = [&](const PlanCode& c) {
+        if (wide) return;
+        if (c.logC == 3 || c.logC == 4) P.logC = (int)c.logC;
+        if (c.rlog == 3 || c.rlog == 4) P.rlog = c.rlog;
+        if (c.smax >= 1 && c.smax <= 3) P.smax = c.smax;
+    };
+    knobs(force);
     auto fill = [&](unsigned logW) {
         P.logW = logW;
         P.W = 1ull << logW;
@@ -268,7 +322,22 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n, bool wide = false) {
         P.M = (uint32_t)pow2ceil(P.Lout);
         P.split = (P.M >= 4 && P.Lout == P.M / 2 + 1) ? 1 : 0;
         if (P.split) P.M /= 2;
-        P.lds_col = ((size_t)tft::padded_words(P.M << P.logC) + P.M / 2) * w;   // tile + one LDS twiddle table
+        // the largest column tile of the forward and of both inverse classes;
+        // the twiddle copy is left out when two tiles per CU fit only without it
+        auto tile = [&]() {
+            size_t l = col_tile_lds(P, P.Lout, true, w);
+            if (P.a) l = std::max(l, col_tile_lds(P, (uint32_t)P.a, false, w));
+            if (P.b) l = std::max(l, col_tile_lds(P, (uint32_t)P.a + 1, false, w));
+            return l;
+        };
+        P.ldstw = 1;
+        P.lds_col = tile();
+        if (P.lds_col > kLdsSoft) {
+            P.ldstw = 0;
+            const size_t bare = tile();
+            if (bare <= kLdsSoft) P.lds_col = bare;
+            else P.ldstw = 1;
+        }
         P.lds_row = (size_t)tft::padded_words((uint32_t)P.W) * w;
     };
     const unsigned logC = (unsigned)P.logC;
@@ -279,10 +348,16 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n, bool wide = false) {
     }
     const unsigned k = log2u(n);
     const unsigned bk = plan_bucket(n);
-    const unsigned tuned = (bk < kPlanBuckets && !tl_ignore_cache) ? ctx->tuned_logW[bk].load(std::memory_order_relaxed) : 0u;
-    if (tuned && (1ull << tuned) < n) {   // tft_autotune
-        fill(tuned);
-        if (P.W >= (1ull << logC) && P.a >= 1 && P.lds_col <= kLdsDynMax && P.lds_row <= kLdsDynMax) return P;
+    const PlanCode tuned = decode_plan((bk < kPlanBuckets && !tl_ignore_cache && !wide && !tl_force_code)
+                                           ? ctx->tuned_logW[bk].load(std::memory_order_relaxed) : 0u);
+    if (tuned.logW && (1ull << tuned.logW) < n) {   // tft_autotune
+        const int logC0 = P.logC;
+        knobs(tuned);
+        fill(tuned.logW);
+        if (P.W >= (1ull << P.logC) && P.a >= 1 && P.lds_col <= kLdsDynMax && P.lds_row <= kLdsDynMax) return P;
+        P.logC = logC0;
+        P.rlog = 3;
+        P.smax = 3;
     }
     // balanced split: W close to sqrt(n), within the LDS budget (preferred
     // budget first, then the larger one)
@@ -291,7 +366,9 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n, bool wide = false) {
         for (unsigned logW = logC; logW <= 16 && (1ull << logW) < n; logW++) {
             fill(logW);
             if (P.lds_col > lim || P.lds_row > lim) continue;
-            const int t = (int)k + (wide ? 1 : 0);
+            const int widen = !wide ? 0
+                              : tl_batch_widen >= 0 ? tl_batch_widen : (int)ctx->batch_widen.load(std::memory_order_relaxed);
+            const int t = (int)k + widen;
             if (best < 0 || std::abs(2 * (int)logW - t) <= std::abs(2 * best - t)) best = (int)logW;
         }
         if (best >= 0) {
@@ -349,7 +426,7 @@ bool set_lds_limits() {
 // Threads of a row workgroup: one radix-8 unit per thread (W / 8, 64 ..
 // 1024), so that idle threads of a wider workgroup do not hold wave slots.
 uint32_t row_threads(const Plan& P) {
-    return (uint32_t)std::min<uint64_t>(tft::kRowThreads, std::max<uint64_t>(64, P.W >> 3));
+    return (uint32_t)std::min<uint64_t>(tft::kRowThreads, std::max<uint64_t>(64, P.W >> (P.rlog ? P.rlog : 3)));
 }
 
 // Threads of a column-tile workgroup: one radix-8 unit per thread (M C / 8,
@@ -377,18 +454,24 @@ tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t
     G.Q = nullptr;
     G.g0 = 0;
     G.nparts = 0;
+    G.ldstw = P.ldstw;
     return G;
 }
 
 // -------------------------------------------------------------- forward
 template <class Mod>
+// buffered (comparator): the extra evaluations of the partial last row go to
+// X + a W, inside X's buffer of 2^ceil(lg n) words, instead of the context's
+// area
 tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_src, typename Mod::Word* X,
-                        uint64_t n, hipStream_t st, uint64_t g0 = 0, uint32_t copies = 1) {
+                        uint64_t n, hipStream_t st, uint64_t g0 = 0, uint32_t copies = 1,
+                        bool buffered = false) {
     using Word = typename Mod::Word;
     const Mod& md = mod_of<Mod>(ctx);
-    const auto T = tables_of<Word>(ctx);
     const Plan P = make_plan(ctx, n);
     if (P.kind < 0) return TFT_ERANGE;
+    auto T = tables_of<Word>(ctx);
+    T.smax = P.smax;
     if (P.kind == 0) {
         if (src != X) {
             launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3(1), dim3(kThreads), 0, st, X, n, src, n_src);
@@ -399,7 +482,7 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
     }
     if (g0 && P.b) return TFT_EINVAL;   // a block at g0 != 0 is a whole power-of-two block
     Word* V = reinterpret_cast<Word*>(ctx->varea);
-    auto G = two_pass_of<Word>(P, X, src, n_src, nullptr, V);
+    auto G = two_pass_of<Word>(P, X, src, n_src, nullptr, buffered ? X + P.a * P.W : V);
     G.g0 = g0;
     const uint32_t tiles = (uint32_t)(P.W >> P.logC);
     // b = 1: the column tiles leave shares of the last row's one output
@@ -415,13 +498,17 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
 
 // -------------------------------------------------------------- inverse
 template <class Mod>
+// buffered (comparator): the extra evaluations live in X's buffer beyond n
+// (X + a W, a buffer of 2^ceil(lg n) words) and the columns c < b wait for
+// the last row (no early modes: those keep per-column values in the area too)
 tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod::Word* Y, uint64_t n,
-                        hipStream_t st) {
+                        hipStream_t st, bool buffered = false) {
     using Word = typename Mod::Word;
     const Mod& md = mod_of<Mod>(ctx);
-    const auto T = tables_of<Word>(ctx);
     const Plan P = make_plan(ctx, n);
     if (P.kind < 0) return TFT_ERANGE;
+    auto T = tables_of<Word>(ctx);
+    T.smax = P.smax;
     if (P.kind == 0) {
         if (Y) launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3(1), dim3(kThreads), 0, st, md, X, Y, n);
         launch(ctx, TFT_K_SMALL_INV, tft::k_small_inv<Mod>, dim3(1), dim3(tft::kSmallThreads), P.lds_row + (size_t)P.M * ctx->wbytes, st, md, T, X, (uint32_t)n,
@@ -429,7 +516,7 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
         return launch_status();
     }
     Word* V = reinterpret_cast<Word*>(ctx->varea);
-    auto G = two_pass_of<Word>(P, X, X, n, Y, V);
+    auto G = two_pass_of<Word>(P, X, X, n, Y, buffered ? X + P.a * P.W : V);
     // With b > 0 the columns c < b (a + 1 values) run with the columns c >= b on
     // their first a values and are finished after the last row: in split mode
     // by the last-row inverse alone (two coefficients change), otherwise by a
@@ -440,8 +527,8 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     // b = W - 1 as well: the one short column and the last row are full
     // inverses with one value missing (k_tail_inv), no truncated walks
     const size_t lds_tail = ((size_t)tft::padded_words((uint32_t)P.a + 1) + (P.a + 1) / 2) * ctx->wbytes;
-    const bool one_short = full_long && P.b + 1 == P.W && P.logW >= 6 && lds_tail <= kLdsDynMax;
-    G.early = one_short ? 3u : (P.b && !full_long) ? (P.split ? 1u : 2u) : 0u;
+    const bool one_short = !buffered && full_long && P.b + 1 == P.W && P.logW >= 6 && lds_tail <= kLdsDynMax;
+    G.early = buffered ? 0u : one_short ? 3u : (P.b && !full_long) ? (P.split ? 1u : 2u) : 0u;
     G.Q = V + kVWords;
     const uint32_t C = 1u << P.logC;
     const uint32_t tiles_all = (uint32_t)(P.W >> P.logC);
@@ -449,10 +536,13 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows + (G.early == 2 ? 1u : 0u)), dim3(row_threads(P)),
            P.lds_row, st, md, T, G, ctx->p);
     auto kern = col_inv_kernel<Mod>(P.logC);
+    // LDS of a column tile inverting len values (as the kernel lays it out)
+    auto col_lds = [&](uint32_t len) -> size_t { return col_tile_lds(P, len, false, ctx->wbytes); };
     if (one_short) {
         launch(ctx, TFT_K_LAST_INV, tft::k_tail_inv<Mod>, dim3(1), dim3(tft::kLastThreads), lds_tail, st, md, T, G);
         const uint32_t nt = (uint32_t)((P.b + C - 1) / C);   // columns c < b, in full
-        launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(col_threads(P)), P.lds_col, st, md, T, G, 1, 0u, nt);
+        launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(col_threads(P)), col_lds((uint32_t)P.a + 1), st, md, T,
+               G, 1, 0u, nt);
         return launch_status();
     }
     // A class with only a few columns runs one column per workgroup, so that a
@@ -467,7 +557,8 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
         } else {
             const uint32_t nt = tiles_all - t0;
             if (P.b == 1 && t0 == 0) G.nparts = nt;   // every tile leaves its share of the last-row sum
-            launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(col_threads(P)), P.lds_col, st, md, T, G, 0, t0, nt);
+            launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(col_threads(P)), col_lds((uint32_t)P.a), st, md, T, G,
+                   0, t0, nt);
         }
     }
     if (P.b) {
@@ -482,8 +573,8 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
                        lds_one, st, md, T, G, 1, 0u, (uint32_t)P.b);
             } else {
                 const uint32_t nt = (uint32_t)((P.b + C - 1) / C);
-                launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(col_threads(P)), P.lds_col, st, md, T, G, 1,
-                       0u, nt);
+                launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(col_threads(P)), col_lds((uint32_t)P.a + 1), st, md,
+                       T, G, 1, 0u, nt);
             }
         }
     }
@@ -1085,7 +1176,7 @@ tft_status batch_once(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pro
 // in order while their workspace (r words, the in-place footprint of B's
 // transform) fits in the queue's device pool and fewer than max_inflight
 // requests are on the device; each group of newly admitted requests becomes
-// one batch, launched with whichever of two slots (a stream and a reusable
+// one batch, launched with whichever of kQueueSlots slots (a stream and a reusable
 // batch arena) is free, so that consecutive batches overlap on the device and
 // a batch in steady state neither allocates nor frees device memory.  The worker polls the batches' completion
 // events, releases their workspace, records completion times and admits more.
@@ -1154,6 +1245,9 @@ uint64_t now_ns() {
 
 }  // namespace
 
+// Batches a queue keeps in flight at once (each with its stream and arena).
+constexpr int kQueueSlots = 3;
+
 struct tft_queue {
     tft_ctx* ctx;
     void* pool;
@@ -1169,9 +1263,9 @@ struct tft_queue {
     uint64_t next_ticket;
     bool stop;
     std::thread worker;
-    hipStream_t streams[2];
-    BatchArena arenas[2];
-    bool slot_busy[2];
+    hipStream_t streams[kQueueSlots];
+    BatchArena arenas[kQueueSlots];
+    bool slot_busy[kQueueSlots];
     uint64_t n_submitted, n_completed, n_batches, n_rejected, max_pool_used;
     tft_status error;
     // one event per producer stream, recorded by every submit on that stream;
@@ -1183,7 +1277,6 @@ namespace {
 
 void queue_worker(tft_queue* q) {
     (void)hipSetDevice(q->ctx->device);
-    const unsigned w = q->ctx->wbytes;
     std::unique_lock<std::mutex> lk(q->mu);
     for (;;) {
         bool progress = false;
@@ -1211,7 +1304,9 @@ void queue_worker(tft_queue* q) {
         if (progress) q->cv_done.notify_all();
         // admit in arrival order and launch one batch (at most two batches in
         // flight, one per slot)
-        const int slot = !q->slot_busy[0] ? 0 : !q->slot_busy[1] ? 1 : -1;
+        int slot = -1;
+        for (int i = 0; i < kQueueSlots && slot < 0; i++)
+            if (!q->slot_busy[i]) slot = i;
         if (!q->pending.empty() && slot >= 0) {
             std::vector<QReq> group;
             while (!q->pending.empty() && group.size() < q->max_batch && q->inflight_reqs + group.size() < q->max_inflight) {
@@ -1335,6 +1430,7 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
     c->v = v < kMaxLog2 ? v : kMaxLog2;
     c->wbytes = wide ? 8 : 4;
     c->override_logW.store(0);
+    c->batch_widen.store(1);
     for (unsigned i = 0; i < kPlanBuckets; i++) c->tuned_logW[i].store(0);
     c->timing.store(false);
     c->timing_mask.store(~0u);
@@ -1494,6 +1590,32 @@ tft_status tft_padded_inverse(tft_ctx* ctx, void* X, size_t n, void* Xpad, void*
     });
 }
 
+tft_status tft_buffered_forward(tft_ctx* ctx, void* Xbuf, size_t n, void* stream) {
+    if (!ctx || !Xbuf) return TFT_EINVAL;
+    tft_status s = check_len(ctx, n);
+    if (s != TFT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    return dispatch(ctx, [&] {
+        if (ctx->wbytes == 4) {
+            auto* x = (uint32_t*)Xbuf;
+            return forward_impl<tft::ModU32>(ctx, x, n, x, n, st, 0, 1, true);
+        }
+        auto* x = (uint64_t*)Xbuf;
+        return forward_impl<tft::ModGL>(ctx, x, n, x, n, st, 0, 1, true);
+    });
+}
+
+tft_status tft_buffered_inverse(tft_ctx* ctx, void* Xbuf, size_t n, void* stream) {
+    if (!ctx || !Xbuf) return TFT_EINVAL;
+    tft_status s = check_len(ctx, n);
+    if (s != TFT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    return dispatch(ctx, [&] {
+        if (ctx->wbytes == 4) return inverse_impl<tft::ModU32>(ctx, (uint32_t*)Xbuf, nullptr, n, st, true);
+        return inverse_impl<tft::ModGL>(ctx, (uint64_t*)Xbuf, nullptr, n, st, true);
+    });
+}
+
 tft_status poly_mul_padded(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X, void* Apad,
                            void* Bpad, void* stream) {
     if (!ctx || !A || !B || !X || !Apad || !Bpad || m == 0 || nb == 0) return TFT_EINVAL;
@@ -1525,6 +1647,8 @@ tft_status tft_plan_info(tft_ctx* ctx, size_t n, tft_plan_desc* out) {
     out->cols_per_tile = P.kind == 1 ? (1u << P.logC) : 0;
     out->lds_bytes_col = P.lds_col;
     out->lds_bytes_row = P.lds_row;
+    out->row_threads = P.kind == 1 ? row_threads(P) : 0;
+    out->stages_per_pass = P.smax;
     return TFT_OK;
 }
 
@@ -1641,18 +1765,18 @@ tft_status tft_queue_create(tft_ctx* ctx, size_t pool_words, size_t max_inflight
     q->inflight_reqs = 0;
     q->next_ticket = 1;
     q->stop = false;
-    q->slot_busy[0] = q->slot_busy[1] = false;
+    for (int i = 0; i < kQueueSlots; i++) q->slot_busy[i] = false;
     q->n_submitted = q->n_completed = q->n_batches = q->n_rejected = q->max_pool_used = 0;
     q->error = TFT_OK;
     q->alloc.init(pool_words);
     hipError_t e = hipMalloc(&q->pool, pool_words * ctx->wbytes);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->streams[0], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->streams[1], hipStreamNonBlocking);
-    if (e == hipSuccess) e = arena_init(&q->arenas[0]);
-    if (e == hipSuccess) e = arena_init(&q->arenas[1]);
+    for (int i = 0; i < kQueueSlots; i++) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->streams[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = arena_init(&q->arenas[i]);
+    }
     if (e != hipSuccess) {
         if (q->pool) (void)hipFree(q->pool);
-        for (int i = 0; i < 2; i++) {
+        for (int i = 0; i < kQueueSlots; i++) {
             if (q->streams[i]) (void)hipStreamDestroy(q->streams[i]);
             arena_free(&q->arenas[i]);
         }
@@ -1756,10 +1880,10 @@ void tft_queue_destroy(tft_queue* q) {
     }
     if (q->worker.joinable()) q->worker.join();
     DeviceGuard guard(q->ctx->device);
-    (void)hipStreamDestroy(q->streams[0]);
-    (void)hipStreamDestroy(q->streams[1]);
-    arena_free(&q->arenas[0]);
-    arena_free(&q->arenas[1]);
+    for (int i = 0; i < kQueueSlots; i++) {
+        (void)hipStreamDestroy(q->streams[i]);
+        arena_free(&q->arenas[i]);
+    }
     for (auto& kv : q->src_events)
         if (kv.second) (void)hipEventDestroy(kv.second);
     (void)hipFree(q->pool);
@@ -1834,7 +1958,7 @@ tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen) {
     tl_ignore_cache = true;   // the planner's own choice, whatever the context holds
     const Plan base = make_plan(ctx, n);
     tft_status st = TFT_OK;
-    unsigned best = 0;
+    unsigned best_code = 0;
     if (base.kind == 1) {
         void* X = nullptr;
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1848,62 +1972,128 @@ tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen) {
                 tft::k_fill_index<uint32_t><<<1024, kThreads>>>((uint32_t*)X, n, ctx->p);
             if (hipGetLastError() != hipSuccess) st = TFT_EDEVICE;
         }
-        // median of five timed round trips per candidate (after one warm-up);
-        // another width replaces the planner's only when 3 % faster, so that
-        // run-to-run noise does not move the plan
-        float base_ms = 0.f, best_ms = 0.f;
-        const int lo = std::max<int>((int)base.logW - 2, (int)base.logC), hi = std::min<int>((int)base.logW + 2, 16);
-        for (int lw = lo; lw <= hi && st == TFT_OK; lw++) {
-            if ((1ull << lw) >= n) break;
-            tl_force_logW = (unsigned)lw;
-            if (make_plan(ctx, n).kind != 1) continue;
-            auto round_trip = [&]() {
-                tft_status a = tft_forward(ctx, X, n, nullptr);
-                tft_status b = tft_inverse(ctx, X, n, nullptr);
-                return a != TFT_OK ? a : b;
-            };
+        // median of five timed round trips of a candidate plan (after one
+        // warm-up); +inf if the candidate is not a valid plan
+        auto time_plan = [&](const PlanCode& c) -> float {
+            tl_force_code = encode_plan(c);
+            const Plan P = make_plan(ctx, n);
+            if (P.kind != 1 || P.logW != c.logW) return 1e30f;
             float t[6];
             for (int rep = 0; rep < 6 && st == TFT_OK; rep++) {
                 t[rep] = 0.f;
                 if (hipEventRecord(e0, nullptr) != hipSuccess) { st = TFT_EDEVICE; break; }
-                const tft_status r = round_trip();
-                if (r != TFT_OK) { st = r; break; }
+                tft_status a = tft_forward(ctx, X, n, nullptr);
+                tft_status b = tft_inverse(ctx, X, n, nullptr);
+                if (a != TFT_OK || b != TFT_OK) { st = a != TFT_OK ? a : b; break; }
                 if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                     st = TFT_EDEVICE;
                     break;
                 }
                 (void)hipEventElapsedTime(&t[rep], e0, e1);
             }
-            if (st != TFT_OK) break;
+            if (st != TFT_OK) return 1e30f;
             std::sort(t + 1, t + 6);   // t[0] is the warm-up
-            const float ms = t[3];
-            if ((unsigned)lw == base.logW) base_ms = ms;
-            if (best == 0 || ms < best_ms) {
-                best = (unsigned)lw;
+            return t[3];
+        };
+        // 1. the column width (logW) within two of the planner's, each with one
+        //    and with two radix-8 units per row thread (how many rows share a
+        //    CU decides whether the row pass takes one round of workgroups or
+        //    two); another choice replaces the planner's only when 3 % faster,
+        //    so that run-to-run noise does not move the plan
+        PlanCode best{base.logW, (unsigned)base.logC, 3u, 3u};
+        float best_ms = time_plan(best);
+        const float base_ms = best_ms;
+        const int lo = std::max<int>((int)base.logW - 2, 3), hi = std::min<int>((int)base.logW + 2, 16);
+        for (int lw = lo; lw <= hi && st == TFT_OK; lw++) {
+            if ((1ull << lw) >= n) continue;
+            for (unsigned rl = 3; rl <= 4 && st == TFT_OK; rl++) {
+                if ((unsigned)lw == base.logW && rl == 3) continue;
+                PlanCode c = best;
+                c.logW = (unsigned)lw;
+                c.rlog = rl;
+                const float ms = time_plan(c);
+                if (ms < 0.97f * best_ms) {
+                    best = c;
+                    best_ms = ms;
+                }
+            }
+        }
+        // 2. at that width, one knob at a time: columns per tile (8 or 16),
+        //    stages per LDS round trip (3 or 2); each kept only when 3 % faster
+        for (int knob = 0; knob < 3 && st == TFT_OK; knob++) {
+            if (knob == 1) continue;   // words per row thread: searched with the width
+            PlanCode c = best;
+            if (knob == 0) c.logC = c.logC == 3 ? 4u : 3u;
+            if (knob == 2) c.smax = c.smax == 3 ? 2u : 3u;
+            const float ms = time_plan(c);
+            if (ms < 0.97f * best_ms) {
+                best = c;
                 best_ms = ms;
             }
         }
-        if (st == TFT_OK && best != base.logW && base_ms > 0.f && best_ms > 0.97f * base_ms) best = base.logW;
+        (void)base_ms;
+        best_code = encode_plan(best);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         if (X) (void)hipFree(X);
     }
-    tl_force_logW = 0;
+    tl_force_code = 0;
     tl_ignore_cache = false;
-    ctx->tuned_logW[k].store(st == TFT_OK ? best : saved_tuned);
+    ctx->tuned_logW[k].store(st == TFT_OK ? best_code : saved_tuned);
     if (st == TFT_OK && chosen) st = tft_plan_info(ctx, n, chosen);
     return st;
 }
 
-tft_status tft_plan_cache_get(tft_ctx* ctx, unsigned bucket, unsigned* logW) {
-    if (!ctx || !logW || bucket >= kPlanBuckets) return TFT_EINVAL;
-    *logW = ctx->tuned_logW[bucket];
+tft_status tft_autotune_batch(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, unsigned* widen) {
+    if (!ctx || !d || count == 0) return TFT_EINVAL;
+    DeviceGuard dg(ctx->device);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    tft_status st = TFT_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = TFT_EDEVICE;
+    // median of five timed runs per candidate (after one warm-up run); another
+    // width replaces the default (one step wider) only when 3 % faster
+    float ms[3] = {0.f, 0.f, 0.f};
+    for (int w = 0; w < 3 && st == TFT_OK; w++) {
+        tl_batch_widen = w;
+        tft_batch* B = nullptr;
+        st = tft_batch_create(ctx, d, count, products, &B);
+        tl_batch_widen = -1;
+        if (st != TFT_OK) break;
+        float t[6];
+        for (int rep = 0; rep < 6 && st == TFT_OK; rep++) {
+            if (hipEventRecord(e0, nullptr) != hipSuccess) st = TFT_EDEVICE;
+            if (st == TFT_OK) st = tft_batch_run(B, nullptr);
+            if (st == TFT_OK && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                st = TFT_EDEVICE;
+            t[rep] = 0.f;
+            if (st == TFT_OK) (void)hipEventElapsedTime(&t[rep], e0, e1);
+        }
+        tft_batch_destroy(B);
+        if (st != TFT_OK) break;
+        std::sort(t + 1, t + 6);
+        ms[w] = t[3];
+    }
+    tl_batch_widen = -1;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != TFT_OK) return st;
+    unsigned best = 1;
+    for (unsigned w = 0; w < 3; w++)
+        if (ms[w] < 0.97f * ms[best]) best = w;
+    ctx->batch_widen.store(best);
+    if (widen) *widen = best;
     return TFT_OK;
 }
 
-tft_status tft_plan_cache_set(tft_ctx* ctx, unsigned bucket, unsigned logW) {
-    if (!ctx || bucket >= kPlanBuckets || logW > 16) return TFT_EINVAL;
-    ctx->tuned_logW[bucket] = logW;
+tft_status tft_plan_cache_get(tft_ctx* ctx, unsigned bucket, unsigned* code) {
+    if (!ctx || !code || bucket >= kPlanBuckets) return TFT_EINVAL;
+    *code = ctx->tuned_logW[bucket];
+    return TFT_OK;
+}
+
+tft_status tft_plan_cache_set(tft_ctx* ctx, unsigned bucket, unsigned code) {
+    if (!ctx || bucket >= kPlanBuckets || (code & 31u) > 16 || code >> 13) return TFT_EINVAL;
+    ctx->tuned_logW[bucket] = code;
     return TFT_OK;
 }
 

@@ -43,6 +43,8 @@ struct Tables {
     // w_s = w[K]^(rev_K s): K is the order (log 2) of the root the tables
     // expand, so w[K]^e = w_{rev_K e} for 0 <= e < 2^K
     uint32_t K = 0;
+    // most stages per LDS round trip (1..3), a tuning parameter of the plan
+    uint32_t smax = 3;
 };
 
 // Threads in the workgroup.  Every launch here has uniform workgroups, so the
@@ -427,9 +429,9 @@ __device__ __forceinline__ void eval_lanes(const Mod& md, const typename Mod::Wo
 // dependent chain for one lane: when the radix-8 units would leave more than
 // half of the workgroup idle (a block that alone occupies the CU), smaller
 // units give more lanes shorter chains.
-__device__ __forceinline__ int group_stages(uint32_t words, int left) {
+__device__ __forceinline__ int group_stages(uint32_t words, int left, uint32_t smax = 3) {
     const uint32_t half = nthreads() >> 1;
-    int S = 3;
+    int S = (int)smax;
     while (S > 1 && (words >> S) < half) S--;
     return S < left ? S : left;
 }
@@ -451,7 +453,7 @@ __device__ __forceinline__ void dif_stages(const Mod& md, const Tables<typename 
         const typename Mod::Word* tab = lds ? T.lf : T.f1;
         const uint32_t sh = lds ? 0u : 1u;
         for (uint32_t h = h_hi; h >= h_lo;) {
-            const int S = group_stages(words, __builtin_ctz(h) - lo + 1);
+            const int S = group_stages(words, __builtin_ctz(h) - lo + 1, T.smax);
             if (h == M >> 1) {   // the first group: sub-blocks q = 0 have twiddle 1
                 if (S == 3) dif_group<Mod, 3, true, true>(md, T, buf, logC, M, h, out_lo, out_hi, 0, tab, sh);
                 else if (S == 2) dif_group<Mod, 2, true, true>(md, T, buf, logC, M, h, out_lo, out_hi, 0, tab, sh);
@@ -466,7 +468,7 @@ __device__ __forceinline__ void dif_stages(const Mod& md, const Tables<typename 
         return;
     }
     for (uint32_t h = h_hi; h >= h_lo;) {
-        const int S = group_stages(words, __builtin_ctz(h) - lo + 1);
+        const int S = group_stages(words, __builtin_ctz(h) - lo + 1, T.smax);
         if (S == 3) dif_group<Mod, 3>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
         else if (S == 2) dif_group<Mod, 2>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
         else dif_group<Mod, 1>(md, T, buf, logC, M, h, out_lo, out_hi, g0);
@@ -527,7 +529,7 @@ __device__ __forceinline__ void dit_stages(const Mod& md, const Tables<typename 
     const int L = __builtin_ctz(Sz);
     const uint32_t words = Sz << logC;
     for (int done = d0; done < d1;) {    // stages 2^d0 .. 2^(done-1) finished
-        const int S = RADIX8 ? (d1 - done < 3 ? d1 - done : 3) : group_stages(words, d1 - done);
+        const int S = RADIX8 ? (d1 - done < 3 ? d1 - done : 3) : group_stages(words, d1 - done, T.smax);
         const uint32_t h = 1u << (done + S - 1);
         if (g == 0) {   // block 0: twiddles as in dif_stages; the last group skips twiddle 1
             const bool lds = T.nli >= (Sz >> 1);
@@ -733,7 +735,7 @@ __device__ __forceinline__ void pieces_inverse(const Mod& md, const Tables<typen
         sh = T.nli >= (M >> 1) ? 0u : 1u;
     }
     for (int s0 = 0; s0 < top;) {
-        const int S = group_stages(m << logC, top - s0);
+        const int S = group_stages(m << logC, top - s0, T.smax);
         if (S == 3) pieces_pass<Mod, 3>(md, T, buf, logC, m, gbase, (uint32_t)s0, scale, tab, sh);
         else if (S == 2) pieces_pass<Mod, 2>(md, T, buf, logC, m, gbase, (uint32_t)s0, scale, tab, sh);
         else pieces_pass<Mod, 1>(md, T, buf, logC, m, gbase, (uint32_t)s0, scale, tab, sh);

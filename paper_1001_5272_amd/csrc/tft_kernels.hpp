@@ -75,7 +75,12 @@ __device__ __forceinline__ void small_inverse_body(const Mod& md, const Tables<t
 }
 
 // Whole product in one workgroup: both operands zero-extended to M words of
-// LDS, forward transforms truncated to r outputs, pointwise product, inverse.
+// LDS (M = 2^ceil(lg r), on-chip scratch; X in HBM holds only the r words of
+// the product), full M-point forward transforms, pointwise product and full
+// M-point inverse: the product has degree < r <= M, so the cyclic product of
+// length M is the product itself.  The full inverse (one scaling by 1/M on the
+// store) replaces the truncated inverse's dependent walk, the longest part of
+// a single-workgroup product.
 template <class Mod>
 __device__ __forceinline__ void small_mul_body(const Mod& md, const Tables<typename Mod::Word>& T0, const typename Mod::Word* A,
                                uint32_t m, const typename Mod::Word* B, uint32_t nb, typename Mod::Word* X,
@@ -90,12 +95,13 @@ __device__ __forceinline__ void small_mul_body(const Mod& md, const Tables<typen
         bb[pad(i)] = i < nb ? B[i] : Word(0);
     }
     __syncthreads();
-    dif_forward(md, L, ba, 0, M, 0, r, 0);
-    dif_forward(md, L, bb, 0, M, 0, r, 0);
-    for (uint32_t i = threadIdx.x; i < M; i += nthreads()) ba[pad(i)] = i < r ? md.mul(ba[pad(i)], bb[pad(i)]) : Word(0);
+    dif_forward(md, L, ba, 0, M, 0, M, 0);
+    dif_forward(md, L, bb, 0, M, 0, M, 0);
+    for (uint32_t i = threadIdx.x; i < M; i += nthreads()) ba[pad(i)] = md.mul(ba[pad(i)], bb[pad(i)]);
     __syncthreads();
-    gitft(md, L, ba, 0, M, r, 0);
-    for (uint32_t i = threadIdx.x; i < r; i += nthreads()) X[i] = ba[pad(i)];
+    full_inverse<Mod, false>(md, L, ba, 0, 0, M, 0);
+    const Word sc = inv_pow2_tw(md, __builtin_ctz(M));
+    for (uint32_t i = threadIdx.x; i < r; i += nthreads()) X[i] = md.mul_tw(ba[pad(i)], sc);
 }
 
 // Single-instance single-workgroup kernels are latency-bound: run 16 waves.
@@ -144,11 +150,34 @@ struct TwoPass {
     Word* Q;          // early == 2: Q_0..Q_a at Q, scratch at Q + kQStride, 1 / Q(w_a) at Q[2 kQStride]
     uint64_t g0;      // forward of a whole block (n = a W, b = 0): the block's global index, else 0
     uint32_t nparts;  // inverse with b = 1: column tiles leaving a partial last-row sum at Q + kQStride, or 0
+    uint32_t ldstw;   // 1: column tiles copy their block-0 twiddles to LDS; 0: read them from the table in memory
+                      // (when the copy would cost a tile per CU)
 };
 constexpr uint32_t kQStride = (1u << 16) + 64;
 
 constexpr int kMaxC = 16;   // widest column tile
 constexpr int kLastThreads = 1024;   // the last-row inverse is one workgroup: give it many waves
+
+// A column transform of len values, len not a power of two, may split at H,
+// the largest power of two below len: with R = len - H it needs a block of
+// S = 2^ceil(lg R) words besides the H-word block, and is used when
+// H/32 <= S <= H/4 (then H + S words of LDS per column instead of 2H; see
+// col_fwd_body and col_inv_body).
+__host__ __device__ inline bool col_split(uint32_t len, uint32_t* H, uint32_t* S) {
+    uint32_t h = 1;
+    while (2 * h < len) h <<= 1;   // h < len <= 2h
+    if (h == len || h < 64) return false;
+    uint32_t s = 1;
+    while (s < len - h) s <<= 1;
+    // S <= H/4 saves a quarter of the LDS or more (at S = H/2 the unfused
+    // passes cost more than the smaller tile gains, measured at a = 768);
+    // S >= H/32 keeps the fold (H/S terms per word, one dependent chain per
+    // thread) short
+    if (4 * s > h || 32 * s < h) return false;
+    *H = h;
+    *S = s;
+    return true;
+}
 
 // Forward column pass over the tile of C columns starting at column tile*C:
 // evaluates each column polynomial at w_0..w_{Lout-1} (Lout = a + (b > 0)) in
@@ -162,7 +191,12 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
     __shared__ Word red[(kColThreads / 64) * C];
     __shared__ Word extra[C], hi0[C];
     Word* buf = lds_buf<Word>();
-    const Tables<Word> T = local_tables<Word, true, false>(T0, buf + padded_words(P.M << LOGC), P.M / 2);
+    uint32_t Hs = 0, Ss = 0;
+    const bool hs = !P.split && P.g0 == 0 && P.Lout != P.M && col_split(P.Lout, &Hs, &Ss);
+    const Tables<Word> T = hs ? local_tables<Word, true, false>(T0, buf + padded_words((Hs + Ss) << LOGC),
+                                                                P.ldstw ? Hs / 2 : 0u)
+                              : local_tables<Word, true, false>(T0, buf + padded_words(P.M << LOGC),
+                                                                P.ldstw ? P.M / 2 : 0u);
     const uint32_t c0 = tile * C;
     const uint64_t W = 1ull << P.logW;
     // b = 1 (P.nparts): the tile's share sum_c Z_c w_{aW}^c of the last row's
@@ -273,6 +307,52 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
                 P.V[c0 + c] = v;
             if (share && d == H) zterm[c] = md.mul_tw(v, ypow[c]);
         }
+        if (share) put_share();
+        return;
+    }
+    if (hs) {
+        // Lout = H + R outputs, R <= S <= H/2, and every column has at most
+        // Lout coefficients: P = lo + x^H hi (hi: R coefficients at most).
+        // Outputs s < H are the block-0 transform of A = P mod (x^H - 1)
+        // = lo + hi; outputs H .. H + R - 1 lie in the block of size S at
+        // global index H/S, which holds (lo - hi) mod (x^S - w_{H/S}):
+        // F_j = sum_k A_{j + k S} w_{H/S}^k - 2 hi_j.  H + S words of LDS per
+        // column instead of 2H.
+        const uint32_t H = Hs, S = Ss, R = P.Lout - Hs;
+        Word* fb = buf + pad(H << LOGC);   // the block of S words (H C is a multiple of 32)
+        staged_copy<8>(H * C, [&](uint32_t it) {
+            const uint32_t c = it & (C - 1), d = it >> LOGC;
+            const uint64_t idx = (c0 + c) + (uint64_t)d * W;
+            return idx < P.n_src ? P.src[idx] : Word(0);
+        }, [&](uint32_t it, Word v) { buf[pad(it)] = v; });
+        staged_copy<8>(S * C, [&](uint32_t it) {
+            const uint32_t c = it & (C - 1), j = it >> LOGC;
+            const uint64_t idx = (c0 + c) + (uint64_t)(H + j) * W;
+            return (j < R && idx < P.n_src) ? P.src[idx] : Word(0);
+        }, [&](uint32_t it, Word v) { fb[pad(it)] = v; });
+        __syncthreads();
+        for (uint32_t it = threadIdx.x; it < (R << LOGC); it += nthreads()) buf[pad(it)] = md.add(buf[pad(it)], fb[pad(it)]);
+        __syncthreads();
+        const Word cf = tw_fwd(md, T, H / S);
+        for (uint32_t it = threadIdx.x; it < (S << LOGC); it += nthreads()) {
+            const uint32_t c = it & (C - 1), j = it >> LOGC;
+            Word acc = 0;
+            for (uint32_t k = H / S; k-- > 0;) acc = md.add(md.mul_tw(acc, cf), buf[pad((j + k * S) * C + c)]);
+            const Word h = fb[pad(it)];
+            fb[pad(it)] = md.sub(md.sub(acc, h), h);
+        }
+        __syncthreads();
+        dif_forward(md, T, buf, LOGC, H, 0, H, 0);       // outputs 0 .. H-1
+        dif_forward(md, T, fb, LOGC, S, 0, R, H / S);    // outputs H .. H+R-1
+        staged_copy<8>(P.Lout * C, [&](uint32_t it) { return buf[pad(it)]; }, [&](uint32_t it, Word v) {
+            const uint32_t c = it & (C - 1), d = it >> LOGC;
+            const uint64_t idx = (c0 + c) + (uint64_t)d * W;
+            if (idx < P.n)
+                P.X[idx] = v;
+            else if (P.b && d == P.a)
+                P.V[c0 + c] = v;
+            if (share && d == P.a) zterm[c] = md.mul_tw(v, ypow[c]);
+        });
         if (share) put_share();
         return;
     }
@@ -587,13 +667,21 @@ __device__ __forceinline__ void col_inv_body(const Mod& md, const Tables<typenam
     __shared__ Word red[(kColThreads / 64) * C];
     __shared__ Word extra[C], last[C];
     Word* buf = lds_buf<Word>();
-    const Tables<Word> T = local_tables<Word, false, true>(T0, buf + padded_words(P.M << LOGC), P.M / 2);
     const uint32_t c0 = tile * C;
     const uint64_t W = 1ull << P.logW;
     const uint32_t len = phase ? P.a + 1 : P.a;
     uint32_t Mg = 1;
     while (Mg < len) Mg <<= 1;
     const bool top = P.split && len == P.M + 1;   // one coefficient above the H-point block
+    uint32_t Hs = 0, Ss = 0;
+    const bool hs = !top && len != Mg && col_split(len, &Hs, &Ss);
+    // the LDS twiddle table sits after the block this class uses (H + S words
+    // when split, else the Mg- or M-word block), inside the launch's tile
+    const uint32_t blk = top ? P.M : Mg;
+    const Tables<Word> T = hs ? local_tables<Word, false, true>(T0, buf + padded_words((Hs + Ss) << LOGC),
+                                                                P.ldstw ? Hs / 2 : 0u)
+                              : local_tables<Word, false, true>(T0, buf + padded_words(blk << LOGC),
+                                                                P.ldstw ? blk / 2 : 0u);
     const uint32_t Mb = top ? P.M : Mg;            // block inverted in LDS
     // the columns of the tile in this class; in early modes phase 0 takes
     // every column with its first a values, and the last-row inverse (and, in
@@ -674,6 +762,80 @@ __device__ __forceinline__ void col_inv_body(const Mod& md, const Tables<typenam
         }
         if (ev) {
             reduce_lanes(md, md.mul_tw(acc, sc), LOGC, red, extra);
+            put_extra();
+        }
+        return;
+    }
+    if (hs) {
+        // len = H + R values, R <= S <= H/2.  A = P mod (x^H - 1) from the
+        // first H values (a full inverse); P = A + (x^H - 1) Q with
+        // deg Q < R, and at the last R points z = w_{H+t} (z^H = -1)
+        // Q(z) = (A(z) - P(z)) / 2.  A(w_{H+t}) for t < R: A folded modulo
+        // x^S - w_{H/S} (the block of size S at global index H/S holds those
+        // points) and transformed there.  Q~(x) = Q(w_H x) takes those values
+        // at w_0 .. w_{R-1} (w_{H+t} = w_H w_t), so Q~ is the truncated
+        // inverse of length R in a block of S words, and Q_i = Q~_i w_H^-i.
+        // The full inverse leaves H A (no halvings), so the block of S words
+        // holds 2H Q~ and the coefficients are (2 H A_i - 2H Q_i) / 2H,
+        // H A_i / H and 2H Q_i / 2H.
+        const uint32_t H = Hs, S = Ss, R = len - Hs;
+        Word* fb = buf + pad(H << LOGC);   // the block of S words (H C is a multiple of 32)
+        const int lgH = __builtin_ctz(H);
+        const uint32_t maskK = (1u << T.K) - 1;
+        if (phase == 0 && P.b) eval_scales(md, LOGC, P.a, tw_fwd(md, T, P.a), zp);
+        staged_copy<8>(H * C, [&](uint32_t it) {
+            const uint32_t c = it & (C - 1), d = it >> LOGC;
+            const uint32_t col = c0 + c;
+            return mine_col(col) ? P.X[col + (uint64_t)d * W] : Word(0);
+        }, [&](uint32_t it, Word v) { buf[pad(it)] = v; });
+        __syncthreads();
+        full_inverse<Mod, false>(md, T, buf, LOGC, 0, H, 0);
+        // fold: F_j = sum_k (H A)_{j + k S} c^k, c = w_{H/S}
+        const Word cf = tw_fwd(md, T, H / S);
+        for (uint32_t it = threadIdx.x; it < (S << LOGC); it += nthreads()) {
+            const uint32_t c = it & (C - 1), j = it >> LOGC;
+            Word acc = 0;
+            for (uint32_t k = H / S; k-- > 0;) acc = md.add(md.mul_tw(acc, cf), buf[pad((j + k * S) * C + c)]);
+            fb[pad(it)] = acc;
+        }
+        lds_sync();
+        dif_forward(md, T, fb, LOGC, S, 0, R, H / S);   // H A(w_{H+t}), t < R
+        Word htw = md.one_tw();   // H in twiddle form
+        for (int i = 0; i < lgH; i++) htw = md.add(htw, htw);
+        for (uint32_t it = threadIdx.x; it < (S << LOGC); it += nthreads()) {
+            const uint32_t c = it & (C - 1), t = it >> LOGC;
+            const uint32_t col = c0 + c;
+            Word v = 0;
+            if (t < R) {
+                const Word y = mine_col(col) ? P.X[col + (uint64_t)(H + t) * W] : Word(0);
+                v = md.sub(fb[pad(it)], md.mul_tw(y, htw));   // 2H Q~(w_t)
+            }
+            fb[pad(it)] = v;
+        }
+        lds_sync();
+        if (S > 1) gitft(md, T, fb, LOGC, S, R, 0);   // 2H Q~ (coefficients R .. S-1 are 0)
+        lds_sync();
+        const Word sH = inv_pow2_tw(md, lgH), s2H = inv_pow2_tw(md, lgH + 1);
+        const uint32_t EH = __builtin_bitreverse32(H) >> (32 - T.K);   // w_H = w[K]^EH
+        for (uint32_t it = threadIdx.x; it < (H << LOGC); it += nthreads()) {
+            const uint32_t i = it >> LOGC;
+            const Word a2 = buf[pad(it)];
+            if (i < R) {
+                const Word q = md.mul_tw(fb[pad(it)], root_pow_inv(md, T, (i * EH) & maskK));   // 2H Q_i
+                buf[pad(it)] = md.mul_tw(md.sub(md.add(a2, a2), q), s2H);
+                fb[pad(it)] = md.mul_tw(q, s2H);
+            } else {
+                buf[pad(it)] = md.mul_tw(a2, sH);
+            }
+        }
+        __syncthreads();
+        staged_copy<8>(len * C, [&](uint32_t it) { return buf[pad(it)]; }, [&](uint32_t it, Word v) {
+            const uint32_t c = it & (C - 1), d = it >> LOGC;
+            const uint32_t col = c0 + c;
+            if (mine_col(col)) P.X[col + (uint64_t)d * W] = v;
+        });
+        if (phase == 0 && P.b) {
+            eval_lanes(md, buf, LOGC, P.a, tw_fwd(md, T, P.a), red, extra, zp);
             put_extra();
         }
         return;
@@ -1262,33 +1424,26 @@ __global__ __launch_bounds__(kThreads) void k_crt3(Crt3 c, const uint32_t* r1, c
 }
 
 // ---- the paper's Algorithms 1 and 2, one wavefront per instance ---------
-// The in-place TFT walks the even/odd tree of section 3 in post order with a
-// constant number of scalars (node S = (q, r): offset q, stride 2^r, length
-// ceil((n - q) / 2^r)), doing at each node either the butterflies of eq. (1)
-// over its pairs or, before descending into the odd child of an odd-length
-// node, the correction S_{m-1} += H(w_{(m-1)/2}) w_{m-1}; the ITFT walks the
-// same path backwards with the inverse steps.  Here the walk is uniform per
-// wavefront (every lane holds the same node) and the 64 lanes share each
-// node's butterflies and the correction's sum; the instance sits in the
-// wavefront's LDS slice (at most kWalkMax words), loaded and stored once.
+// Sections 3 and 4 compute the TFT and ITFT in place on the even/odd tree with
+// a constant number of scalars.  A node (q, r) is the strided subarray
+// S_i = X_{q + i 2^r} of length ceil((n - q) / 2^r); its even child is
+// (q, r + 1), its odd child (q + 2^r, r + 1), and its parent (q with bit r - 1
+// cleared, r - 1) -- the node is the odd child exactly when that bit is set --
+// so the walk keeps only the current node and how it got there (just entered,
+// back from the even child, back from the odd child).  Forward at a node of
+// length m > 1: enter the even child; back from it, if m is odd add
+// w_{m-1} H(w_{(m-1)/2}) into S_{m-1} (H: the odd child's raw coefficients as
+// a polynomial) and enter the odd child; back from the odd child, apply the
+// butterflies of eq. (1) and return.  Inverse: on entering, the inverse
+// butterflies, then the odd child; back from it, remove the correction and
+// enter the even child; back from the even child, return.  Every lane of a
+// wavefront holds the same state; the 64 lanes share each node's butterflies
+// and the correction's sum; the instance sits in the wavefront's LDS slice
+// (at most kWalkMax words), loaded and stored once.
 constexpr uint32_t kWalkMax = 1024;
 constexpr uint32_t kWalkWaves = 4;   // wavefronts (instances) per workgroup
 
-struct WalkNode {
-    uint32_t q, r;
-};
-__device__ __forceinline__ uint32_t walk_len(uint32_t n, WalkNode s) { return (n - s.q + (1u << s.r) - 1) >> s.r; }
-__device__ __forceinline__ WalkNode walk_even(WalkNode s) { return WalkNode{s.q, s.r + 1}; }
-__device__ __forceinline__ WalkNode walk_odd(WalkNode s) { return WalkNode{s.q + (1u << s.r), s.r + 1}; }
-__device__ __forceinline__ WalkNode walk_parent(WalkNode s) {
-    const uint32_t h = 1u << (s.r - 1);
-    return WalkNode{s.q < h ? s.q : s.q - h, s.r - 1};
-}
-__device__ __forceinline__ WalkNode walk_first_leaf(uint32_t n, WalkNode s) {
-    while (walk_len(n, s) > 1) s = walk_even(s);
-    return s;
-}
-__device__ __forceinline__ bool walk_same(WalkNode a, WalkNode b) { return a.q == b.q && a.r == b.r; }
+__device__ __forceinline__ uint32_t walk_len(uint32_t n, uint32_t q, uint32_t r) { return (n - q + (1u << r) - 1) >> r; }
 // orders the wavefront's LDS accesses across lanes (one wavefront, no barrier)
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1296,19 +1451,19 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// v = sum_{i <= (m-3)/2} S_{2i+1} w_{(m-1)/2}^i over the lanes (every lane gets v)
+// w_{m-1} H(w_{(m-1)/2}), H(y) = sum_{i <= (m-3)/2} S_{2i+1} y^i over the lanes (every lane gets it)
 template <class Mod>
-__device__ __forceinline__ typename Mod::Word walk_odd_sum(const Mod& md, const Tables<typename Mod::Word>& T,
-                                                          const typename Mod::Word* x, uint32_t n, WalkNode s,
-                                                          uint32_t m, uint32_t lane) {
+__device__ __forceinline__ typename Mod::Word walk_correction(const Mod& md, const Tables<typename Mod::Word>& T,
+                                                             const typename Mod::Word* x, uint32_t q, uint32_t r,
+                                                             uint32_t m, uint32_t lane) {
     using Word = typename Mod::Word;
     const uint32_t maskK = (1u << T.K) - 1;
     const uint32_t e = __builtin_bitreverse32((m - 1) >> 1) >> (32 - T.K);   // w_{(m-1)/2} = w[K]^e
     Word acc = 0;
     for (uint32_t i = lane; 2 * i + 1 < m - 1; i += 64)
-        acc = md.add(acc, md.mul_tw(x[s.q + ((2 * i + 1) << s.r)], root_pow(md, T, (i * e) & maskK)));
+        acc = md.add(acc, md.mul_tw(x[q + ((2 * i + 1) << r)], root_pow(md, T, (i * e) & maskK)));
     for (int o = 1; o < 64; o <<= 1) acc = md.add(acc, shfl_xor_word(acc, o));
-    return acc;
+    return md.mul_tw(acc, tw_fwd(md, T, m - 1));
 }
 
 template <class Mod, bool INV>
@@ -1325,71 +1480,58 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_walk(Mod md, Tables<typenam
     Word* x = slice[wv];
     for (uint32_t i = lane; i < n; i += 64) x[i] = g[i];
     wave_sync();
-    const WalkNode root{0, 0};
-    const WalkNode first = walk_first_leaf(n, root);
-    if (!INV) {
-        // Algorithm 1
-        WalkNode s = first, prev{~0u, ~0u};
-        while (true) {
-            const uint32_t m = walk_len(n, s);
-            if (m == 1 || walk_same(prev, walk_odd(s))) {
-                for (uint32_t j = lane; j < (m >> 1); j += 64) {
-                    const Word th = tw_fwd(md, T, 2 * (uint64_t)j);
-                    Word& a = x[s.q + ((2 * j) << s.r)];
-                    Word& b = x[s.q + ((2 * j + 1) << s.r)];
-                    const Word t = md.mul_tw(b, th), u = a;
-                    a = md.add(u, t);
-                    b = md.sub(u, t);
-                }
-                wave_sync();
-                if (walk_same(s, root)) break;
-                prev = s;
-                s = walk_parent(s);
-            } else {   // prev is the even child
-                if (m & 1u) {
-                    const Word v = walk_odd_sum(md, T, x, n, s, m, lane);
-                    if (lane == 0) {
-                        Word& last = x[s.q + ((m - 1) << s.r)];
-                        last = md.add(last, md.mul_tw(v, tw_fwd(md, T, m - 1)));
-                    }
-                    wave_sync();
-                }
-                prev = s;
-                s = walk_first_leaf(n, walk_odd(s));
-            }
-        }
-    } else {
-        // Algorithm 2
-        WalkNode s = root;
-        while (!walk_same(s, first)) {
-            if (walk_len(n, s) == 1) {
-                // s = parent(rp(s)): climb while s is an even child, then once more
-                while (s.r > 0 && s.q < (1u << (s.r - 1))) s = walk_parent(s);
-                s = walk_parent(s);
-                const uint32_t m = walk_len(n, s);
-                if (m & 1u) {
-                    const Word v = walk_odd_sum(md, T, x, n, s, m, lane);
-                    if (lane == 0) {
-                        Word& last = x[s.q + ((m - 1) << s.r)];
-                        last = md.sub(last, md.mul_tw(v, tw_fwd(md, T, m - 1)));
-                    }
-                    wave_sync();
-                }
-                s = walk_even(s);
-            } else {
-                const uint32_t m = walk_len(n, s);
+    enum { kEnter, kFromEven, kFromOdd };
+    uint32_t q = 0, r = 0;
+    int how = kEnter;
+    for (;;) {
+        const uint32_t m = walk_len(n, q, r), st = 1u << r;
+        if (how == kEnter && m > 1) {
+            if (INV) {
                 for (uint32_t j = lane; j < (m >> 1); j += 64) {
                     const Word th = tw_inv(md, T, 2 * (uint64_t)j);
-                    Word& a = x[s.q + ((2 * j) << s.r)];
-                    Word& b = x[s.q + ((2 * j + 1) << s.r)];
+                    Word& a = x[q + ((2 * j) << r)];
+                    Word& b = x[q + ((2 * j + 1) << r)];
                     const Word u = a, w = b;
                     a = md.half(md.add(u, w));
                     b = md.mul_tw(md.half(md.sub(u, w)), th);
                 }
                 wave_sync();
-                s = walk_odd(s);
+                q += st;   // the odd child next
             }
+            r++;           // forward: the even child next
+            continue;
         }
+        if ((!INV && how == kFromEven) || (INV && how == kFromOdd)) {
+            if (m & 1u) {
+                const Word v = walk_correction(md, T, x, q, r, m, lane);
+                if (lane == 0) {
+                    Word& last = x[q + ((m - 1) << r)];
+                    last = INV ? md.sub(last, v) : md.add(last, v);
+                }
+                wave_sync();
+            }
+            if (!INV) q += st;   // forward: the odd child next; inverse: the even child
+            r++;
+            how = kEnter;
+            continue;
+        }
+        if (!INV && how == kFromOdd) {
+            for (uint32_t j = lane; j < (m >> 1); j += 64) {
+                const Word th = tw_fwd(md, T, 2 * (uint64_t)j);
+                Word& a = x[q + ((2 * j) << r)];
+                Word& b = x[q + ((2 * j + 1) << r)];
+                const Word t = md.mul_tw(b, th), u = a;
+                a = md.add(u, t);
+                b = md.sub(u, t);
+            }
+            wave_sync();
+        }
+        // the node is finished: back to its parent
+        if (r == 0) break;
+        const uint32_t bit = 1u << (r - 1);
+        how = (q & bit) ? kFromOdd : kFromEven;
+        q &= ~bit;
+        r--;
     }
     for (uint32_t i = lane; i < n; i += 64) g[i] = x[i];
 }

@@ -29,7 +29,7 @@ _st = ctypes.c_int
 class PlanDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("logW", ctypes.c_uint), ("W", _sz), ("a", _sz), ("b", _sz),
                 ("col_block", _sz), ("cols_per_tile", ctypes.c_uint), ("lds_bytes_col", _sz),
-                ("lds_bytes_row", _sz)]
+                ("lds_bytes_row", _sz), ("row_threads", ctypes.c_uint), ("stages_per_pass", ctypes.c_uint)]
 
 
 class _Calibration(ctypes.Structure):
@@ -50,6 +50,8 @@ SIGNATURES = {
     "poly_mul_noalloc": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp]),
     "tft_padded_forward": (_st, [_vp, _vp, _sz, _vp, _vp]),
     "tft_padded_inverse": (_st, [_vp, _vp, _sz, _vp, _vp]),
+    "tft_buffered_forward": (_st, [_vp, _vp, _sz, _vp]),
+    "tft_buffered_inverse": (_st, [_vp, _vp, _sz, _vp]),
     "poly_mul_padded": (_st, [_vp, _vp, _sz, _vp, _sz, _vp, _vp, _vp, _vp]),
     "tft_plan_info": (_st, [_vp, _sz, _vp]),
     "tft_set_plan_override": (_st, [_vp, ctypes.c_uint]),
@@ -70,6 +72,7 @@ SIGNATURES = {
     "tft_queue_destroy": (None, [_vp]),
     "tft_calibrate": (_st, [_vp, ctypes.POINTER(_Calibration)]),
     "tft_autotune": (_st, [_vp, _sz, ctypes.POINTER(PlanDesc)]),
+    "tft_autotune_batch": (_st, [_vp, _vp, _sz, ctypes.c_int, ctypes.POINTER(ctypes.c_uint)]),
     "tft_plan_cache_get": (_st, [_vp, ctypes.c_uint, ctypes.POINTER(ctypes.c_uint)]),
     "tft_plan_cache_set": (_st, [_vp, ctypes.c_uint, ctypes.c_uint]),
     "tft_plan_bucket": (ctypes.c_uint, [_sz]),
@@ -238,6 +241,23 @@ def tft_padded_inverse(ctx: Context, X, Xpad, n: int | None = None, stream=None)
     return X
 
 
+def tft_buffered_forward(ctx: Context, Xbuf, n: int, stream=None):
+    """Van der Hoeven-style buffered TFT (comparator): Xbuf holds 2^ceil(lg n)
+    words, the first n of them the input and, on return, the transform."""
+    if Xbuf.numel() < (1 << (n - 1).bit_length()):
+        raise ValueError("Xbuf needs 2^ceil(lg n) words")
+    _check(load().tft_buffered_forward(ctx.handle, ctx._t(Xbuf, "Xbuf"), n, _stream(stream)), "tft_buffered_forward")
+    return Xbuf
+
+
+def tft_buffered_inverse(ctx: Context, Xbuf, n: int, stream=None):
+    """Inverse of tft_buffered_forward in the same 2^ceil(lg n)-word buffer."""
+    if Xbuf.numel() < (1 << (n - 1).bit_length()):
+        raise ValueError("Xbuf needs 2^ceil(lg n) words")
+    _check(load().tft_buffered_inverse(ctx.handle, ctx._t(Xbuf, "Xbuf"), n, _stream(stream)), "tft_buffered_inverse")
+    return Xbuf
+
+
 def poly_mul_padded(ctx: Context, A, B, X, Apad, Bpad, stream=None):
     _check(load().poly_mul_padded(ctx.handle, ctx._t(A, "A"), A.numel(), ctx._t(B, "B"), B.numel(),
                                   ctx._t(X, "X"), ctx._t(Apad, "Apad"), ctx._t(Bpad, "Bpad"), _stream(stream)),
@@ -252,15 +272,28 @@ def tft_plan_info(ctx: Context, n: int) -> dict:
 
 
 def tft_autotune(ctx: Context, n: int) -> dict:
-    """Time the candidate row widths W = 2^logW for length n (the planner's
-    choice and its neighbours) and cache the fastest for every length in the
-    same quarter octave (tft_plan_bucket); returns the resulting plan."""
+    """Time candidate plans for length n (column width W = 2^logW near the
+    planner's choice, then columns per tile, threads per row and stages per
+    LDS round trip) and cache the fastest for every length in the same
+    quarter octave (tft_plan_bucket); returns the resulting plan."""
     d = PlanDesc()
     _check(load().tft_autotune(ctx.handle, n, ctypes.byref(d)), "tft_autotune")
     return {f: getattr(d, f) for f, _ in PlanDesc._fields_}
 
 
+def tft_autotune_batch(ctx: Context, jobs, products=True) -> int:
+    """Time the batch of jobs (as Batch would run it) with the two-pass rows at
+    the balanced split, one step wider and two steps wider, keep the fastest
+    for the context's later batches, and return it (0..2).  Runs the batch."""
+    arr = _descs(ctx, jobs, products)
+    w = ctypes.c_uint()
+    _check(load().tft_autotune_batch(ctx.handle, arr, len(jobs), 1 if products else 0, ctypes.byref(w)),
+           "tft_autotune_batch")
+    return int(w.value)
+
+
 def tft_plan_cache_get(ctx: Context, bucket: int) -> int:
+    """The plan code cached for a bucket (0: the planner's choice)."""
     v = ctypes.c_uint()
     _check(load().tft_plan_cache_get(ctx.handle, bucket, ctypes.byref(v)), "tft_plan_cache_get")
     return int(v.value)
@@ -276,7 +309,7 @@ def tft_plan_bucket(n: int) -> int:
 
 
 def plan_cache_dump(ctx: Context) -> dict:
-    """The context's tuned plans as {bucket: logW} (JSON-ready)."""
+    """The context's tuned plans as {bucket: plan code} (JSON-ready)."""
     out = {}
     for k in range(0, 4 * 28 + 4):
         v = tft_plan_cache_get(ctx, k)

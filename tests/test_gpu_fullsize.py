@@ -120,6 +120,20 @@ def test_batch_4096_every_instance():
         got = jobs[i][2].cpu().numpy().astype(np.uint64)
         assert (got == ref).all(), f"instance {i}: {len(host[i][0])} x {len(host[i][1])}"
     b.close()
+    # the batch tuner's choice of row width (it runs the batch itself), then a
+    # fresh batch planned with it: every instance again
+    widen = libtft.tft_autotune_batch(ctx, jobs)
+    print(f"[gpu] batch tuner chose rows {widen} steps wider than balanced", flush=True)
+    assert widen in (0, 1, 2)
+    for _, _, X, _ in jobs:
+        X.zero_()
+    b = libtft.Batch(ctx, jobs)
+    b.run()
+    torch.cuda.synchronize()
+    for i, ref in enumerate(refs):
+        got = jobs[i][2].cpu().numpy().astype(np.uint64)
+        assert (got == ref).all(), f"tuned batch, instance {i}"
+    b.close()
     ctx.close()
 
 

@@ -87,6 +87,31 @@ def test_two_pass_forced_small(ctxs, name, logW):
 
 
 @pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("logW", [8, 9, 10])
+def test_two_pass_general_b_tiles(ctxs, name, logW):
+    # general last rows with more than 128 columns c < b, so the columns run
+    # as tiles (not one per workgroup) beside the last row's inverse; a + 1 is
+    # not a power of two (the rank-one completion) or is (two column phases)
+    p, g = PRIMES[name]
+    ctx = ctxs[name]
+    libtft.tft_set_plan_override(ctx, logW)
+    try:
+        W = 1 << logW
+        # a in (H, 1.25 H] for a power of two H >= 64: the column inverse splits
+        # at H (70, 140, 270, 300, 520); b = 0 and 1 as well
+        ns = [a * W + b for a in (5, 17, 70, 100, 140, 270, 300, 511, 520) for b in (0, 1, 129, W // 2 + 3, W - 5)]
+        if logW == 8:
+            # a = 1116 splits at 1024: tiles of more than 76 KiB with the
+            # twiddle copy, so the planner leaves the copy out
+            ns += [1116 * W + b for b in (0, 1, 129, 200)]
+        for n in ns:
+            print(f"[gpu] {name} logW={logW} n={n}", flush=True)
+            check_roundtrip(ctx, p, g, n, seed=n + 7 * logW)
+    finally:
+        libtft.tft_set_plan_override(ctx, 0)
+
+
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
 def test_two_pass_planner_sizes(ctxs, name):
     p, g = PRIMES[name]
     ctx = ctxs[name]
@@ -151,3 +176,24 @@ def test_rejects_bad_arguments(ctxs):
     assert e.value.status == libtft.TFT_ERANGE
     with pytest.raises(libtft.TftError):
         libtft.Context(998244353, 4)                   # 4 is a square: not a generator
+
+
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+def test_buffered_comparator(ctxs, name):
+    # van der Hoeven-style buffered transforms (2^ceil(lg n)-word buffer): the
+    # same outputs as the oracle, the inverse restores the input, for every
+    # kind of last row and the single-workgroup sizes
+    import torch
+    p, g = PRIMES[name]
+    ctx = ctxs[name]
+    for n in [1, 7, 1000, 2499, 8193, 100003, 65537, 3 * 4096 + 5, (1 << 17) - 1, 40000, 262145, 300000]:
+        F = synth.residues(p, n, 4 * n + 1)
+        L = 1 << (n - 1).bit_length()
+        buf = torch.full((L,), 3, dtype=ctx.dtype, device="cuda")
+        buf[:n] = torch.from_numpy(F.astype(np.uint32 if ctx.word_bytes == 4 else np.uint64)).cuda()
+        print(f"[gpu] buffered {name} n={n}", flush=True)
+        libtft.tft_buffered_forward(ctx, buf, n)
+        got = buf[:n].cpu().numpy().astype(np.uint64)
+        assert (got == oracle.fft_padded(p, g, F)).all(), n
+        libtft.tft_buffered_inverse(ctx, buf, n)
+        assert (buf[:n].cpu().numpy().astype(np.uint64) == F).all(), n

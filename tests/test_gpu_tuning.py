@@ -41,10 +41,12 @@ def test_autotune_then_parity(name):
         print(f"[gpu] autotune {name} n={n}", flush=True)
         plan = libtft.tft_autotune(ctx, n)
         assert plan["kind"] == 1
-        assert libtft.tft_plan_cache_get(ctx, bk) == plan["logW"]
-        assert libtft.plan_cache_dump(ctx) == {bk: plan["logW"]}
-        for m in (n, 97000, 110000):    # every length of the bucket uses the tuned width
+        code = libtft.tft_plan_cache_get(ctx, bk)
+        assert code & 31 == plan["logW"]
+        assert libtft.plan_cache_dump(ctx) == {bk: code}
+        for m in (n, 97000, 110000):    # every length of the bucket uses the tuned plan
             assert libtft.tft_plan_info(ctx, m)["logW"] == plan["logW"]
+            assert libtft.tft_plan_info(ctx, m)["cols_per_tile"] == plan["cols_per_tile"]
             F = synth.residues(p, m, 77 + m)
             X = torch.from_numpy(F.astype(dt)).cuda()
             libtft.tft_forward(ctx, X)
@@ -58,8 +60,55 @@ def test_autotune_then_parity(name):
         # a cache entry can be set by hand and cleared
         libtft.tft_plan_cache_set(ctx, bk, 0)
         assert libtft.plan_cache_dump(ctx) == {}
-        libtft.plan_cache_load(ctx, {bk: plan["logW"]})
-        assert libtft.tft_plan_cache_get(ctx, bk) == plan["logW"]
+        libtft.plan_cache_load(ctx, {bk: code})
+        assert libtft.tft_plan_cache_get(ctx, bk) == code
+    finally:
+        ctx.close()
+
+
+def plan_code(logW, logC=0, rlog=0, smax=0):
+    return logW | (logC << 5) | (rlog << 8) | (smax << 11)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+def test_every_plan_knob_is_exact(name):
+    """Each knob the autotuner can set -- columns per tile 8 or 16, one or two
+    radix-8 units per row thread, 1, 2 or 3 stages per LDS round trip -- with
+    the product and both transforms against the oracle, at lengths with
+    b = 0, a general last row, b = W - 1 and a split column."""
+    p, g = PRIMES[name]
+    ctx = libtft.Context(p, g, 0)
+    dt = np.uint32 if ctx.word_bytes == 4 else np.uint64
+    codes = [plan_code(7, 3, 3, 3), plan_code(7, 4, 3, 3), plan_code(8, 0, 4, 0), plan_code(7, 0, 0, 2),
+             plan_code(8, 4, 4, 1), plan_code(9, 3, 4, 2)]
+    try:
+        for code in codes:
+            W = 1 << (code & 31)
+            for n in (129 * W, 150 * W + 37, 256 * W - 1, 256 * W + W // 2):
+                bk = libtft.tft_plan_bucket(n)
+                libtft.tft_plan_cache_set(ctx, bk, code)
+                plan = libtft.tft_plan_info(ctx, n)
+                print(f"[gpu] {name} code={code:#x} n={n} plan={plan}", flush=True)
+                assert plan["logW"] == code & 31
+                F = synth.residues(p, n, n + code)
+                X = torch.from_numpy(F.astype(dt)).cuda()
+                libtft.tft_forward(ctx, X)
+                torch.cuda.synchronize()
+                assert (X.cpu().numpy().astype(np.uint64) == oracle.fft_padded(p, g, F)).all(), (code, n)
+                libtft.tft_inverse(ctx, X)
+                torch.cuda.synchronize()
+                assert (X.cpu().numpy().astype(np.uint64) == F).all(), (code, n)
+                la = n // 2 + 1
+                A, B = synth.residues(p, la, 3 * n), synth.residues(p, n + 1 - la, 3 * n + 1)
+                dA = torch.from_numpy(A.astype(dt)).cuda()
+                dB = torch.from_numpy(B.astype(dt)).cuda()
+                Xc = torch.empty(n, dtype=ctx.dtype, device="cuda")
+                Yc = torch.empty(n, dtype=ctx.dtype, device="cuda")
+                libtft.poly_mul(ctx, dA, dB, Xc, Yc)
+                torch.cuda.synchronize()
+                assert (Xc.cpu().numpy().astype(np.uint64) == oracle.mul_padded(p, g, A, B)).all(), (code, n)
+                libtft.tft_plan_cache_set(ctx, bk, 0)
     finally:
         ctx.close()
 
