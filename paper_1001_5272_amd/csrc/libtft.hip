@@ -105,6 +105,7 @@ struct Plan {
     unsigned rlog;       // words per row thread 2^rlog (one or two radix-8 units)
     unsigned smax;       // most stages per LDS round trip
     unsigned ldstw;      // column tiles copy their twiddles to LDS (1) or read them from memory (0)
+    unsigned hs;         // column transforms may split at a power of two (single transforms; not batches)
     size_t lds_col, lds_row;
 };
 
@@ -234,14 +235,19 @@ unsigned plan_bucket(uint64_t n) {
 // the column kernels' registers already bound.
 constexpr int col_log_width(unsigned w) { return w == 4 ? 4 : 3; }
 
-// Column-tile kernels by tile width (2^3 or 2^4 columns).
+// Column-tile kernels by tile width (2^3 or 2^4 columns) and by whether the
+// columns of the launch split at a power of two (tft::col_split): the split
+// is a separate instantiation so that the other launches keep the registers
+// (and occupancy) of the plain column transform.
 template <class Mod>
-auto col_fwd_kernel(int logC) {
-    return logC == 3 ? tft::k_col_fwd<Mod, 3> : tft::k_col_fwd<Mod, 4>;
+auto col_fwd_kernel(int logC, bool hs) {
+    if (hs) return logC == 3 ? tft::k_col_fwd<Mod, 3, true> : tft::k_col_fwd<Mod, 4, true>;
+    return logC == 3 ? tft::k_col_fwd<Mod, 3, false> : tft::k_col_fwd<Mod, 4, false>;
 }
 template <class Mod>
-auto col_inv_kernel(int logC) {
-    return logC == 3 ? tft::k_col_inv<Mod, 3> : tft::k_col_inv<Mod, 4>;
+auto col_inv_kernel(int logC, bool hs) {
+    if (hs) return logC == 3 ? tft::k_col_inv<Mod, 3, true> : tft::k_col_inv<Mod, 4, true>;
+    return logC == 3 ? tft::k_col_inv<Mod, 3, false> : tft::k_col_inv<Mod, 4, false>;
 }
 template <class Mod>
 auto col_fwd_list_kernel(int logC) {
@@ -262,20 +268,32 @@ auto col_inv_list_kernel(int logC) {
 // len values split at H when tft::col_split allows (H + S words per column),
 // else use the power-of-two block (the forward P.M; the inverse 2^ceil(lg len),
 // or P.M for the split mode's long class).
+// The forward's columns (Lout values) split at a power of two; the kernels
+// take the same decision (col_fwd_body, with the split instantiation).
+bool fwd_splits(const Plan& P, uint32_t* H, uint32_t* S) {
+    return P.hs && !P.split && P.Lout != P.M && tft::col_split(P.Lout, H, S);
+}
+// The inverse's class of len values splits at a power of two (col_inv_body).
+bool inv_splits(const Plan& P, uint32_t len, uint32_t* H, uint32_t* S) {
+    const bool top = P.split && len == P.M + 1;
+    return P.hs && !top && len != pow2ceil(len) && tft::col_split(len, H, S);
+}
+bool inv_splits(const Plan& P, uint32_t len) {
+    uint32_t H, S;
+    return inv_splits(P, len, &H, &S);
+}
+
 size_t col_tile_lds(const Plan& P, uint32_t len, bool fwd, unsigned w) {
     uint32_t H = 0, S = 0;
     uint32_t blk;
     const uint32_t tw = P.ldstw ? 1u : 0u;
+    if (fwd ? fwd_splits(P, &H, &S) : inv_splits(P, len, &H, &S))
+        return ((size_t)tft::padded_words((H + S) << P.logC) + tw * (H / 2)) * w;
     if (fwd) {
-        if (!P.split && P.Lout != P.M && tft::col_split(P.Lout, &H, &S))
-            return ((size_t)tft::padded_words((H + S) << P.logC) + tw * (H / 2)) * w;
         blk = P.M;
     } else {
-        const uint32_t Mg = (uint32_t)pow2ceil(len);
         const bool top = P.split && len == P.M + 1;
-        if (!top && len != Mg && tft::col_split(len, &H, &S))
-            return ((size_t)tft::padded_words((H + S) << P.logC) + tw * (H / 2)) * w;
-        blk = top ? P.M : Mg;
+        blk = top ? P.M : (uint32_t)pow2ceil(len);
     }
     return ((size_t)tft::padded_words(blk << P.logC) + tw * (blk / 2)) * w;
 }
@@ -296,6 +314,7 @@ Plan make_plan(const tft_ctx* ctx, uint64_t n, bool wide = false) {
                                     : (tl_ignore_cache ? 0u : ctx->override_logW.load(std::memory_order_relaxed));
     P.smax = 3;
     P.rlog = 3;
+    P.hs = wide ? 0 : 1;
     if (log2u(n) <= small_max_log2(w) && !(ovr && (1ull << ovr) < n)) {
         P.kind = 0;
         P.M = (uint32_t)pow2ceil(n);
@@ -409,6 +428,8 @@ bool set_lds_limits() {
         (const void*)tft::k_small_mul<Mod>,       (const void*)tft::k_small_list<Mod>,
         (const void*)tft::k_col_fwd<Mod, 3>,      (const void*)tft::k_col_fwd<Mod, 4>,
         (const void*)tft::k_col_inv<Mod, 3>,      (const void*)tft::k_col_inv<Mod, 4>,
+        (const void*)tft::k_col_fwd<Mod, 3, true>, (const void*)tft::k_col_fwd<Mod, 4, true>,
+        (const void*)tft::k_col_inv<Mod, 3, true>, (const void*)tft::k_col_inv<Mod, 4, true>,
         (const void*)tft::k_col_inv<Mod, 0>,
         (const void*)tft::k_row_fwd<Mod>,         (const void*)tft::k_row_inv<Mod>,
         (const void*)tft::k_last_inv<Mod>,        (const void*)tft::k_tail_inv<Mod>,
@@ -489,8 +510,10 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
     // (scratch after V), and the row pass needs no workgroup for that row
     G.Q = V + kVWords;
     if (P.b == 1) G.nparts = tiles;
-    launch(ctx, TFT_K_COL_FWD, col_fwd_kernel<Mod>(P.logC), dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T, G,
-           tiles);
+    uint32_t Hs, Ss;
+    const bool hs = g0 == 0 && fwd_splits(P, &Hs, &Ss);
+    launch(ctx, TFT_K_COL_FWD, col_fwd_kernel<Mod>(P.logC, hs), dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T,
+           G, tiles);
     launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b > 1 ? 1 : 0))), dim3(row_threads(P)), P.lds_row,
            st, md, T, G);
     return launch_status();
@@ -535,14 +558,14 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     const uint32_t nrows = one_short ? (uint32_t)P.a + 1 : tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
     launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows + (G.early == 2 ? 1u : 0u)), dim3(row_threads(P)),
            P.lds_row, st, md, T, G, ctx->p);
-    auto kern = col_inv_kernel<Mod>(P.logC);
+    auto kern = [&](uint32_t len) { return col_inv_kernel<Mod>(P.logC, inv_splits(P, len)); };
     // LDS of a column tile inverting len values (as the kernel lays it out)
     auto col_lds = [&](uint32_t len) -> size_t { return col_tile_lds(P, len, false, ctx->wbytes); };
     if (one_short) {
         launch(ctx, TFT_K_LAST_INV, tft::k_tail_inv<Mod>, dim3(1), dim3(tft::kLastThreads), lds_tail, st, md, T, G);
         const uint32_t nt = (uint32_t)((P.b + C - 1) / C);   // columns c < b, in full
-        launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(col_threads(P)), col_lds((uint32_t)P.a + 1), st, md, T,
-               G, 1, 0u, nt);
+        launch(ctx, TFT_K_COL_INV_LONG, kern((uint32_t)P.a + 1), dim3(nt), dim3(col_threads(P)),
+               col_lds((uint32_t)P.a + 1), st, md, T, G, 1, 0u, nt);
         return launch_status();
     }
     // A class with only a few columns runs one column per workgroup, so that a
@@ -557,8 +580,8 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
         } else {
             const uint32_t nt = tiles_all - t0;
             if (P.b == 1 && t0 == 0) G.nparts = nt;   // every tile leaves its share of the last-row sum
-            launch(ctx, TFT_K_COL_INV_SHORT, kern, dim3(nt), dim3(col_threads(P)), col_lds((uint32_t)P.a), st, md, T, G,
-                   0, t0, nt);
+            launch(ctx, TFT_K_COL_INV_SHORT, kern((uint32_t)P.a), dim3(nt), dim3(col_threads(P)), col_lds((uint32_t)P.a),
+                   st, md, T, G, 0, t0, nt);
         }
     }
     if (P.b) {
@@ -573,8 +596,8 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
                        lds_one, st, md, T, G, 1, 0u, (uint32_t)P.b);
             } else {
                 const uint32_t nt = (uint32_t)((P.b + C - 1) / C);
-                launch(ctx, TFT_K_COL_INV_LONG, kern, dim3(nt), dim3(col_threads(P)), col_lds((uint32_t)P.a + 1), st, md,
-                       T, G, 1, 0u, nt);
+                launch(ctx, TFT_K_COL_INV_LONG, kern((uint32_t)P.a + 1), dim3(nt), dim3(col_threads(P)),
+                       col_lds((uint32_t)P.a + 1), st, md, T, G, 1, 0u, nt);
             }
         }
     }

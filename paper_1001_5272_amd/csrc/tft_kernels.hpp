@@ -183,7 +183,7 @@ __host__ __device__ inline bool col_split(uint32_t len, uint32_t* H, uint32_t* S
 // evaluates each column polynomial at w_0..w_{Lout-1} (Lout = a + (b > 0)) in
 // an LDS block of M = 2^ceil(lg Lout) words per column, writes the outputs
 // that have a slot and the extra value P_c(w_a) of columns c >= b to V[c].
-template <class Mod, int LOGC>
+template <class Mod, int LOGC, bool HS = false>
 __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typename Mod::Word>& T0,
                              const TwoPass<typename Mod::Word>& P, uint32_t tile) {
     using Word = typename Mod::Word;
@@ -192,7 +192,7 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
     __shared__ Word extra[C], hi0[C];
     Word* buf = lds_buf<Word>();
     uint32_t Hs = 0, Ss = 0;
-    const bool hs = !P.split && P.g0 == 0 && P.Lout != P.M && col_split(P.Lout, &Hs, &Ss);
+    const bool hs = HS && !P.split && P.g0 == 0 && P.Lout != P.M && col_split(P.Lout, &Hs, &Ss);
     const Tables<Word> T = hs ? local_tables<Word, true, false>(T0, buf + padded_words((Hs + Ss) << LOGC),
                                                                 P.ldstw ? Hs / 2 : 0u)
                               : local_tables<Word, true, false>(T0, buf + padded_words(P.M << LOGC),
@@ -310,8 +310,8 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
         if (share) put_share();
         return;
     }
-    if (hs) {
-        // Lout = H + R outputs, R <= S <= H/2, and every column has at most
+    if constexpr (HS) if (hs) {
+        // Lout = H + R outputs, R <= S <= H/4, and every column has at most
         // Lout coefficients: P = lo + x^H hi (hi: R coefficients at most).
         // Outputs s < H are the block-0 transform of A = P mod (x^H - 1)
         // = lo + hi; outputs H .. H + R - 1 lie in the block of size S at
@@ -659,7 +659,7 @@ __host__ __device__ inline uint32_t row_inv_items(uint32_t W, uint32_t a, uint32
 // c >= b (length a) and, when b > 0, re-evaluates V_c = P_c(w_a) from the
 // restored coefficients; phase 1 handles c < b (length a + 1).  Columns of the
 // other class inside the tile are skipped.
-template <class Mod, int LOGC>
+template <class Mod, int LOGC, bool HS = false>
 __device__ __forceinline__ void col_inv_body(const Mod& md, const Tables<typename Mod::Word>& T0,
                              const TwoPass<typename Mod::Word>& P, int phase, uint32_t tile) {
     using Word = typename Mod::Word;
@@ -674,7 +674,7 @@ __device__ __forceinline__ void col_inv_body(const Mod& md, const Tables<typenam
     while (Mg < len) Mg <<= 1;
     const bool top = P.split && len == P.M + 1;   // one coefficient above the H-point block
     uint32_t Hs = 0, Ss = 0;
-    const bool hs = !top && len != Mg && col_split(len, &Hs, &Ss);
+    const bool hs = HS && !top && len != Mg && col_split(len, &Hs, &Ss);
     // the LDS twiddle table sits after the block this class uses (H + S words
     // when split, else the Mg- or M-word block), inside the launch's tile
     const uint32_t blk = top ? P.M : Mg;
@@ -766,8 +766,8 @@ __device__ __forceinline__ void col_inv_body(const Mod& md, const Tables<typenam
         }
         return;
     }
-    if (hs) {
-        // len = H + R values, R <= S <= H/2.  A = P mod (x^H - 1) from the
+    if constexpr (HS) if (hs) {
+        // len = H + R values, R <= S <= H/4.  A = P mod (x^H - 1) from the
         // first H values (a full inverse); P = A + (x^H - 1) Q with
         // deg Q < R, and at the last R points z = w_{H+t} (z^H = -1)
         // Q(z) = (A(z) - P(z)) / 2.  A(w_{H+t}) for t < R: A folded modulo
@@ -1103,10 +1103,12 @@ __device__ __forceinline__ void col_poly_body(const Mod& md, const Tables<typena
 }
 
 // ---- single transform: one launch per pass, geometry by value
-template <class Mod, int LOGC>
+// HS: the column transforms of the launch split at a power of two (col_split);
+// a separate instantiation, so that the others keep their register budget
+template <class Mod, int LOGC, bool HS = false>
 __global__ __launch_bounds__(kColThreads) void k_col_fwd(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P, uint32_t tiles) {
-    col_fwd_body<Mod, LOGC>(md, T, P, xcd_remap(blockIdx.x, tiles));
+    col_fwd_body<Mod, LOGC, HS>(md, T, P, xcd_remap(blockIdx.x, tiles));
 }
 template <class Mod>
 __global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_row_fwd(Mod md, Tables<typename Mod::Word> T,
@@ -1155,11 +1157,11 @@ __global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))
     const uint32_t np = __builtin_popcount(P.b);   // the pieces of [0, b): one per set bit
     row_inv_body(md, T, P, r < np ? P.a + r : r - np);
 }
-template <class Mod, int LOGC>
+template <class Mod, int LOGC, bool HS = false>
 __global__ __launch_bounds__(kColThreads) void k_col_inv(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P, int phase, uint32_t tile0,
                                                       uint32_t tiles) {
-    col_inv_body<Mod, LOGC>(md, T, P, phase, tile0 + xcd_remap(blockIdx.x, tiles));
+    col_inv_body<Mod, LOGC, HS>(md, T, P, phase, tile0 + xcd_remap(blockIdx.x, tiles));
 }
 template <class Mod>
 __global__ __launch_bounds__(kLastThreads) void k_last_inv(Mod md, Tables<typename Mod::Word> T,
