@@ -45,6 +45,9 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # product as four 32 x 32 + 64 multiply-adds, folding with 2^64 = 2^32 - 1 and
 # 2^96 = -1, modular add and subtract), register moves not counted
 OPS_PER_BUTTERFLY = 33
+# the timed steps bracket the dominant kernel with HIP events in every
+# TIMING_EVERY-th step (the first, the sixth, ...)
+TIMING_EVERY = 5
 ROW_KERNELS = ("row_fwd", "row_inv")
 COL_KERNELS = ("col_fwd", "col_inv_short", "col_inv_long")
 
@@ -167,10 +170,11 @@ def main():
             libtft.tft_inverse(ctx, bufs[n])
 
     # The last warm-up step times every launch (HIP events around each): its
-    # kernel table and the dominant kernel.  The timed steps bracket only the
-    # dominant kernel's launches (each bracketed launch adds two event records
-    # to the stream, a few microseconds each), so the step time is measured
-    # with the few events the roofline needs.
+    # kernel table and the dominant kernel.  Inside the timed region only the
+    # dominant kernel's launches are bracketed, and only in every
+    # TIMING_EVERY-th step: each bracketed launch adds two event records to the
+    # stream, about 5 us of idle device each, so the step time carries a
+    # fifth of the events the roofline needs.
     wstats = None
     for i in range(args.warmup):
         if i == args.warmup - 1:
@@ -184,10 +188,12 @@ def main():
         wstats = libtft.tft_timing_read(ctx)
         libtft.tft_timing_select(ctx, [max(wstats.items(), key=lambda kv: kv[1][1])[0]])
     libtft.tft_timing_reset(ctx)
-    libtft.tft_timing_enable(ctx, True)
+    libtft.tft_timing_enable(ctx, False)
+    bracketed = [i for i in range(args.steps) if i % TIMING_EVERY == 0]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        libtft.tft_timing_enable(ctx, i % TIMING_EVERY == 0)
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -208,7 +214,7 @@ def main():
     dom = max(kstats.items(), key=lambda kv: kv[1][1])
     dname, (dcount, dms) = dom
     avg_ms = dms / dcount
-    launches_per_step = dcount / args.steps
+    launches_per_step = dcount / len(bracketed)
     plans = {n: libtft.tft_plan_info(ctx, n) for n in SWEEP}
     # Algorithmic work of one launch: the butterflies of the pass it runs
     # (the nominal count split between the passes by their tree depth) and
@@ -223,7 +229,7 @@ def main():
         "kernel": dname, "bound": "alu", "achieved": round(alu_achieved, 2), "peak": round(VALU_PEAK_TOPS, 1),
         "unit": "Tops/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4), "traffic": None,
         "ops_per_butterfly": OPS_PER_BUTTERFLY, "butterflies_per_launch": int(bf_launch),
-        "avg_launch_us": round(avg_ms * 1e3, 2), "launches": dcount,
+        "avg_launch_us": round(avg_ms * 1e3, 2), "launches": dcount, "bracketed_steps": len(bracketed),
         "hbm": {"achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(hbm_bytes)},
         # the whole TFT+ITFT step: algorithmic bytes (each of the n words read

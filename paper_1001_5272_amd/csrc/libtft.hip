@@ -60,6 +60,16 @@ constexpr size_t kVWords = size_t(1) << 16;          // V_c area: one word per c
 // V_c area, then the column polynomial Q of the general last-row step (two
 // buffers of kQStride words and 1 / Q(w_a))
 constexpr size_t kScratchWords = kVWords + 2 * size_t(tft::kQStride) + 64;
+// the space-restricted product's fold partials: two areas of kFoldItems words
+// (about that many threads per operand read it at once), then kFoldSpare words
+// for sums of spans
+constexpr size_t kFoldItems = size_t(1) << 18;
+constexpr size_t kFoldSpare = size_t(1) << 10;
+// the restricted product's last positions (fewer than 2^(kRestrLog + 1)) come
+// from node folds of at most 2^kRestrLog words, four of them (two nodes, two
+// operands) after the partials in the fold area
+constexpr unsigned kRestrLog = 17;
+constexpr size_t kFoldWords = 2 * kFoldItems + kFoldSpare + (size_t(4) << kRestrLog);
 constexpr size_t kLdsSoft = 76 * 1024;          // preferred LDS per workgroup (two per CU)
 constexpr size_t kLdsHard = 160 * 1024;         // gfx950 LDS per workgroup
 constexpr size_t kLdsDynMax = 144 * 1024;       // dynamic LDS any launch may request
@@ -154,6 +164,7 @@ struct tft_ctx {
     void* tables;        // f1 | f2 | i1 | i2
     size_t n1, n2;       // entries per level
     void* varea;         // V_c area and column polynomial (kScratchWords words)
+    void* fold;          // the space-restricted product's fold partials and node folds (kFoldWords words)
     // measurement mode (tft_timing_*): events bracketing each launch of the
     // kernels selected in timing_mask (bit = tft_kernel_id)
     std::atomic<bool> timing;
@@ -426,12 +437,14 @@ bool set_lds_limits() {
     const void* ks[] = {
         (const void*)tft::k_small_fwd<Mod>,       (const void*)tft::k_small_inv<Mod>,
         (const void*)tft::k_small_mul<Mod>,       (const void*)tft::k_small_list<Mod>,
+        (const void*)tft::k_restr_tail<Mod>,
         (const void*)tft::k_col_fwd<Mod, 3>,      (const void*)tft::k_col_fwd<Mod, 4>,
         (const void*)tft::k_col_inv<Mod, 3>,      (const void*)tft::k_col_inv<Mod, 4>,
         (const void*)tft::k_col_fwd<Mod, 3, true>, (const void*)tft::k_col_fwd<Mod, 4, true>,
         (const void*)tft::k_col_inv<Mod, 3, true>, (const void*)tft::k_col_inv<Mod, 4, true>,
         (const void*)tft::k_col_inv<Mod, 0>,
         (const void*)tft::k_row_fwd<Mod>,         (const void*)tft::k_row_inv<Mod>,
+        (const void*)tft::k_row_fwd_mul<Mod>,
         (const void*)tft::k_last_inv<Mod>,        (const void*)tft::k_tail_inv<Mod>,
         (const void*)tft::k_col_fwd_list<Mod, 3>,
         (const void*)tft::k_col_fwd_list<Mod, 4>, (const void*)tft::k_col_inv_list<Mod, 3>,
@@ -476,6 +489,7 @@ tft::TwoPass<Word> two_pass_of(const Plan& P, Word* X, const Word* src, uint64_t
     G.g0 = 0;
     G.nparts = 0;
     G.ldstw = P.ldstw;
+    G.inst = 0;
     return G;
 }
 
@@ -501,10 +515,12 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
                P.lds_row + (size_t)P.M * ctx->wbytes, st, md, T, X, (uint32_t)n, P.M, g0, (uint64_t)n);
         return launch_status();
     }
-    if (g0 && P.b) return TFT_EINVAL;   // a block at g0 != 0 is a whole power-of-two block
+    // a block at g0 != 0, and each of several instances, is a whole power-of-two block
+    if ((g0 || copies > 1) && P.b) return TFT_EINVAL;
     Word* V = reinterpret_cast<Word*>(ctx->varea);
     auto G = two_pass_of<Word>(P, X, src, n_src, nullptr, buffered ? X + P.a * P.W : V);
     G.g0 = g0;
+    G.inst = n;   // copies > 1: instance y at X + y n (src + y n), at the same block index
     const uint32_t tiles = (uint32_t)(P.W >> P.logC);
     // b = 1: the column tiles leave shares of the last row's one output
     // (scratch after V), and the row pass needs no workgroup for that row
@@ -512,10 +528,10 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
     if (P.b == 1) G.nparts = tiles;
     uint32_t Hs, Ss;
     const bool hs = g0 == 0 && fwd_splits(P, &Hs, &Ss);
-    launch(ctx, TFT_K_COL_FWD, col_fwd_kernel<Mod>(P.logC, hs), dim3(tiles), dim3(col_threads(P)), P.lds_col, st, md, T,
-           G, tiles);
-    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b > 1 ? 1 : 0))), dim3(row_threads(P)), P.lds_row,
-           st, md, T, G);
+    launch(ctx, TFT_K_COL_FWD, col_fwd_kernel<Mod>(P.logC, hs), dim3(tiles, copies), dim3(col_threads(P)), P.lds_col, st,
+           md, T, G, tiles);
+    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b > 1 ? 1 : 0)), copies), dim3(row_threads(P)),
+           P.lds_row, st, md, T, G);
     return launch_status();
 }
 
@@ -636,13 +652,45 @@ tft_status mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const
     return inverse_impl<Mod>(ctx, X, Y, r, st);
 }
 
-// Space-restricted product (section 5, Algorithm 3): the output buffer is the
-// only memory written.  For q = 0, L_0, L_0 + L_1, ... with L the largest
-// power of two such that q + 2L <= r: fold A modulo x^L - w_{q/L} into
-// X[q, q+L) and transform that block (global index q/L, so X_{q+i} = A(w_{q+i})),
-// the same for B into X[q+L, q+2L), multiply pointwise into X[q, q+L).  The
-// last point r - 1 is one evaluation of each operand, then the inverse TFT of
-// length r.  At most 2 lg r blocks; each fold reads the whole operand.
+// Forward transforms of the two whole blocks (n a power of two) at X and X + n,
+// both at global block index g0, then X[i] = X[i] X[n + i], i < n: one column
+// launch for both, then both blocks' rows in one launch that multiplies on its
+// store (k_row_fwd_mul), when the rows are fused (W >= 64) and two of them fit
+// in LDS; otherwise the two forwards and a pointwise launch.
+template <class Mod>
+tft_status forward_pair_mul(tft_ctx* ctx, typename Mod::Word* X, uint64_t n, uint64_t g0, hipStream_t st) {
+    using Word = typename Mod::Word;
+    const Mod& md = mod_of<Mod>(ctx);
+    const Plan P = make_plan(ctx, n);
+    if (P.kind < 0) return TFT_ERANGE;
+    if (P.kind != 1 || P.b || P.logW < 6 || 2 * P.lds_row > kLdsDynMax) {
+        tft_status s = forward_impl<Mod>(ctx, X, n, X, n, st, g0, 2);
+        if (s != TFT_OK) return s;
+        const uint64_t blocks = std::min<uint64_t>(8192, (n + kThreads - 1) / kThreads);
+        launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, md, X,
+               (const Word*)(X + n), n);
+        return launch_status();
+    }
+    auto T = tables_of<Word>(ctx);
+    T.smax = P.smax;
+    Word* V = reinterpret_cast<Word*>(ctx->varea);
+    auto G = two_pass_of<Word>(P, X, X, n, nullptr, V);
+    G.g0 = g0;
+    G.inst = n;
+    G.Q = V + kVWords;
+    const uint32_t tiles = (uint32_t)(P.W >> P.logC);
+    launch(ctx, TFT_K_COL_FWD, col_fwd_kernel<Mod>(P.logC, false), dim3(tiles, 2), dim3(col_threads(P)), P.lds_col, st,
+           md, T, G, tiles);
+    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd_mul<Mod>, dim3((uint32_t)P.a), dim3(row_threads(P)), 2 * P.lds_row, st, md,
+           T, G);
+    return launch_status();
+}
+
+// Folding for the space-restricted product: A mod (x^L - w_g) into outA and B
+// mod (x^L - w_g) into outB, each word a Horner sum over the operand's terms
+// j + t L.  The terms of a word are split into K chunks so that about
+// kFoldItems threads per operand read the operand at once; the chunks' partial
+// sums go to the context's fold area and are added by a second launch.
 template <class Mod>
 tft_status fold_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, typename Mod::Word* outA,
                      const typename Mod::Word* B, uint64_t nb, typename Mod::Word* outB, unsigned logL, uint64_t g,
@@ -652,45 +700,66 @@ tft_status fold_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, type
     const auto T = tables_of<Word>(ctx);
     const uint64_t L = 1ull << logL;
     const uint64_t terms = (std::max(m, nb) + L - 1) >> logL;   // largest number of t per j
-    // enough threads to fill the device, at most 2^16 partial words per operand
-    uint64_t K = std::max<uint64_t>(1, std::min<uint64_t>(terms, (uint64_t(1) << 16) >> logL));
+    uint64_t K = std::max<uint64_t>(1, std::min<uint64_t>(terms, kFoldItems >> logL));
     const uint64_t chunk = (terms + K - 1) / K;
     K = (terms + chunk - 1) / chunk;
-    Word* part = reinterpret_cast<Word*>(ctx->varea) + kVWords;   // two areas of 2^16 words
+    Word* part = reinterpret_cast<Word*>(ctx->fold);   // two areas of kFoldItems words, then kFoldSpare
     tft::FoldArgs<Word> F;
     F.A[0] = A;
     F.A[1] = B;
     F.m[0] = m;
     F.m[1] = nb;
     F.out[0] = K == 1 ? outA : part;
-    F.out[1] = K == 1 ? outB : part + (size_t(1) << 16);
+    F.out[1] = K == 1 ? outB : part + kFoldItems;
     const uint64_t items = K << logL;
     launch(ctx, TFT_K_FOLD, tft::k_fold<Mod>, dim3((uint32_t)((items + kThreads - 1) / kThreads), 2), dim3(kThreads), 0,
            st, md, T, F, logL, (uint32_t)K, chunk, g);
-    if (K > 1) {
-        // sums of spans of the K partials, then (if more than one span) of those
-        const uint32_t spans = (uint32_t)((K + tft::kFoldSpan - 1) / tft::kFoldSpan);
-        Word* part2 = part + (size_t(1) << 17);   // 2 x spans * L <= 128 words: K > kFoldSpan only for L < 32
-        tft::SumArgs<Word> S1;
-        S1.part[0] = part;
-        S1.part[1] = part + (size_t(1) << 16);
-        S1.out[0] = spans == 1 ? outA : part2;
-        S1.out[1] = spans == 1 ? outB : part2 + 64;
-        launch(ctx, TFT_K_FOLD, tft::k_fold_sum<Mod>, dim3((uint32_t)L, spans, 2), dim3(kThreads), 0, st, md, S1, logL,
-               (uint32_t)K);
-        if (spans > 1) {
-            tft::SumArgs<Word> S2;
-            S2.part[0] = part2;
-            S2.part[1] = part2 + 64;
-            S2.out[0] = outA;
-            S2.out[1] = outB;
-            launch(ctx, TFT_K_FOLD, tft::k_fold_sum<Mod>, dim3((uint32_t)L, 1, 2), dim3(kThreads), 0, st, md, S2, logL,
-                   spans);
-        }
+    if (K == 1) return launch_status();
+    tft::SumArgs<Word> S1;
+    S1.part[0] = part;
+    S1.part[1] = part + kFoldItems;
+    if (K <= tft::kFoldFewK) {
+        S1.out[0] = outA;
+        S1.out[1] = outB;
+        launch(ctx, TFT_K_FOLD, tft::k_fold_sum_few<Mod>, dim3((uint32_t)((L + kThreads - 1) / kThreads), 2),
+               dim3(kThreads), 0, st, md, S1, logL, (uint32_t)K);
+        return launch_status();
+    }
+    // many partials per word (L < kFoldItems / kFoldFewK): a workgroup per word and
+    // span of kFoldSpan partials, then (if more than one span) per word
+    const uint32_t spans = (uint32_t)((K + tft::kFoldSpan - 1) / tft::kFoldSpan);
+    Word* part2 = part + 2 * kFoldItems;   // 2 spans L words, spans L <= kFoldItems / kFoldSpan + L
+    S1.out[0] = spans == 1 ? outA : part2;
+    S1.out[1] = spans == 1 ? outB : part2 + kFoldSpare / 2;
+    launch(ctx, TFT_K_FOLD, tft::k_fold_sum<Mod>, dim3((uint32_t)L, spans, 2), dim3(kThreads), 0, st, md, S1, logL,
+           (uint32_t)K);
+    if (spans > 1) {
+        tft::SumArgs<Word> S2;
+        S2.part[0] = part2;
+        S2.part[1] = part2 + kFoldSpare / 2;
+        S2.out[0] = outA;
+        S2.out[1] = outB;
+        launch(ctx, TFT_K_FOLD, tft::k_fold_sum<Mod>, dim3((uint32_t)L, 1, 2), dim3(kThreads), 0, st, md, S2, logL,
+               spans);
     }
     return launch_status();
 }
 
+// Space-restricted product (section 5, Algorithm 3): the output buffer is the
+// only memory of the product's size written.  For q = 0, L_0, L_0 + L_1, ...
+// with L the largest power of two such that q + 2L <= r: fold A modulo
+// x^L - w_{q/L} into X[q, q+L) and B into X[q+L, q+2L), transform both blocks
+// (global index q/L, one launch per pass for the two, so X_{q+i} = A(w_{q+i})),
+// multiply pointwise into X[q, q+L) (on the row pass's store, forward_pair_mul).  Each block reads all of A and B once, and
+// the short blocks at the end are latency-bound launches, so once
+// t = r - q < 2^(kRestrLog + 1) the remaining blocks are not taken one by one:
+// they lie in at most two aligned nodes of the transform tree of size
+// S = 2^(ceil(lg t) - 1) (t <= 2 S, and q is a multiple of S), whose folds of
+// A and B (4 S words, a fixed area of the context) are transformed and
+// multiplied into X[q, r) -- the same values, two passes over A and B instead
+// of about lg t.  Below two single-workgroup sizes the nodes are transformed
+// and multiplied by one workgroup each (k_restr_tail, folds in the V area).
+// Then the inverse TFT of length r.
 template <class Mod>
 tft_status mul_restricted_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const typename Mod::Word* B,
                                uint64_t nb, typename Mod::Word* X, hipStream_t st) {
@@ -698,33 +767,42 @@ tft_status mul_restricted_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64
     const Mod& md = mod_of<Mod>(ctx);
     const uint64_t r = m + nb - 1;
     if (r > (1ull << ctx->v)) return TFT_ERANGE;
+    const unsigned logSs = small_max_log2(ctx->wbytes);
+    const uint64_t Ss = 1ull << logSs;
     tft_status s = TFT_OK;
     uint64_t q = 0;
-    while (s == TFT_OK && q + 1 < r) {
+    while (s == TFT_OK && r - q >= (2ull << kRestrLog)) {
         const unsigned logL = (63u - (unsigned)__builtin_clzll(r - q)) - 1u;
         const uint64_t L = 1ull << logL, g = q >> logL;
         s = fold_impl<Mod>(ctx, A, m, X + q, B, nb, X + q + L, logL, g, st);
-        if (s == TFT_OK && make_plan(ctx, L).kind == 0) {
-            s = forward_impl<Mod>(ctx, X + q, L, X + q, L, st, g, 2);   // both blocks in one launch
-        } else if (s == TFT_OK) {
-            s = forward_impl<Mod>(ctx, X + q, L, X + q, L, st, g);
-            if (s == TFT_OK) s = forward_impl<Mod>(ctx, X + q + L, L, X + q + L, L, st, g);
-        }
-        if (s == TFT_OK) {
-            const uint64_t blocks = std::min<uint64_t>(8192, (L + kThreads - 1) / kThreads);
-            launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, md,
-                   X + q, (const Word*)(X + q + L), L);
-            s = launch_status();
-        }
+        if (s == TFT_OK) s = forward_pair_mul<Mod>(ctx, X + q, L, g, st);
         q += L;
     }
     if (s != TFT_OK) return s;
-    // the last point w_{r-1}: A(w_{r-1}) into X[r-1], B(w_{r-1}) into a scratch word
-    Word* tmp = reinterpret_cast<Word*>(ctx->varea) + kVWords + 2 * size_t(tft::kQStride);
-    s = fold_impl<Mod>(ctx, A, m, X + (r - 1), B, nb, tmp, 0, r - 1, st);
-    if (s != TFT_OK) return s;
-    launch(ctx, TFT_K_POINTWISE, tft::k_pointwise<Mod>, dim3(1), dim3(kThreads), 0, st, md, X + (r - 1),
-           (const Word*)tmp, (uint64_t)1);
+    const uint64_t t = r - q;   // q is a multiple of every block size so far (all >= 2^kRestrLog)
+    if (t < 2 * Ss) {
+        Word* N = reinterpret_cast<Word*>(ctx->varea);
+        const uint32_t nodes = (uint32_t)((t + Ss - 1) >> logSs);
+        for (uint32_t j = 0; j < nodes && s == TFT_OK; j++)
+            s = fold_impl<Mod>(ctx, A, m, N + j * Ss, B, nb, N + (2 + j) * Ss, logSs, (q >> logSs) + j, st);
+        if (s != TFT_OK) return s;
+        launch(ctx, TFT_K_SMALL_MUL, tft::k_restr_tail<Mod>, dim3(nodes), dim3(tft::kSmallThreads),
+               2 * (size_t)tft::padded_words((uint32_t)Ss) * ctx->wbytes, st, md, tables_of<Word>(ctx),
+               (const Word*)N, logSs, q >> logSs, r, X);
+    } else {
+        const unsigned logS = (t & (t - 1)) ? 64u - (unsigned)__builtin_clzll(t) - 1u : 63u - (unsigned)__builtin_clzll(t) - 1u;
+        const uint64_t S = 1ull << logS;   // S < t <= 2 S, Ss <= S <= 2^kRestrLog
+        Word* N = reinterpret_cast<Word*>(ctx->fold) + 2 * kFoldItems + kFoldSpare;
+        const uint32_t nodes = (uint32_t)((t + S - 1) >> logS);
+        for (uint32_t j = 0; j < nodes && s == TFT_OK; j++) {
+            const uint64_t g = (q >> logS) + j;
+            s = fold_impl<Mod>(ctx, A, m, N + 2 * j * S, B, nb, N + (2 * j + 1) * S, logS, g, st);
+            if (s == TFT_OK) s = forward_impl<Mod>(ctx, N + 2 * j * S, S, N + 2 * j * S, S, st, g, 2);
+        }
+        if (s != TFT_OK) return s;
+        launch(ctx, TFT_K_POINTWISE, tft::k_restr_nodes_mul<Mod>, dim3((uint32_t)((t + kThreads - 1) / kThreads)),
+               dim3(kThreads), 0, st, md, (const Word*)N, logS, q, r, X);
+    }
     s = launch_status();
     return s == TFT_OK ? inverse_impl<Mod>(ctx, X, nullptr, r, st) : s;
 }
@@ -1490,9 +1568,12 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
         if (e == hipSuccess) e = hipMemcpy(c->tables, t.data(), bytes, hipMemcpyHostToDevice);
         if (e == hipSuccess && !set_lds_limits<tft::ModU32>()) e = hipErrorInvalidValue;
     }
+    c->varea = c->fold = nullptr;
     if (e == hipSuccess) e = hipMalloc(&c->varea, kScratchWords * c->wbytes);
+    if (e == hipSuccess) e = hipMalloc(&c->fold, kFoldWords * c->wbytes);
     if (e != hipSuccess) {
         if (c->tables) (void)hipFree(c->tables);
+        if (c->varea) (void)hipFree(c->varea);
         delete c;
         return e == hipErrorOutOfMemory ? TFT_ENOMEM : TFT_EDEVICE;
     }
@@ -1511,6 +1592,7 @@ void tft_ctx_destroy(tft_ctx* ctx) {
     arena_free(&ctx->once_arena);
     (void)hipFree(ctx->tables);
     (void)hipFree(ctx->varea);
+    (void)hipFree(ctx->fold);
     for (auto& r : ctx->recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
     delete ctx;

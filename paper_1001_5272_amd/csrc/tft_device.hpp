@@ -316,6 +316,11 @@ struct Unit {
 // which spreads the strided accesses of the radix-8 units over the banks (a
 // row tile without it meets 16-way bank conflicts in its lowest stages).
 __host__ __device__ __forceinline__ uint32_t pad(uint32_t x) { return x + (x >> 5); }
+// pad(x + t s) - pad(x) for the elements x + t s (t < R) of a unit at stride s,
+// a power of two, when x mod (R s) < s (the unit lies in one aligned block of
+// R s words): t s + (t s >> 5), the same in every lane, so a unit computes
+// one padded address and adds a wave-uniform offset per element.
+__host__ __device__ __forceinline__ uint32_t pad_step(uint32_t t, uint32_t s) { return t * s + ((t * s) >> 5); }
 // words of LDS a padded tile of n words occupies
 __host__ __device__ __forceinline__ uint32_t padded_words(uint32_t n) { return n + (n >> 5) + 1; }
 
@@ -347,14 +352,15 @@ __device__ __forceinline__ void dif_group(const Mod& md, const Tables<typename M
         const uint32_t i = i_lo + (u >> logq);
         const uint32_t j = u & (q - 1);
         const uint32_t base = i * two_h + j;
+        const uint32_t a0 = pad(base * C + c), st = q << logC;   // (base C + c) mod (2h C) < q C
         Word x[R];
 #pragma unroll
-        for (int t = 0; t < R; t++) x[t] = buf[pad((base + t * q) * C + c)];
+        for (int t = 0; t < R; t++) x[t] = buf[a0 + pad_step(t, st)];
         if (Z) un.load0(tab, sh, i);
         else un.load_fwd(md, T, gbase + i);
         un.template forward<TOP>(md, x);
 #pragma unroll
-        for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
+        for (int t = 0; t < R; t++) buf[a0 + pad_step(t, st)] = x[t];
     }
     lds_sync();
 }
@@ -507,14 +513,15 @@ __device__ __forceinline__ void dit_group(const Mod& md, const Tables<typename M
         const uint32_t i = u >> logq;
         const uint32_t j = u & (q - 1);
         const uint32_t base = off + i * two_h + j;
+        const uint32_t a0 = pad(base * C + c), st = q << logC;   // off is a multiple of Sz >= 2h
         Word x[R];
 #pragma unroll
-        for (int t = 0; t < R; t++) x[t] = buf[pad((base + t * q) * C + c)];
+        for (int t = 0; t < R; t++) x[t] = buf[a0 + pad_step(t, st)];
         if (Z) un.load0(tab, sh, i);
         else un.load_inv(md, T, gbase + i);
         un.template inverse<HALF, TOP>(md, x);
 #pragma unroll
-        for (int t = 0; t < R; t++) buf[pad((base + t * q) * C + c)] = x[t];
+        for (int t = 0; t < R; t++) buf[a0 + pad_step(t, st)] = x[t];
     }
     if (SYNC) lds_sync();
 }

@@ -152,6 +152,7 @@ struct TwoPass {
     uint32_t nparts;  // inverse with b = 1: column tiles leaving a partial last-row sum at Q + kQStride, or 0
     uint32_t ldstw;   // 1: column tiles copy their block-0 twiddles to LDS; 0: read them from the table in memory
                       // (when the copy would cost a tile per CU)
+    uint64_t inst;    // forward over whole blocks (b = 0) with gridDim.y > 1: instance y at X + y inst (and src + y inst)
 };
 constexpr uint32_t kQStride = (1u << 16) + 64;
 
@@ -250,7 +251,7 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
                 acc = md.add(acc, md.mul_tw(e, root_pow(md, T, (u * EH) & maskK)));
                 top.template forward<true>(md, x);
 #pragma unroll
-                for (int t = 0; t < 8; t++) buf[pad((u + t * M8) * C + c)] = x[t];
+                for (int t = 0; t < 8; t++) buf[pad(u * C + c) + pad_step(t, M8 * C)] = x[t];
             }
             reduce_lanes(md, acc, LOGC, red, extra);   // its barriers also publish the tile
             if (H >= 64) {
@@ -260,7 +261,7 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
                     const uint32_t c = it & (C - 1), i = it >> LOGC;
                     Word x[8];
 #pragma unroll
-                    for (int t = 0; t < 8; t++) x[t] = buf[pad((8 * i + t) * C + c)];
+                    for (int t = 0; t < 8; t++) x[t] = buf[pad(8 * i * C + c) + pad_step(t, C)];
                     Unit<Mod, 3> un;
                     un.load0(T.lf, 0, i);
                     un.forward(md, x);
@@ -373,7 +374,7 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
             }
             top.template forward<true>(md, x);
 #pragma unroll
-            for (int t = 0; t < 8; t++) buf[pad((u + t * M8) * C + c)] = x[t];
+            for (int t = 0; t < 8; t++) buf[pad(u * C + c) + pad_step(t, M8 * C)] = x[t];
         }
         __syncthreads();
         if (P.M >= 64) {
@@ -385,7 +386,7 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
                 const uint32_t c = it & (C - 1), i = it >> LOGC;
                 Word x[8];
 #pragma unroll
-                for (int t = 0; t < 8; t++) x[t] = buf[pad((8 * i + t) * C + c)];
+                for (int t = 0; t < 8; t++) x[t] = buf[pad(8 * i * C + c) + pad_step(t, C)];
                 Unit<Mod, 3> un;
                 un.load0(T.lf, 0, i);
                 un.forward(md, x);
@@ -447,11 +448,12 @@ __device__ __forceinline__ void store8(Word* p, const Word (&x)[8]) {
     for (int t = 0; t < 8; t++) p[t] = x[t];
 }
 
-// Forward transform of row g (block F mod (x^W - w_g)) in place at row,
-// twisted to block index 0 as described in row_fwd_body.
+// Forward transform of row g (block F mod (x^W - w_g)) from row into buf
+// (padded, published by the last barrier), twisted to block index 0 as
+// described in row_fwd_body.
 template <class Mod>
-__device__ __forceinline__ void row_fwd_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
-                              typename Mod::Word* row, uint32_t logW, uint64_t g) {
+__device__ __forceinline__ void row_fwd_lds(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+                                            const typename Mod::Word* row, uint32_t logW, uint64_t g) {
     using Word = typename Mod::Word;
     const uint32_t W = 1u << logW, W8 = W >> 3, nt = nthreads(), maskK = (1u << T.K) - 1;
     const Word* tab = T.f1;   // w_{2x} = f1[2x], x < W/2 <= 2^(B1-1)
@@ -472,11 +474,18 @@ __device__ __forceinline__ void row_fwd_fused(const Mod& md, const Tables<typena
         }
         top.template forward<true>(md, x);
 #pragma unroll
-        for (int t = 0; t < 8; t++) buf[pad(u + t * W8)] = x[t];
+        for (int t = 0; t < 8; t++) buf[pad(u) + pad_step(t, W8)] = x[t];
     }
     __syncthreads();
     dif_stages(md, T, buf, 0, W, W >> 4, 1, 0, W, 0);
-    staged_copy<8>(W, [&](uint32_t i) { return buf[pad(i)]; }, [&](uint32_t i, Word v) { row[i] = v; });
+}
+// The same, in place at row.
+template <class Mod>
+__device__ __forceinline__ void row_fwd_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+                              typename Mod::Word* row, uint32_t logW, uint64_t g) {
+    using Word = typename Mod::Word;
+    row_fwd_lds(md, T, buf, row, logW, g);
+    staged_copy<8>(1u << logW, [&](uint32_t i) { return buf[pad(i)]; }, [&](uint32_t i, Word v) { row[i] = v; });
 }
 
 // Inverse of row_fwd_fused: coefficients of row g from its W values at row
@@ -513,7 +522,7 @@ __device__ __forceinline__ void row_inv_fused(const Mod& md, const Tables<typena
         un.load0(tab, 1, i);
         un.template inverse<false>(md, x);
 #pragma unroll
-        for (int t = 0; t < 8; t++) buf[pad(8 * i + t)] = x[t];
+        for (int t = 0; t < 8; t++) buf[pad(8 * i) + t] = x[t];
     }
     __syncthreads();
     if (logW > 6) dit_stages<Mod, false>(md, T, buf, 0, 0, W, 3, (int)logW - 3, 0);
@@ -526,7 +535,7 @@ __device__ __forceinline__ void row_inv_fused(const Mod& md, const Tables<typena
     for (uint32_t u = threadIdx.x; u < W8; u += nt) {
         Word x[8];
 #pragma unroll
-        for (int t = 0; t < 8; t++) x[t] = buf[pad(u + t * W8)];
+        for (int t = 0; t < 8; t++) x[t] = buf[pad(u) + pad_step(t, W8)];
         top.template inverse<false, true>(md, x);
         Word f = md.tw_mul_tw(sc, root_pow_inv(md, T, (u * E) & maskK));
 #pragma unroll
@@ -730,7 +739,7 @@ __device__ __forceinline__ void col_inv_body(const Mod& md, const Tables<typenam
             un.load0(T.li, 0, i);
             un.template inverse<false>(md, x);
 #pragma unroll
-            for (int t = 0; t < 8; t++) buf[pad((8 * i + t) * C + c)] = x[t];
+            for (int t = 0; t < 8; t++) buf[pad(8 * i * C + c) + pad_step(t, C)] = x[t];
         }
         __syncthreads();
         const int L = __builtin_ctz(Mg);
@@ -747,7 +756,7 @@ __device__ __forceinline__ void col_inv_body(const Mod& md, const Tables<typenam
             const uint32_t col = c0 + c;
             Word x[8];
 #pragma unroll
-            for (int t = 0; t < 8; t++) x[t] = buf[pad((u + t * M8) * C + c)];
+            for (int t = 0; t < 8; t++) x[t] = buf[pad(u * C + c) + pad_step(t, M8 * C)];
             lastg.template inverse<false, true>(md, x);
             if (mine_col(col)) {
 #pragma unroll
@@ -1108,12 +1117,17 @@ __device__ __forceinline__ void col_poly_body(const Mod& md, const Tables<typena
 template <class Mod, int LOGC, bool HS = false>
 __global__ __launch_bounds__(kColThreads) void k_col_fwd(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P, uint32_t tiles) {
+    if (blockIdx.y) {
+        P.X += blockIdx.y * P.inst;
+        P.src += blockIdx.y * P.inst;
+    }
     col_fwd_body<Mod, LOGC, HS>(md, T, P, xcd_remap(blockIdx.x, tiles));
 }
 template <class Mod>
 __global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_row_fwd(Mod md, Tables<typename Mod::Word> T,
                                                       TwoPass<typename Mod::Word> P) {
     using Word = typename Mod::Word;
+    if (blockIdx.y) P.X += blockIdx.y * P.inst;
     if (P.b == 1 && P.nparts) {
         // one output in the last row: the sum of the column tiles' shares,
         // added by workgroup 0 before its own row (no workgroup of its own)
@@ -1137,6 +1151,24 @@ __global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))
     // alone after the full rows whenever they fill every slot of the device
     const uint32_t k = P.b ? (blockIdx.x == 0 ? P.a : blockIdx.x - 1) : blockIdx.x;
     row_fwd_body(md, T, P, k);
+}
+// Forward row pass of two instances of a whole block (b = 0, W >= 64) at X
+// and X + inst, multiplied: workgroup j transforms row j of both in LDS and
+// stores their pointwise product over the first instance's row (the
+// space-restricted product's blocks, no pointwise launch of their own).
+template <class Mod>
+__global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_row_fwd_mul(
+    Mod md, Tables<typename Mod::Word> T, TwoPass<typename Mod::Word> P) {
+    using Word = typename Mod::Word;
+    const uint32_t W = 1u << P.logW;
+    Word* ba = lds_buf<Word>();
+    Word* bb = ba + padded_words(W);
+    const uint32_t j = blockIdx.x;
+    const uint64_t g = P.g0 * P.a + j;
+    Word* ra = P.X + (uint64_t)j * W;
+    row_fwd_lds(md, T, ba, ra, P.logW, g);
+    row_fwd_lds(md, T, bb, ra + P.inst, P.logW, g);
+    staged_copy<8>(W, [&](uint32_t i) { return md.mul(ba[pad(i)], bb[pad(i)]); }, [&](uint32_t i, Word v) { ra[i] = v; });
 }
 // With P.early == 2 workgroup 0 builds Q (col_poly_body; dispatched first, it
 // runs beside the rows).  The last row's pieces come next, the full rows last.
@@ -1259,6 +1291,66 @@ __global__ __launch_bounds__(kThreads) void k_fold_sum(Mod md, SumArgs<typename 
         for (int w = 0; w < kThreads / 64; w++) t = md.add(t, red[w]);
         S.out[blockIdx.z][((uint64_t)blockIdx.y << logL) + j] = t;
     }
+}
+
+// out[j] = sum_{k < K} part[k L + j] for few partials (K <= kFoldFewK): one
+// thread per word j and operand (grid y), the K loads of a thread independent.
+constexpr uint32_t kFoldFewK = 64;
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_fold_sum_few(Mod md, SumArgs<typename Mod::Word> S, uint32_t logL,
+                                                          uint32_t K) {
+    using Word = typename Mod::Word;
+    const uint64_t j = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j >> logL) return;
+    const Word* part = S.part[blockIdx.y];
+    Word s = 0;
+#pragma unroll 8
+    for (uint32_t k = 0; k < K; k++) s = md.add(s, part[((uint64_t)k << logL) + j]);
+    S.out[blockIdx.y][j] = s;
+}
+
+// The last blocks of the space-restricted product (section 5, Algorithm 3),
+// those of fewer than S = 2^logS points, all lie in at most two aligned nodes
+// of size S of the transform tree, [g S, (g + 1) S) for g = G0 and G0 + 1.
+// For each node (workgroup x): A mod (x^S - w_g) at N + x S and B mod
+// (x^S - w_g) at N + (2 + x) S (folded beforehand) are transformed at block
+// index g, and the products A(w_s) B(w_s) of the positions s < r of the node
+// are written to X[s].  The same values as the blocks one at a time, without a
+// pass over A and B per block.
+template <class Mod>
+__global__ __launch_bounds__(kSmallThreads) void k_restr_tail(Mod md, Tables<typename Mod::Word> T,
+                                                             const typename Mod::Word* N, uint32_t logS, uint64_t G0,
+                                                             uint64_t r, typename Mod::Word* X) {
+    using Word = typename Mod::Word;
+    const uint32_t S = 1u << logS;
+    const uint64_t g = G0 + blockIdx.x;
+    const uint64_t base = g << logS;
+    const uint32_t need = r - base < S ? (uint32_t)(r - base) : S;
+    Word* ba = lds_buf<Word>();
+    Word* bb = ba + padded_words(S);
+    const Word* na = N + ((uint64_t)blockIdx.x << logS);
+    const Word* nb = N + ((uint64_t)(2 + blockIdx.x) << logS);
+    for (uint32_t i = threadIdx.x; i < S; i += nthreads()) {
+        ba[pad(i)] = na[i];
+        bb[pad(i)] = nb[i];
+    }
+    __syncthreads();
+    dif_forward(md, T, ba, 0, S, 0, need, g);
+    dif_forward(md, T, bb, 0, S, 0, need, g);
+    for (uint32_t i = threadIdx.x; i < need; i += nthreads()) X[base + i] = md.mul(ba[pad(i)], bb[pad(i)]);
+}
+
+// The space-restricted product's last positions q <= s < r from at most two
+// nodes of size S = 2^logS, [q + j S, q + (j + 1) S): node j holds A's values
+// at N + 2 j S and B's at N + (2 j + 1) S (transformed beforehand), and
+// X[s] = A(w_s) B(w_s).
+template <class Mod>
+__global__ __launch_bounds__(kThreads) void k_restr_nodes_mul(Mod md, const typename Mod::Word* N, uint32_t logS,
+                                                             uint64_t q, uint64_t r, typename Mod::Word* X) {
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= r - q) return;
+    const uint64_t j = i >> logS, k = i & ((1ull << logS) - 1);
+    X[q + i] = md.mul(N[((2 * j) << logS) + k], N[((2 * j + 1) << logS) + k]);
 }
 
 // X[i] = i mod p (canonical residues for timing runs).

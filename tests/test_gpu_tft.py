@@ -163,6 +163,29 @@ def test_restricted_products(ctxs, name):
         assert (C == ref).all(), f"restricted product {m}x{nb} mismatches at {np.nonzero(C != ref)[0][:5]}"
 
 
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+def test_restricted_tail_nodes(ctxs, name):
+    # the restricted product's last positions (t = r - q < 2^18 of them) come
+    # from one or two aligned nodes: single-workgroup nodes of S = 2^13 words
+    # (4-byte words) or 2^12 (8-byte) when t < 2S, else nodes of size
+    # 2^(ceil(lg t) - 1) transformed in two passes.  r below, at and above 2S,
+    # 3S and 4S, r < 2S (the whole product from the nodes), and r around 2^18
+    # (the first block of 2^17, then nodes)
+    p, g = PRIMES[name]
+    ctx = ctxs[name]
+    S = 1 << (13 if ctx.word_bytes == 4 else 12)
+    for r in [S - 3, 2 * S - 1, 2 * S, 2 * S + 1, 3 * S - 1, 3 * S, 3 * S + 1, 4 * S - 1, 5 * S + 7,
+              3 * (1 << 15) + 1, (1 << 18) - 1, 1 << 18, (1 << 18) + 1, 5 * (1 << 17) + 3]:
+        m = r // 3 + 1
+        nb = r + 1 - m
+        print(f"[gpu] {name} restricted product {m}x{nb} (r = {r}, S = {S})", flush=True)
+        A = synth.residues(p, m, 500 + r)
+        B = synth.residues(p, nb, 600 + r)
+        C = gpu_mul_restricted(ctx, A, B)
+        ref = oracle.mul_padded(p, g, A, B)
+        assert (C == ref).all(), f"restricted product r={r} mismatches at {np.nonzero(C != ref)[0][:5]}"
+
+
 def test_rejects_bad_arguments(ctxs):
     import torch
     ctx = ctxs["p998244353"]
