@@ -354,6 +354,27 @@ def extras(ctx, bufs, host, p, skip=frozenset()):
     return out
 
 
+def restricted_fold_passes(r, word_bytes=8):
+    """Fold passes over A and B of poly_mul_restricted at product length r:
+    one per step with at least 2^18 positions left, then one per node (two,
+    or ceil(t / S) single-workgroup nodes of S words when t < 2S); and the
+    same count for the step-by-step schedule (one per block, plus the last
+    point)."""
+    small = 1 << (13 if word_bytes == 4 else 12)
+    q = passes = 0
+    while r - q >= 1 << 18:
+        L = 1 << ((r - q).bit_length() - 2)
+        q += L
+        passes += 1
+    t = r - q
+    passes += -(-t // small) if t < 2 * small else 2
+    q = literal = 0
+    while q + 1 < r:
+        q += 1 << ((r - q).bit_length() - 2)
+        literal += 1
+    return passes, literal + (1 if q < r else 0)
+
+
 def products(ctx, p, dev):
     """poly_mul at product lengths r of the sweep against the padded product."""
     import torch
@@ -379,10 +400,15 @@ def products(ctx, p, dev):
         X3 = torch.empty(r, dtype=torch.uint64, device=dev)
         trm = event_time(lambda: libtft.poly_mul_restricted(ctx, A, B, X3), 3)
         same_r = bool(torch.equal(X, X3))
+        passes, literal = restricted_fold_passes(r)
         prods.append({"r": r, "poly_mul_us": round(tm * 1e3, 1), "padded_mul_us": round(tpm * 1e3, 1),
-                      "restricted_mul_us": round(trm * 1e3, 1),
+                      "restricted_mul_us": round(trm * 1e3, 1), "restricted_over_poly_mul": round(trm / tm, 2),
                       "mults_per_s": round(1e3 / tm, 1), "same_as_padded": same, "restricted_same": same_r,
-                      "written_words": {"poly_mul": 2 * r, "restricted": r, "padded": 2 * N + r}})
+                      "written_words": {"poly_mul": 2 * r, "restricted": r, "padded": 2 * N + r},
+                      # every fold pass reads both operands once
+                      "restricted_fold_reads": {"passes": passes, "bytes": passes * (la + lb) * 8,
+                                                "step_by_step_passes": literal,
+                                                "step_by_step_bytes": literal * (la + lb) * 8}})
         del X3
         del Ap, Bp, X2
     return prods

@@ -103,14 +103,18 @@ tft_status poly_mul_noalloc(tft_ctx* ctx, const void* A, size_t m, const void* B
                             void* hip_stream);
 
 /* Space-restricted product (section 5, Algorithm 3; Proposition 5.1): the same
- * C = A B with X (r = m + nb - 1 words) as the only memory written -- no
- * workspace.  For q = 0, L_0, L_0 + L_1, ... (L the largest power of two with
- * q + 2L <= r, at most 2 lg r blocks) A and B are folded modulo x^L - w_{q/L}
- * into X[q, q+L) and X[q+L, q+2L), both blocks are transformed (their values
- * are A^_{q+i} and B^_{q+i}) and multiplied into X[q, q+L); the last slot gets
- * A(w_{r-1}) B(w_{r-1}); then the inverse TFT of length r.  Each fold reads a
- * whole operand, so this path moves more memory than poly_mul in exchange for
- * the r-word footprint.  Errors as for poly_mul. */
+ * C = A B with X (r = m + nb - 1 words) as the only memory of the product's
+ * size written -- no workspace.  For q = 0, L_0, L_0 + L_1, ... (L the largest
+ * power of two with q + 2L <= r) A and B are folded modulo x^L - w_{q/L} into
+ * X[q, q+L) and X[q+L, q+2L), both blocks are transformed (their values are
+ * A^_{q+i} and B^_{q+i}) and multiplied into X[q, q+L).  Once fewer than 2^18
+ * positions remain, they lie in at most two aligned nodes of the transform
+ * tree; A and B are folded once per node into a fixed area of the context
+ * (four nodes of at most 2^17 words, allocated with the context) and the
+ * node values are multiplied into X[q, r).  Then the inverse TFT of length r.
+ * Each fold reads a whole operand, so this path moves more memory than
+ * poly_mul in exchange for the r-word footprint.  Calls on one context share
+ * its fold area: issue them on one stream.  Errors as for poly_mul. */
 tft_status poly_mul_restricted(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t nb, void* X,
                                void* hip_stream);
 
