@@ -54,7 +54,10 @@ typedef struct tft_ctx tft_ctx;
 
 /* Create a context for prime p with generator g of (Z/pZ)^* on HIP device
  * `device` (section 2.1: the ring needs 2^k-th roots of unity and 2 must be a
- * unit).  Supported: odd primes p < 2^31 with 2 | p-1, and p = 2^64-2^32+1.
+ * unit).  Supported: odd primes p < 2^31 (words of 4 bytes, 32-bit
+ * Montgomery arithmetic), p = 2^64-2^32+1 (8-byte words, reduction by
+ * 2^64 = 2^32 - 1 and 2^96 = -1), and the other odd primes 2^31 < p < 2^63
+ * (8-byte words, 64-bit Montgomery arithmetic); any other p is TFT_ERANGE.
  * g must generate the 2-part of the group: g^((p-1)/2) = -1.  On success
  * *out owns device tables of about 1 MiB; release it with tft_ctx_destroy. */
 tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out);

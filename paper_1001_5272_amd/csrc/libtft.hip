@@ -161,6 +161,7 @@ struct tft_ctx {
     std::atomic<unsigned> batch_widen;                // batches: rows this many steps wider than balanced (0..2)
     tft::ModU32 m32;
     tft::ModGL m64;
+    tft::ModM64 mm64;    // 8-byte words, p other than 2^64 - 2^32 + 1
     void* tables;        // f1 | f2 | i1 | i2
     size_t n1, n2;       // entries per level
     void* varea;         // V_c area and column polynomial (kScratchWords words)
@@ -428,6 +429,8 @@ template <>
 const tft::ModU32& mod_of<tft::ModU32>(const tft_ctx* ctx) { return ctx->m32; }
 template <>
 const tft::ModGL& mod_of<tft::ModGL>(const tft_ctx* ctx) { return ctx->m64; }
+template <>
+const tft::ModM64& mod_of<tft::ModM64>(const tft_ctx* ctx) { return ctx->mm64; }
 
 // Allow each kernel the dynamic LDS the planner may give it (the largest tile
 // plus headroom, below the 160 KiB per workgroup minus static LDS).
@@ -863,8 +866,8 @@ std::vector<Word> build_tables(uint64_t p, uint64_t g, unsigned v, size_t n1, si
     // f1[s] = w_s (s < n1), f2[h] = w_{h 2^B1} (h < n2), i1[s] = w_s^-1, i2[h] = w_{h 2^B1}^-1
     std::vector<Word> out(2 * (n1 + n2), Word(0));
     auto root = [&](unsigned k) { return powmod_h(g, (p - 1) >> k, p); };
-    auto enc = [&](uint64_t x) -> Word {
-        return montgomery ? (Word)(((u128)x << 32) % p) : (Word)x;
+    auto enc = [&](uint64_t x) -> Word {   // Montgomery form: x 2^(bits of Word) mod p
+        return montgomery ? (Word)(((u128)x << (8 * sizeof(Word))) % p) : (Word)x;
     };
     const unsigned k1 = v < (unsigned)kB1 ? v : (unsigned)kB1;
     const uint64_t lim1 = 1ull << k1;
@@ -919,11 +922,21 @@ bool is_probable_prime(uint64_t n) {
     return true;
 }
 
+// f(Mod{}) with the context's arithmetic: ModU32 (words of 4 bytes), ModGL
+// (p = 2^64 - 2^32 + 1) or ModM64 (the other primes of 8-byte words); f uses
+// the argument's type only.
+template <class F>
+tft_status with_mod(const tft_ctx* ctx, F&& f) {
+    if (ctx->wbytes == 4) return f(tft::ModU32{});
+    if (ctx->p == kGoldilocks) return f(tft::ModGL{});
+    return f(tft::ModM64{});
+}
+
 template <class F>
 tft_status dispatch(tft_ctx* ctx, F&& f) {
     if (!ctx) return TFT_EINVAL;
     DeviceGuard guard(ctx->device);
-    return f();
+    return with_mod(ctx, f);
 }
 
 // ================================================================= batches
@@ -1228,8 +1241,7 @@ tft_status batch_create(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int p
         B->fork = arena->fork;
         B->join = arena->join;
     }
-    tft_status s = ctx->wbytes == 4 ? batch_build<tft::ModU32>(ctx, d, count, products, B, upload)
-                                    : batch_build<tft::ModGL>(ctx, d, count, products, B, upload);
+    tft_status s = with_mod(ctx, [&](auto mt) { return batch_build<decltype(mt)>(ctx, d, count, products, B, upload); });
     if (s == TFT_OK && !arena) {
         if (hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) != hipSuccess ||
@@ -1261,7 +1273,7 @@ tft_status batch_once(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pro
     tft_status s = batch_create(ctx, d, count, products, &B, &ctx->once_arena, st);
     if (s != TFT_OK) return s;
     DeviceGuard guard(ctx->device);
-    s = ctx->wbytes == 4 ? batch_run<tft::ModU32>(B, st) : batch_run<tft::ModGL>(B, st);
+    s = with_mod(ctx, [&](auto mt) { return batch_run<decltype(mt)>(B, st); });
     ctx->last_batch = B;
     if (!ctx->last_done && hipEventCreateWithFlags(&ctx->last_done, hipEventDisableTiming) != hipSuccess)
         return TFT_EDEVICE;
@@ -1515,8 +1527,11 @@ const char* tft_strerror(tft_status s) {
 tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
     if (!out) return TFT_EINVAL;
     *out = nullptr;
-    const bool wide = (p == kGoldilocks);
-    if (!wide && (p >= (1ull << 31) || p < 3 || !(p & 1) || !is_probable_prime(p))) return TFT_ERANGE;
+    // 4-byte words for p < 2^31; 8-byte words for p = 2^64 - 2^32 + 1 and for
+    // the other primes below 2^63 (Montgomery arithmetic, ModM64)
+    const bool gold = (p == kGoldilocks);
+    if (!gold && (p >= (1ull << 63) || p < 3 || !(p & 1) || !is_probable_prime(p))) return TFT_ERANGE;
+    const bool wide = gold || p >= (1ull << 31);
     unsigned v = 0;
     while (!(((p - 1) >> v) & 1)) v++;
     if (v < 1) return TFT_ERANGE;
@@ -1545,6 +1560,14 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
         c->m32.pneg = (uint32_t)(0u - inv);
         c->m32.r2 = (uint32_t)(((u128)1 << 64) % p);
         c->m32.halfp1 = (uint32_t)((p + 1) / 2);
+    } else if (!gold) {
+        uint64_t inv = 1;                          // p^-1 mod 2^64 by Newton iteration
+        for (int i = 0; i < 6; i++) inv *= 2u - p * inv;
+        c->mm64.p = p;
+        c->mm64.pneg = 0u - inv;
+        const uint64_t r1 = (uint64_t)(((u128)1 << 64) % p);
+        c->mm64.r2 = (uint64_t)((u128)r1 * r1 % p);
+        c->mm64.halfp1 = (p + 1) / 2;
     }
     c->n1 = size_t(1) << kB1;
     c->n2 = c->v > (unsigned)kB1 ? size_t(1) << (c->v - kB1) : 1;
@@ -1556,11 +1579,12 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
         return TFT_EDEVICE;
     }
     if (wide) {
-        auto t = build_tables<uint64_t>(p, g, c->v, c->n1, c->n2, false);
+        auto t = build_tables<uint64_t>(p, g, c->v, c->n1, c->n2, !gold);
         bytes = t.size() * 8;
         e = hipMalloc(&c->tables, bytes);
         if (e == hipSuccess) e = hipMemcpy(c->tables, t.data(), bytes, hipMemcpyHostToDevice);
-        if (e == hipSuccess && !set_lds_limits<tft::ModGL>()) e = hipErrorInvalidValue;
+        if (e == hipSuccess && !(gold ? set_lds_limits<tft::ModGL>() : set_lds_limits<tft::ModM64>()))
+            e = hipErrorInvalidValue;
     } else {
         auto t = build_tables<uint32_t>(p, g, c->v, c->n1, c->n2, true);
         bytes = t.size() * 4;
@@ -1612,13 +1636,10 @@ tft_status tft_forward(tft_ctx* ctx, void* X, size_t n, void* stream) {
     tft_status s = check_len(ctx, n);
     if (s != TFT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4) {
-            auto* x = (uint32_t*)X;
-            return forward_impl<tft::ModU32>(ctx, x, n, x, n, st);
-        }
-        auto* x = (uint64_t*)X;
-        return forward_impl<tft::ModGL>(ctx, x, n, x, n, st);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        auto* x = (typename Mod::Word*)X;
+        return forward_impl<Mod>(ctx, x, n, x, n, st);
     });
 }
 
@@ -1627,18 +1648,19 @@ tft_status tft_inverse(tft_ctx* ctx, void* X, size_t n, void* stream) {
     tft_status s = check_len(ctx, n);
     if (s != TFT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4) return inverse_impl<tft::ModU32>(ctx, (uint32_t*)X, nullptr, n, st);
-        return inverse_impl<tft::ModGL>(ctx, (uint64_t*)X, nullptr, n, st);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        return inverse_impl<Mod>(ctx, (typename Mod::Word*)X, nullptr, n, st);
     });
 }
 
 tft_status tft_pointwise_mul(tft_ctx* ctx, void* X, const void* Y, size_t n, void* stream) {
     if (!ctx || !X || !Y || n == 0) return TFT_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4) return pointwise_impl<tft::ModU32>(ctx, (uint32_t*)X, (const uint32_t*)Y, n, st);
-        return pointwise_impl<tft::ModGL>(ctx, (uint64_t*)X, (const uint64_t*)Y, n, st);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        using Word = typename Mod::Word;
+        return pointwise_impl<Mod>(ctx, (Word*)X, (const Word*)Y, n, st);
     });
 }
 
@@ -1647,11 +1669,10 @@ tft_status poly_mul(tft_ctx* ctx, const void* A, size_t m, const void* B, size_t
     tft_status s = check_len(ctx, m + nb - 1);
     if (s != TFT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4)
-            return mul_impl<tft::ModU32>(ctx, (const uint32_t*)A, m, (const uint32_t*)B, nb, (uint32_t*)X, (uint32_t*)Y,
-                                         st);
-        return mul_impl<tft::ModGL>(ctx, (const uint64_t*)A, m, (const uint64_t*)B, nb, (uint64_t*)X, (uint64_t*)Y, st);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        using Word = typename Mod::Word;
+        return mul_impl<Mod>(ctx, (const Word*)A, m, (const Word*)B, nb, (Word*)X, (Word*)Y, st);
     });
 }
 
@@ -1665,11 +1686,10 @@ tft_status poly_mul_noalloc(tft_ctx* ctx, const void* A, size_t m, const void* B
     void* Y = ctx->device < kMaxDevices ? g_noalloc_ptr[ctx->device].load(std::memory_order_acquire) : nullptr;
     if (!Y) return TFT_EDEVICE;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4)
-            return mul_impl<tft::ModU32>(ctx, (const uint32_t*)A, m, (const uint32_t*)B, nb, (uint32_t*)X, (uint32_t*)Y,
-                                         st);
-        return mul_impl<tft::ModGL>(ctx, (const uint64_t*)A, m, (const uint64_t*)B, nb, (uint64_t*)X, (uint64_t*)Y, st);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        using Word = typename Mod::Word;
+        return mul_impl<Mod>(ctx, (const Word*)A, m, (const Word*)B, nb, (Word*)X, (Word*)Y, st);
     });
 }
 
@@ -1678,9 +1698,10 @@ tft_status tft_padded_forward(tft_ctx* ctx, void* X, size_t n, void* Xpad, void*
     tft_status s = check_len(ctx, n);
     if (s != TFT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4) return padded_forward_impl<tft::ModU32>(ctx, (uint32_t*)X, n, (uint32_t*)Xpad, st);
-        return padded_forward_impl<tft::ModGL>(ctx, (uint64_t*)X, n, (uint64_t*)Xpad, st);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        using Word = typename Mod::Word;
+        return padded_forward_impl<Mod>(ctx, (Word*)X, n, (Word*)Xpad, st);
     });
 }
 
@@ -1689,9 +1710,10 @@ tft_status tft_padded_inverse(tft_ctx* ctx, void* X, size_t n, void* Xpad, void*
     tft_status s = check_len(ctx, n);
     if (s != TFT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4) return padded_inverse_impl<tft::ModU32>(ctx, (uint32_t*)X, n, (uint32_t*)Xpad, st);
-        return padded_inverse_impl<tft::ModGL>(ctx, (uint64_t*)X, n, (uint64_t*)Xpad, st);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        using Word = typename Mod::Word;
+        return padded_inverse_impl<Mod>(ctx, (Word*)X, n, (Word*)Xpad, st);
     });
 }
 
@@ -1700,13 +1722,10 @@ tft_status tft_buffered_forward(tft_ctx* ctx, void* Xbuf, size_t n, void* stream
     tft_status s = check_len(ctx, n);
     if (s != TFT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4) {
-            auto* x = (uint32_t*)Xbuf;
-            return forward_impl<tft::ModU32>(ctx, x, n, x, n, st, 0, 1, true);
-        }
-        auto* x = (uint64_t*)Xbuf;
-        return forward_impl<tft::ModGL>(ctx, x, n, x, n, st, 0, 1, true);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        auto* x = (typename Mod::Word*)Xbuf;
+        return forward_impl<Mod>(ctx, x, n, x, n, st, 0, 1, true);
     });
 }
 
@@ -1715,9 +1734,9 @@ tft_status tft_buffered_inverse(tft_ctx* ctx, void* Xbuf, size_t n, void* stream
     tft_status s = check_len(ctx, n);
     if (s != TFT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4) return inverse_impl<tft::ModU32>(ctx, (uint32_t*)Xbuf, nullptr, n, st, true);
-        return inverse_impl<tft::ModGL>(ctx, (uint64_t*)Xbuf, nullptr, n, st, true);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        return inverse_impl<Mod>(ctx, (typename Mod::Word*)Xbuf, nullptr, n, st, true);
     });
 }
 
@@ -1727,12 +1746,10 @@ tft_status poly_mul_padded(tft_ctx* ctx, const void* A, size_t m, const void* B,
     tft_status s = check_len(ctx, m + nb - 1);
     if (s != TFT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4)
-            return padded_mul_impl<tft::ModU32>(ctx, (const uint32_t*)A, m, (const uint32_t*)B, nb, (uint32_t*)X,
-                                                (uint32_t*)Apad, (uint32_t*)Bpad, st);
-        return padded_mul_impl<tft::ModGL>(ctx, (const uint64_t*)A, m, (const uint64_t*)B, nb, (uint64_t*)X,
-                                           (uint64_t*)Apad, (uint64_t*)Bpad, st);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        using Word = typename Mod::Word;
+        return padded_mul_impl<Mod>(ctx, (const Word*)A, m, (const Word*)B, nb, (Word*)X, (Word*)Apad, (Word*)Bpad, st);
     });
 }
 
@@ -1771,7 +1788,7 @@ tft_status tft_batch_run(tft_batch* B, void* stream) {
     if (!B) return TFT_EINVAL;
     DeviceGuard guard(B->ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    return B->ctx->wbytes == 4 ? batch_run<tft::ModU32>(B, st) : batch_run<tft::ModGL>(B, st);
+    return with_mod(B->ctx, [&](auto mt) { return batch_run<decltype(mt)>(B, st); });
 }
 
 tft_status tft_batch_info(const tft_batch* B, tft_batch_desc* out) {
@@ -1813,8 +1830,9 @@ tft_status tft_walk_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t 
     }
     if (!count) return TFT_OK;
     DeviceGuard guard(ctx->device);
-    if (ctx->wbytes == 4) return walk_impl<tft::ModU32>(ctx, X, n, count, inverse, (hipStream_t)stream);
-    return walk_impl<tft::ModGL>(ctx, X, n, count, inverse, (hipStream_t)stream);
+    return with_mod(ctx, [&](auto mt) {
+        return walk_impl<decltype(mt)>(ctx, X, n, count, inverse, (hipStream_t)stream);
+    });
 }
 
 tft_status tft_from_signed(tft_ctx* ctx, const int64_t* src, size_t n, void* dst, void* stream) {
@@ -2046,11 +2064,10 @@ tft_status poly_mul_restricted(tft_ctx* ctx, const void* A, size_t m, const void
     tft_status s = check_len(ctx, m + nb - 1);
     if (s != TFT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    return dispatch(ctx, [&] {
-        if (ctx->wbytes == 4)
-            return mul_restricted_impl<tft::ModU32>(ctx, (const uint32_t*)A, m, (const uint32_t*)B, nb, (uint32_t*)X,
-                                                    st);
-        return mul_restricted_impl<tft::ModGL>(ctx, (const uint64_t*)A, m, (const uint64_t*)B, nb, (uint64_t*)X, st);
+    return dispatch(ctx, [&](auto mt) {
+        using Mod = decltype(mt);
+        using Word = typename Mod::Word;
+        return mul_restricted_impl<Mod>(ctx, (const Word*)A, m, (const Word*)B, nb, (Word*)X, st);
     });
 }
 
@@ -2243,10 +2260,12 @@ tft_status tft_calibrate(tft_ctx* ctx, tft_calibration* out) {
     const double t_valu = timed([&] { tft::k_cal_valu<<<blocks, tft::kCalThreads>>>((uint32_t*)o, 3u, it_alu); });
     const double t_mad = timed([&] { tft::k_cal_mad64<<<blocks, tft::kCalThreads>>>((uint32_t*)o, 3u, it_alu); });
     const double t_bf = timed([&] {
-        if (ctx->wbytes == 8)
-            tft::k_cal_bfly<tft::ModGL><<<blocks, tft::kCalThreads>>>(ctx->m64, (uint64_t*)x, (const uint64_t*)tw, it_bf);
-        else
-            tft::k_cal_bfly<tft::ModU32><<<blocks, tft::kCalThreads>>>(ctx->m32, (uint32_t*)x, (const uint32_t*)tw, it_bf);
+        (void)with_mod(ctx, [&](auto mt) {
+            using Mod = decltype(mt);
+            using Word = typename Mod::Word;
+            tft::k_cal_bfly<Mod><<<blocks, tft::kCalThreads>>>(mod_of<Mod>(ctx), (Word*)x, (const Word*)tw, it_bf);
+            return TFT_OK;
+        });
     });
     const double t_copy = timed([&] {
         tft::k_cal_copy<<<2048, tft::kCalThreads>>>((uint4*)dst, (const uint4*)src, copy_words);

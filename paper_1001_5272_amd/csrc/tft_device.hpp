@@ -99,6 +99,45 @@ struct ModU32 {
     __device__ __forceinline__ Word one_tw() const { return mont(1u, r2); }   // 1 in twiddle (Montgomery) form
 };
 
+// ------------------------------------------------ other primes p < 2^63
+// Residues in [0, p), 2^31 < p < 2^63 odd: 64-bit Montgomery arithmetic
+// (R = 2^64), twiddles in Montgomery form (w 2^64 mod p), as ModU32 with
+// words of 64 bits.  p < 2^63 keeps a + b and the reduction's (t + m p) / R
+// below 2^64.
+struct ModM64 {
+    using Word = uint64_t;
+    uint64_t p;        // modulus
+    uint64_t pneg;     // -p^-1 mod 2^64
+    uint64_t r2;       // 2^128 mod p
+    uint64_t halfp1;   // (p + 1) / 2
+
+    __device__ __forceinline__ Word add(Word a, Word b) const {
+        const Word s = a + b;                 // < 2p < 2^64
+        return s >= p ? s - p : s;
+    }
+    __device__ __forceinline__ Word sub(Word a, Word b) const {
+        const Word d = a - b;
+        return a < b ? d + p : d;
+    }
+    // Montgomery product a b 2^-64 mod p for a < 2^64, b < p: with
+    // m = (a b mod 2^64) pneg mod 2^64, a b + m p is a multiple of 2^64 and
+    // (a b + m p) / 2^64 < 2p.
+    __device__ __forceinline__ Word mont(Word a, Word b) const {
+        const unsigned __int128 t = (unsigned __int128)a * b;
+        const uint64_t lo = (uint64_t)t, hi = (uint64_t)(t >> 64);
+        const uint64_t m = lo * pneg;
+        const uint64_t mh = (uint64_t)(((unsigned __int128)m * p) >> 64);
+        const uint64_t u = hi + mh + (lo != 0u ? 1u : 0u);   // the low words sum to 0 or 2^64
+        return u >= p ? u - p : u;
+    }
+    __device__ __forceinline__ Word mul_tw(Word a, Word twm) const { return mont(a, twm); }
+    __device__ __forceinline__ Word tw_mul_tw(Word t1, Word t2) const { return mont(t1, t2); }
+    // plain product of two residues
+    __device__ __forceinline__ Word mul(Word a, Word b) const { return mont(mont(a, b), r2); }
+    __device__ __forceinline__ Word half(Word x) const { return (x >> 1) + ((x & 1u) ? halfp1 : 0u); }
+    __device__ __forceinline__ Word one_tw() const { return mont(1u, r2); }   // 2^64 mod p
+};
+
 // ------------------------------------------------- p = 2^64 - 2^32 + 1
 // Residues in [0, p).  2^64 = 2^32 - 1 and 2^96 = -1 modulo p, so a 128-bit
 // product reduces with shifts, adds and subtracts only.

@@ -25,4 +25,8 @@ PRIMES = {
     "p2013265921": (2013265921, 31),
     "p1811939329": (1811939329, 13),
     "goldilocks": (2**64 - 2**32 + 1, 7),
+    # other primes of 8-byte words (64-bit Montgomery arithmetic): just below
+    # 2^63 with 2-adic order 32, and a 62-bit one of order 35
+    "p63": (9223372006790004737, 3),
+    "p62": (2478761244408938497, 5),
 }

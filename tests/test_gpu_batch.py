@@ -121,6 +121,28 @@ def test_poly_mul_batch_convenience(ctxgl):
         assert (X.cpu().numpy().astype(np.uint64) == expected(p, g, A, B)).all()
 
 
+def test_batch_products_64bit_montgomery_prime():
+    # a prime of 8-byte words other than 2^64 - 2^32 + 1: the batch's
+    # single-workgroup and two-pass products in 64-bit Montgomery arithmetic,
+    # every product against the oracle
+    p, g = PRIMES["p63"]
+    ctx = libtft.Context(p, g)
+    try:
+        lens = seeded_lengths(60, 1, 12000, 78) + [(1, 1), (4096, 4097), (9000, 9000), (1, 30000)]
+        print(f"[gpu] batch of {len(lens)} products, p63", flush=True)
+        jobs, host = make_jobs(ctx, p, lens, 700)
+        b = libtft.Batch(ctx, jobs)
+        info = b.info()
+        assert info["single_workgroup"] > 0 and info["two_pass"] > 0, info
+        b.run()
+        torch.cuda.synchronize()
+        for (A, B), (_, _, X, _) in zip(host, jobs):
+            assert (X.cpu().numpy().astype(np.uint64) == expected(p, g, A, B)).all(), (len(A), len(B))
+        b.close()
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("which", ["p998244353", "goldilocks"])
 def test_forward_batch(ctx998, ctxgl, which):
     ctx = ctx998 if which == "p998244353" else ctxgl

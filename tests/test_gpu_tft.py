@@ -20,7 +20,8 @@ def ctxs():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     out = {name: libtft.Context(*PRIMES[name]) for name in
-           ["p998244353", "goldilocks", "p12289", "p7681", "p2013265921", "p469762049", "p1811939329"]}
+           ["p998244353", "goldilocks", "p63", "p62", "p12289", "p7681", "p2013265921", "p469762049",
+            "p1811939329"]}
     yield out
     for c in out.values():
         c.close()
@@ -37,7 +38,7 @@ def check_roundtrip(ctx, p, g, n, seed, direct=False):
     assert len(bad) == 0, f"p={p} n={n}: {len(bad)} inverse mismatches, first at {bad[:5]}"
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p63"])
 def test_every_small_length(ctxs, name):
     p, g = PRIMES[name]
     ctx = ctxs[name]
@@ -46,7 +47,7 @@ def test_every_small_length(ctxs, name):
         check_roundtrip(ctx, p, g, n, seed=n, direct=(n <= 64))
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p63"])
 def test_single_workgroup_sizes(ctxs, name):
     p, g = PRIMES[name]
     ctx = ctxs[name]
@@ -55,7 +56,7 @@ def test_single_workgroup_sizes(ctxs, name):
         check_roundtrip(ctx, p, g, n, seed=7 * n)
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p63"])
 @pytest.mark.parametrize("logW", [3, 4, 5, 6, 7])
 def test_two_pass_forced_small(ctxs, name, logW):
     # the two-pass schedule at sizes the oracle handles quickly: many column
@@ -86,7 +87,7 @@ def test_two_pass_forced_small(ctxs, name, logW):
         libtft.tft_set_plan_override(ctx, 0)
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p63"])
 @pytest.mark.parametrize("logW", [8, 9, 10])
 def test_two_pass_general_b_tiles(ctxs, name, logW):
     # general last rows with more than 128 columns c < b, so the columns run
@@ -111,7 +112,7 @@ def test_two_pass_general_b_tiles(ctxs, name, logW):
         libtft.tft_set_plan_override(ctx, 0)
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p63"])
 def test_two_pass_planner_sizes(ctxs, name):
     p, g = PRIMES[name]
     ctx = ctxs[name]
@@ -121,7 +122,7 @@ def test_two_pass_planner_sizes(ctxs, name):
         check_roundtrip(ctx, p, g, n, seed=3 * n)
 
 
-@pytest.mark.parametrize("name", ["p12289", "p7681", "p2013265921", "p469762049", "p1811939329"])
+@pytest.mark.parametrize("name", ["p12289", "p7681", "p2013265921", "p469762049", "p1811939329", "p62"])
 def test_other_primes(ctxs, name):
     p, g = PRIMES[name]
     ctx = ctxs[name]
@@ -134,7 +135,7 @@ def test_other_primes(ctxs, name):
         check_roundtrip(ctx, p, g, n, seed=n + 5)
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p63"])
 def test_products(ctxs, name):
     p, g = PRIMES[name]
     ctx = ctxs[name]
@@ -147,7 +148,7 @@ def test_products(ctxs, name):
         assert (C == ref).all(), f"product {m}x{nb} mismatches at {np.nonzero(C != ref)[0][:5]}"
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p63"])
 def test_restricted_products(ctxs, name):
     # section 5's space-restricted product (Algorithm 3): X is the only memory
     # written; blocks at global index q/L include two-pass ones with q > 0
@@ -163,7 +164,7 @@ def test_restricted_products(ctxs, name):
         assert (C == ref).all(), f"restricted product {m}x{nb} mismatches at {np.nonzero(C != ref)[0][:5]}"
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p63"])
 def test_restricted_tail_nodes(ctxs, name):
     # the restricted product's last positions (t = r - q < 2^18 of them) come
     # from one or two aligned nodes: single-workgroup nodes of S = 2^13 words
@@ -199,9 +200,13 @@ def test_rejects_bad_arguments(ctxs):
     assert e.value.status == libtft.TFT_ERANGE
     with pytest.raises(libtft.TftError):
         libtft.Context(998244353, 4)                   # 4 is a square: not a generator
+    for p in [(1 << 63) + 29, (1 << 61) - 3, 9223372006790004739]:   # beyond 2^63, composite, composite
+        with pytest.raises(libtft.TftError) as e:
+            libtft.Context(p, 3)
+        assert e.value.status == libtft.TFT_ERANGE
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p63"])
 def test_buffered_comparator(ctxs, name):
     # van der Hoeven-style buffered transforms (2^ceil(lg n)-word buffer): the
     # same outputs as the oracle, the inverse restores the input, for every

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 libtft = pytest.importorskip("paper_1001_5272_amd.libtft")
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p63"])
 def test_walk_matches_oracle(name):
     import torch
     if not torch.cuda.is_available():
