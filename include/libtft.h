@@ -233,9 +233,10 @@ tft_status tft_walk_batch(tft_ctx* ctx, void* const* X, const size_t* n, size_t 
  * batches' work lists, grown as needed, so a batch in steady state allocates
  * and frees nothing.  poll reports completion without blocking; wait blocks;
  * completion_ns gives the steady-clock time (ns) at which the worker saw the
- * request complete (0 while pending).  A request whose batch failed reports
- * TFT_EDEVICE.  stats: `rejected` counts submits refused for footprint.
- * destroy waits for all submitted requests. */
+ * request complete (0 while pending); the queue keeps that time, 8 bytes per
+ * request ever submitted, until it is destroyed.  A request whose batch
+ * failed reports TFT_EDEVICE.  stats: `rejected` counts submits refused for
+ * footprint.  destroy waits for all submitted requests. */
 typedef struct tft_queue tft_queue;
 typedef struct {
     uint64_t submitted, completed, batches, rejected, pending, inflight, pool_words, pool_used_max;

@@ -1371,8 +1371,13 @@ struct tft_queue {
     std::deque<QBatch> inflight;
     size_t inflight_reqs;
     PoolAlloc alloc;
-    std::unordered_map<uint64_t, uint64_t> done_ns;   // ticket -> completion time (steady clock)
-    std::unordered_map<uint64_t, int> failed;
+    // completion time (steady clock, ns; 0 while pending) of ticket t at
+    // done_ns[t - 1]: tickets are consecutive, so a deque indexed by ticket
+    // grows by one word per request without rehashing or moving what it
+    // holds (a hash map's rehash at a million entries took tens of ms under
+    // the queue's lock, stalling the client and the worker alike)
+    std::deque<uint64_t> done_ns;
+    std::unordered_map<uint64_t, int> failed;   // tickets whose batch failed
     uint64_t next_ticket;
     bool stop;
     std::thread worker;
@@ -1402,7 +1407,7 @@ void queue_worker(tft_queue* q) {
             }
             const uint64_t t = now_ns();
             for (const QReq& rq : it->reqs) {
-                q->done_ns[rq.ticket] = t;
+                q->done_ns[rq.ticket - 1] = t;
                 if (e != hipSuccess) q->failed[rq.ticket] = 1;
                 if (rq.off != ~0ull) q->alloc.release(rq.off, rq.r);
             }
@@ -1454,7 +1459,7 @@ void queue_worker(tft_queue* q) {
                     if (B) tft_batch_destroy(B);
                     const uint64_t t = now_ns();
                     for (const QReq& rq : group) {
-                        q->done_ns[rq.ticket] = t;
+                        q->done_ns[rq.ticket - 1] = t;
                         q->failed[rq.ticket] = 1;
                         if (rq.off != ~0ull) q->alloc.release(rq.off, rq.r);
                     }
@@ -1948,6 +1953,7 @@ tft_status tft_queue_submit(tft_queue* q, const tft_mul_desc* d, void* hip_strea
         return TFT_EDEVICE;
     }
     rq.ticket = q->next_ticket++;
+    q->done_ns.push_back(0);
     q->pending.push_back(rq);
     q->n_submitted++;
     *ticket = rq.ticket;
@@ -1958,8 +1964,7 @@ tft_status tft_queue_submit(tft_queue* q, const tft_mul_desc* d, void* hip_strea
 tft_status tft_queue_poll(tft_queue* q, uint64_t ticket, int* done) {
     if (!q || !done) return TFT_EINVAL;
     std::lock_guard<std::mutex> lk(q->mu);
-    auto it = q->done_ns.find(ticket);
-    *done = it != q->done_ns.end();
+    *done = ticket >= 1 && ticket <= q->done_ns.size() && q->done_ns[ticket - 1] != 0;
     if (*done && q->failed.count(ticket)) return TFT_EDEVICE;
     return TFT_OK;
 }
@@ -1968,15 +1973,14 @@ tft_status tft_queue_wait(tft_queue* q, uint64_t ticket) {
     if (!q || ticket == 0) return TFT_EINVAL;
     std::unique_lock<std::mutex> lk(q->mu);
     if (ticket >= q->next_ticket) return TFT_EINVAL;
-    q->cv_done.wait(lk, [&] { return q->done_ns.count(ticket) != 0; });
+    q->cv_done.wait(lk, [&] { return q->done_ns[ticket - 1] != 0; });
     return q->failed.count(ticket) ? TFT_EDEVICE : TFT_OK;
 }
 
 tft_status tft_queue_completion_ns(tft_queue* q, uint64_t ticket, uint64_t* ns) {
     if (!q || !ns) return TFT_EINVAL;
     std::lock_guard<std::mutex> lk(q->mu);
-    auto it = q->done_ns.find(ticket);
-    *ns = it == q->done_ns.end() ? 0 : it->second;
+    *ns = ticket >= 1 && ticket <= q->done_ns.size() ? q->done_ns[ticket - 1] : 0;
     return TFT_OK;
 }
 
