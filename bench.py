@@ -288,7 +288,7 @@ def main():
         skip = set(x for x in args.skip.split(",") if x)
         result.update(extras(ctx, bufs, host, p, skip))
         if "sweep" not in skip:
-            result["sweep"] = length_sweep(ctx, p)
+            result["sweep"] = length_sweep(ctx, p, autotune=not args.no_autotune)
         if "batched" not in skip:
             result["batched"] = batched_c3()
         if "served" not in skip:
@@ -489,7 +489,7 @@ def small_c1(dev):
     return res
 
 
-def length_sweep(ctx, p, per_octave=16):
+def length_sweep(ctx, p, per_octave=16, autotune=True):
     """TFT+ITFT time at lengths spread through [2^21, 2^23] (the jump-free
     curve) next to the padded comparator; the summary gives the mean rate,
     the largest time step between adjacent lengths and the lengths where the
@@ -501,6 +501,22 @@ def length_sweep(ctx, p, per_octave=16):
     print("[bench] length sweep", file=sys.stderr, flush=True)
     ns = sorted({int(round(2 ** (21 + i / per_octave))) for i in range(2 * per_octave + 1)} |
                 {(1 << 22) - 1, (1 << 22) + 1, (1 << 21) + 1})
+    # the library's tuning as a user would apply it: every plan-cache bucket
+    # the sweep meets (a quarter octave, or a power of two's own slot) is
+    # autotuned once, at the middle one of its sweep lengths; buckets the timed
+    # step already tuned keep their plans
+    tuned = {}
+    if autotune:
+        members = {}
+        for n in ns:
+            members.setdefault(libtft.tft_plan_bucket(n), []).append(n)
+        for bk, group in sorted(members.items()):
+            if libtft.tft_plan_cache_get(ctx, bk):
+                tuned[bk] = "kept"
+                continue
+            rep = group[len(group) // 2]
+            libtft.tft_autotune(ctx, rep)
+            tuned[bk] = rep
     pad = torch.empty(1 << 23, dtype=torch.uint64, device="cuda")
     out = []
     for n in ns:
@@ -511,14 +527,16 @@ def length_sweep(ctx, p, per_octave=16):
         pad[:n].copy_(X)
         tb = event_time(lambda: (libtft.tft_buffered_forward(ctx, pad[:L], n),
                                  libtft.tft_buffered_inverse(ctx, pad[:L], n)), 5)
-        out.append({"n": n, "tft_itft_us": round(t * 1e3, 1), "padded_us": round(tp * 1e3, 1),
+        out.append({"n": n, "logW": libtft.tft_plan_info(ctx, n)["logW"],
+                    "tft_itft_us": round(t * 1e3, 1), "padded_us": round(tp * 1e3, 1),
                     "buffered_us": round(tb * 1e3, 1), "mem_words": n, "padded_mem_words": n + L,
                     "buffered_mem_words": L,
                     "gbfly_s": round(2 * nominal_butterflies(n) / (t * 1e-3) / 1e9, 1)})
         del X
     steps = [(b["tft_itft_us"] / a["tft_itft_us"], a["n"], b["n"]) for a, b in zip(out, out[1:])]
     worst = max(steps)
-    summary = {"points": len(out), "mean_gbfly_s": round(sum(d["gbfly_s"] for d in out) / len(out), 1),
+    summary = {"points": len(out), "autotuned_quarter_octaves": {str(k): v for k, v in sorted(tuned.items())},
+               "mean_gbfly_s": round(sum(d["gbfly_s"] for d in out) / len(out), 1),
                "max_adjacent_step": {"ratio": round(worst[0], 3), "from_n": worst[1], "to_n": worst[2]},
                "slower_than_padded": [d["n"] for d in out if d["tft_itft_us"] > d["padded_us"]]}
     return {"points": out, "summary": summary}

@@ -303,7 +303,9 @@ tft_status tft_set_plan_override(tft_ctx* ctx, unsigned logW);
  * 0-4 (0: the planner's choice), log2 columns per tile in bits 5-7, log2 words
  * per row thread in bits 8-10 and stages per LDS round trip in bits 11-12 (0
  * in a field: the default), so that a caller can store tuned plans and load
- * them into a new context; tft_plan_bucket gives the bucket of a length. */
+ * them into a new context; tft_plan_bucket gives the bucket of a length:
+ * floor(4 lg n) (quarter octaves), and 4 * 28 + 4 + k for n = 2^k (a power
+ * of two has no partial last row, so it keeps a plan of its own). */
 tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen);
 /* Batch autotuner.  Runs the batch of `count` descriptors (as tft_batch_create
  * and tft_batch_run would: products if `products`, else forward transforms)

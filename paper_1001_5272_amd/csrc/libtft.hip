@@ -55,7 +55,9 @@ namespace {
 
 constexpr uint64_t kGoldilocks = 0xFFFFFFFF00000001ull;
 constexpr unsigned kMaxLog2 = 28;               // longest transform supported by the tables
-constexpr unsigned kPlanBuckets = 4 * kMaxLog2 + 4;   // plan cache: quarter octaves of n
+// plan cache: quarter octaves of n, then one slot per power of two
+constexpr unsigned kPow2Buckets = 4 * kMaxLog2 + 4;
+constexpr unsigned kPlanBuckets = kPow2Buckets + kMaxLog2 + 1;
 constexpr size_t kVWords = size_t(1) << 16;          // V_c area: one word per column, W <= 2^16
 // V_c area, then the column polynomial Q of the general last-row step (two
 // buffers of kQStride words and 1 / Q(w_a))
@@ -232,9 +234,13 @@ void launch(tft_ctx* ctx, int kid, Kernel kernel, dim3 grid, dim3 block, size_t 
 
 unsigned small_max_log2(unsigned wbytes) { return wbytes == 4 ? 13 : 12; }
 
-// Plan-cache bucket of a length: floor(4 lg n) (quarter octaves), exactly.
+// Plan-cache bucket of a length: floor(4 lg n) (quarter octaves), exactly;
+// a power of two 2^e has a slot of its own, kPow2Buckets + e: with b = 0 its
+// passes have no partial last row, and the plan that suits it is not the one
+// that suits the truncated lengths just above it.
 unsigned plan_bucket(uint64_t n) {
     const unsigned e = 63u - (unsigned)__builtin_clzll(n);
+    if ((n & (n - 1)) == 0) return kPow2Buckets + e;
     const u128 n4 = (u128)n * n * n * n;
     unsigned j = 0;
     while (j < 3 && n4 >= ((u128)1 << (4 * e + j + 1))) j++;

@@ -3,7 +3,8 @@
 Argument marshalling only: every step of the transform runs in the HIP
 kernels of ``libtft.so``.  PyTorch supplies device memory (tensors) and
 streams; tensors must be contiguous ``torch.uint32`` (primes below 2^31) or
-``torch.uint64`` (p = 2^64 - 2^32 + 1) on the context's device.  Functions
+``torch.uint64`` (p = 2^64 - 2^32 + 1 and the other primes below 2^63) on the
+context's device.  Functions
 carry the names of the C entry points; a failing status raises ``TftError``.
 
 There is no fallback: if ``libtft.so`` has not been built, or no GPU is
@@ -275,7 +276,8 @@ def tft_autotune(ctx: Context, n: int) -> dict:
     """Time candidate plans for length n (column width W = 2^logW near the
     planner's choice, then columns per tile, threads per row and stages per
     LDS round trip) and cache the fastest for every length in the same
-    quarter octave (tft_plan_bucket); returns the resulting plan."""
+    quarter octave (or, for a power of two, its own slot: tft_plan_bucket);
+    returns the resulting plan."""
     d = PlanDesc()
     _check(load().tft_autotune(ctx.handle, n, ctypes.byref(d)), "tft_autotune")
     return {f: getattr(d, f) for f, _ in PlanDesc._fields_}
@@ -304,14 +306,15 @@ def tft_plan_cache_set(ctx: Context, bucket: int, logW: int):
 
 
 def tft_plan_bucket(n: int) -> int:
-    """Plan-cache bucket of a length: floor(4 lg n)."""
+    """Plan-cache bucket of a length: floor(4 lg n), or 4 * 28 + 4 + k for
+    n = 2^k."""
     return int(load().tft_plan_bucket(n))
 
 
 def plan_cache_dump(ctx: Context) -> dict:
     """The context's tuned plans as {bucket: plan code} (JSON-ready)."""
     out = {}
-    for k in range(0, 4 * 28 + 4):
+    for k in range(0, 4 * 28 + 4 + 29):   # quarter octaves, then one slot per power of two
         v = tft_plan_cache_get(ctx, k)
         if v:
             out[k] = v

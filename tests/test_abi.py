@@ -47,11 +47,15 @@ def test_strerror_without_device():
 
 
 def test_plan_bucket_without_device():
-    # floor(4 lg n), exactly: the largest t with n^4 >= 2^t
+    # floor(4 lg n), exactly: the largest t with n^4 >= 2^t; a power of two
+    # 2^k has the slot 4 * 28 + 4 + k of its own
     lib = ctypes.CDLL(LIB)
     lib.tft_plan_bucket.restype = ctypes.c_uint
     lib.tft_plan_bucket.argtypes = [ctypes.c_size_t]
     for n in [1, 2, 3, 4, 5, 7, 8, 9, 100003, (1 << 22) - 1, 1 << 22, (1 << 22) + 1, 3 << 21, 5931642, (1 << 28)]:
+        if n & (n - 1) == 0:
+            assert lib.tft_plan_bucket(n) == 4 * 28 + 4 + n.bit_length() - 1, n
+            continue
         t = 0
         while n ** 4 >= 2 ** (t + 1):
             t += 1
