@@ -29,7 +29,7 @@ def test_schoolbook_against_numpy(name):
             assert oracle.mul_coeff(p, A, B, s) == ref[s]
 
 
-@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p1811939329"])
+@pytest.mark.parametrize("name", ["p998244353", "goldilocks", "p1811939329", "p63"])
 def test_padded_product_against_schoolbook_full_range(name):
     p, g = PRIMES[name]
     rng = random.Random(2)

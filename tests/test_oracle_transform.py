@@ -49,7 +49,7 @@ def test_golden_cases():
         assert [int(x) for x in oracle.itft_inplace(17, 3, c["X"])] == c["F"]
 
 
-@pytest.mark.parametrize("name", ["p17", "p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p17", "p998244353", "goldilocks", "p63"])
 def test_monomials(name):
     p, g = PRIMES[name]
     n = 13 if p > 17 else 9
@@ -60,7 +60,7 @@ def test_monomials(name):
         assert [int(x) for x in X] == [pow(py_omega(p, g, s), t, p) for s in range(n)]
 
 
-@pytest.mark.parametrize("name", ["p17", "p257", "p998244353", "goldilocks"])
+@pytest.mark.parametrize("name", ["p17", "p257", "p998244353", "goldilocks", "p63"])
 def test_closed_form_inverse_dft_at_power_of_two(name):
     # n = N = 2^k: sum_s X_s w_s^(-t) = N F_t (orthogonality of N-th roots)
     p, g = PRIMES[name]
