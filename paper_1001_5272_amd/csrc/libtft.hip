@@ -1871,9 +1871,15 @@ tft_status tft_crt3(tft_ctx* const ctxs[3], const void* r1, const void* r2, cons
     c.p1 = p1;
     c.p2 = p2;
     c.p3 = p3;
-    c.inv_p1_mod_p2 = powmod_h(p1 % p2, p2 - 2, p2);
-    c.p1p2_mod_p3 = mulmod_h(p1 % p3, p2 % p3, p3);
-    c.inv_p1p2_mod_p3 = powmod_h(c.p1p2_mod_p3, p3 - 2, p3);
+    c.m2 = ctxs[1]->m32;
+    c.m3 = ctxs[2]->m32;
+    const uint64_t inv12 = powmod_h(p1 % p2, p2 - 2, p2);
+    const uint64_t inv123 = powmod_h(mulmod_h(p1 % p3, p2 % p3, p3), p3 - 2, p3);
+    c.inv12_m = (uint32_t)(((u128)inv12 << 32) % p2);
+    c.inv123_m = (uint32_t)(((u128)inv123 << 32) % p3);
+    c.b2 = (uint32_t)((1ull << 32) / p2);
+    c.b3 = (uint32_t)((1ull << 32) / p3);
+    c.p1p2 = p1 * p2;
     c.M = (u128)p1 * p2 * p3;
     c.half_M = (c.M + 1) / 2;
     tft_ctx* ctx = ctxs[0];

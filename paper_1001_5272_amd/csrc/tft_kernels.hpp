@@ -1494,24 +1494,37 @@ __global__ __launch_bounds__(kThreads) void k_from_signed(Word* dst, const int64
 // output is the signed representative in [-M/2, M/2), little-endian 128-bit.
 struct Crt3 {
     uint64_t p1, p2, p3;
-    uint64_t inv_p1_mod_p2, inv_p1p2_mod_p3, p1p2_mod_p3;
+    ModU32 m2, m3;              // 32-bit Montgomery arithmetic modulo p2 and p3
+    uint32_t inv12_m;           // p1^-1 mod p2, Montgomery form (x 2^32 mod p2)
+    uint32_t inv123_m;          // (p1 p2)^-1 mod p3, Montgomery form
+    uint32_t b2, b3;            // floor(2^32 / p2), floor(2^32 / p3)
+    uint64_t p1p2;              // p1 p2 < 2^62
     unsigned __int128 M, half_M;
 };
-__device__ __forceinline__ uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t p) {
-    return (uint64_t)(((unsigned __int128)a * b) % p);
+// x mod p for x < 2^32, p < 2^31, b = floor(2^32 / p): the quotient estimate
+// floor(x b / 2^32) is at most one short, so one conditional subtraction.
+__device__ __forceinline__ uint32_t barrett32(uint32_t x, uint32_t p, uint32_t b) {
+    const uint32_t r = x - __umulhi(x, b) * p;
+    return r >= p ? r - p : r;
 }
+// Garner's mixed-radix reconstruction, one coefficient per thread:
+// x = a1 + p1 t2 + p1 p2 t3 with t2 = (a2 - a1) / p1 mod p2 and
+// t3 = (a3 - (a1 + p1 t2)) / (p1 p2) mod p3, then the signed representative in
+// (-M/2, M/2].  Every reduction is a 32-bit Barrett step or a Montgomery
+// product (no 64- or 128-bit division).
 __global__ __launch_bounds__(kThreads) void k_crt3(Crt3 c, const uint32_t* r1, const uint32_t* r2, const uint32_t* r3,
                                                   uint64_t* out, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)nthreads() + threadIdx.x; i < n; i += (uint64_t)gridDim.x * nthreads()) {
-        const uint64_t a1 = r1[i], a2 = r2[i], a3 = r3[i];
-        const uint64_t d2 = (a2 + c.p2 - a1 % c.p2) % c.p2;
-        const uint64_t t2 = mulmod64(d2, c.inv_p1_mod_p2, c.p2);
-        const uint64_t x12 = a1 + c.p1 * t2;                         // < p1 p2 < 2^62
-        const uint64_t x12m = x12 % c.p3;
-        const uint64_t d3 = (a3 + c.p3 - x12m) % c.p3;
-        const uint64_t t3 = mulmod64(d3, c.inv_p1p2_mod_p3, c.p3);
-        unsigned __int128 x = (unsigned __int128)x12 + (unsigned __int128)(c.p1 * c.p2) * t3;
-        if (x >= c.half_M) x -= c.M;                                 // two's complement wrap to signed
+        const uint32_t a1 = r1[i], a2 = r2[i], a3 = r3[i];
+        const uint32_t d2 = c.m2.sub(a2, barrett32(a1, (uint32_t)c.p2, c.b2));
+        const uint32_t t2 = c.m2.mont(d2, c.inv12_m);
+        const uint64_t x12 = a1 + c.p1 * t2;                                  // < p1 p2 < 2^62
+        // x12 mod p3 = (hi 2^32 + lo) mod p3, hi < 2^30: mont(hi, 2^64 mod p3) = hi 2^32 mod p3
+        const uint32_t hi = (uint32_t)(x12 >> 32), lo = (uint32_t)x12;
+        const uint32_t x12m = c.m3.add(c.m3.mont(hi, c.m3.r2), barrett32(lo, (uint32_t)c.p3, c.b3));
+        const uint32_t t3 = c.m3.mont(c.m3.sub(a3, x12m), c.inv123_m);
+        unsigned __int128 x = (unsigned __int128)x12 + (unsigned __int128)c.p1p2 * t3;
+        if (x >= c.half_M) x -= c.M;                                          // two's complement wrap to signed
         out[2 * i] = (uint64_t)x;
         out[2 * i + 1] = (uint64_t)(x >> 64);
     }

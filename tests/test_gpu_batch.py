@@ -186,6 +186,39 @@ def test_convenience_calls_reuse_work_list_memory(ctxgl):
         assert (X.cpu().numpy().astype(np.uint64) == expected(p, g, A, B)).all()
 
 
+def test_crt3_random_residues():
+    # Garner's reconstruction alone: random residue triples (and the edges 0,
+    # -1, (M-1)/2, (M+1)/2) against the Chinese remainder by Python integers,
+    # as the signed representative in (-M/2, M/2]
+    ctxs = [libtft.Context(p, g) for p, g in synth.CRT_PRIMES]
+    try:
+        (p1, _), (p2, _), (p3, _) = synth.CRT_PRIMES
+        M = p1 * p2 * p3
+        n = 100000
+        rs = [synth.residues(p, n, 8100 + i).astype(np.uint32) for i, (p, _) in enumerate(synth.CRT_PRIMES)]
+        edges = [0, M - 1, (M - 1) // 2, (M + 1) // 2, p1, p1 * p2, M - p1 * p2]
+        for k, v in enumerate(edges):
+            for r, (p, _) in zip(rs, synth.CRT_PRIMES):
+                r[k] = v % p
+        dev = [torch.from_numpy(r).cuda() for r in rs]
+        out = torch.empty(2 * n, dtype=torch.int64, device="cuda")
+        libtft.tft_crt3(ctxs, dev[0], dev[1], dev[2], out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint64)
+        e1, e2, e3 = [(M // p) * pow(M // p, -1, p) for p in (p1, p2, p3)]   # idempotents of Z/M
+        for i in range(n):
+            x = (int(rs[0][i]) * e1 + int(rs[1][i]) * e2 + int(rs[2][i]) * e3) % M
+            if x > M // 2:
+                x -= M
+            v = (int(got[2 * i + 1]) << 64) | int(got[2 * i])
+            if v >= 1 << 127:
+                v -= 1 << 128
+            assert v == x, (i, [int(r[i]) for r in rs])
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def test_exact_integer_product_crt():
     ctxs = [libtft.Context(p, g) for p, g in synth.CRT_PRIMES]
     try:
