@@ -1852,8 +1852,8 @@ tft_status tft_from_signed(tft_ctx* ctx, const int64_t* src, size_t n, void* dst
     hipStream_t st = (hipStream_t)stream;
     uint64_t blocks = std::min<uint64_t>((n + kThreads - 1) / kThreads, 8192);
     if (ctx->wbytes == 4)
-        launch(ctx, TFT_K_COPY, tft::k_from_signed<uint32_t>, dim3((uint32_t)blocks), dim3(kThreads), 0, st,
-               (uint32_t*)dst, src, (uint64_t)n, ctx->p);
+        launch(ctx, TFT_K_COPY, tft::k_from_signed32, dim3((uint32_t)blocks), dim3(kThreads), 0, st, ctx->m32,
+               (uint32_t)((1ull << 32) / ctx->p), (uint32_t*)dst, src, (uint64_t)n);
     else
         launch(ctx, TFT_K_COPY, tft::k_from_signed<uint64_t>, dim3((uint32_t)blocks), dim3(kThreads), 0, st,
                (uint64_t*)dst, src, (uint64_t)n, ctx->p);

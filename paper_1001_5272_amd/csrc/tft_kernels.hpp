@@ -1488,6 +1488,25 @@ __global__ __launch_bounds__(kThreads) void k_from_signed(Word* dst, const int64
     }
 }
 
+// The same for primes below 2^31 without 64-bit division: |v| = hi 2^32 + lo,
+// hi 2^32 mod p = mont(hi, 2^64 mod p), lo mod p by a 32-bit Barrett step
+// (barrett32, b = floor(2^32 / p)), then the sign.
+// x mod p for x < 2^32, p < 2^31, b = floor(2^32 / p): the quotient estimate
+// floor(x b / 2^32) is at most one short, so one conditional subtraction.
+__device__ __forceinline__ uint32_t barrett32(uint32_t x, uint32_t p, uint32_t b) {
+    const uint32_t r = x - __umulhi(x, b) * p;
+    return r >= p ? r - p : r;
+}
+__global__ __launch_bounds__(kThreads) void k_from_signed32(ModU32 md, uint32_t b, uint32_t* dst, const int64_t* src,
+                                                           uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)nthreads() + threadIdx.x; i < n; i += (uint64_t)gridDim.x * nthreads()) {
+        const int64_t v = src[i];
+        const uint64_t u = v >= 0 ? (uint64_t)v : 0u - (uint64_t)v;   // |v| (2^63 for INT64_MIN)
+        const uint32_t r = md.add(md.mont((uint32_t)(u >> 32), md.r2), barrett32((uint32_t)u, md.p, b));
+        dst[i] = v >= 0 ? r : md.sub(0u, r);
+    }
+}
+
 // Chinese remaindering of three residue vectors (Garner's mixed-radix form):
 // x = r1 + p1 t2 + p1 p2 t3 with t2 = (r2 - r1) p1^-1 mod p2 and
 // t3 = (r3 - (r1 + p1 t2)) (p1 p2)^-1 mod p3, so 0 <= x < M = p1 p2 p3; the
@@ -1501,12 +1520,6 @@ struct Crt3 {
     uint64_t p1p2;              // p1 p2 < 2^62
     unsigned __int128 M, half_M;
 };
-// x mod p for x < 2^32, p < 2^31, b = floor(2^32 / p): the quotient estimate
-// floor(x b / 2^32) is at most one short, so one conditional subtraction.
-__device__ __forceinline__ uint32_t barrett32(uint32_t x, uint32_t p, uint32_t b) {
-    const uint32_t r = x - __umulhi(x, b) * p;
-    return r >= p ? r - p : r;
-}
 // Garner's mixed-radix reconstruction, one coefficient per thread:
 // x = a1 + p1 t2 + p1 p2 t3 with t2 = (a2 - a1) / p1 mod p2 and
 // t3 = (a3 - (a1 + p1 t2)) / (p1 p2) mod p3, then the signed representative in

@@ -186,6 +186,28 @@ def test_convenience_calls_reuse_work_list_memory(ctxgl):
         assert (X.cpu().numpy().astype(np.uint64) == expected(p, g, A, B)).all()
 
 
+@pytest.mark.parametrize("name", ["p2013265921", "p469762049", "goldilocks", "p63"])
+def test_from_signed_edges(name):
+    # signed 64-bit integers to residues: the extremes, small values of both
+    # signs and random 64-bit values, against Python's floor modulo
+    p, g = PRIMES[name]
+    ctx = libtft.Context(p, g)
+    try:
+        rng = np.random.default_rng(9)
+        v = np.concatenate([np.array([0, 1, -1, 2**63 - 1, -2**63, -2**63 + 1, p % 2**63, -(p % 2**63),
+                                      2**32, -2**32, 2**32 - 1, -(2**32 - 1)], dtype=np.int64),
+                            rng.integers(-2**63, 2**63 - 1, 100000, dtype=np.int64, endpoint=True)])
+        dv = torch.from_numpy(v).cuda()
+        X = torch.empty(len(v), dtype=ctx.dtype, device="cuda")
+        libtft.tft_from_signed(ctx, dv, X)
+        torch.cuda.synchronize()
+        got = X.cpu().numpy().astype(np.uint64)
+        want = np.array([int(x) % p for x in v.tolist()], dtype=np.uint64)
+        assert (got == want).all(), np.nonzero(got != want)[0][:5]
+    finally:
+        ctx.close()
+
+
 def test_crt3_random_residues():
     # Garner's reconstruction alone: random residue triples (and the edges 0,
     # -1, (M-1)/2, (M+1)/2) against the Chinese remainder by Python integers,
