@@ -334,7 +334,8 @@ typedef enum {
     TFT_K_SMALL_INV,       /* single-workgroup inverse */
     TFT_K_SMALL_MUL,       /* single-workgroup product */
     TFT_K_COL_FWD,         /* forward column pass (large-stride layers) */
-    TFT_K_ROW_FWD,         /* forward row pass (small-stride layers) and last row */
+    TFT_K_ROW_FWD,         /* forward row pass (small-stride layers) and last row; in batched
+                              products, forward rows of both operands, product and inverse rows */
     TFT_K_ROW_INV,         /* inverse row pass */
     TFT_K_COL_INV_SHORT,   /* inverse columns c >= b (single transforms with b > 0: every column on
                               its first a values), re-deriving the extra evaluations */

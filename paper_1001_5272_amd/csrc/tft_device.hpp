@@ -81,14 +81,17 @@ struct ModU32 {
         Word e = d + p;
         return d < e ? d : e;
     }
-    // Montgomery product a b 2^-32 mod p for a < 2^32, b < p.
+    // Montgomery product a b 2^-32 mod p for a < 2^32, b < p: t = a b and
+    // m = t pneg mod 2^32 make t + m p a multiple of 2^32 below 2p 2^32 <
+    // 2^64, so its high word is the product in [0, 2p).  Written as two
+    // 32 x 32 -> 64 multiply-adds and one low multiply (v_mad_u64_u32,
+    // v_mul_lo_u32): five VALU instructions, against eight with separate
+    // low and high products and the carry of the low words.
     __device__ __forceinline__ Word mont(Word a, Word b) const {
-        uint32_t lo = a * b;
-        uint32_t hi = __umulhi(a, b);
-        uint32_t m = lo * pneg;
-        uint32_t mh = __umulhi(m, p);
-        uint32_t u = hi + mh + (lo != 0u);   // (a b + m p) / 2^32 < 2p
-        uint32_t v = u - p;
+        const uint64_t t = (uint64_t)a * b;
+        const uint32_t m = (uint32_t)t * pneg;
+        const uint32_t u = (uint32_t)((t + (uint64_t)m * p) >> 32);
+        const uint32_t v = u - p;
         return u < v ? u : v;
     }
     __device__ __forceinline__ Word mul_tw(Word a, Word twm) const { return mont(a, twm); }

@@ -49,6 +49,14 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t x, uint32_t tiles) {
     return (x & 7u) * (tiles >> 3) + (x >> 3);
 }
 
+// The same for a work list of n items (adjacent items are neighbouring tiles
+// of one transform): a bijection on [0, n), identity on the last n mod 8.
+__device__ __forceinline__ uint32_t xcd_remap_list(uint32_t x, uint32_t n) {
+    const uint32_t full = n & ~7u;
+    if (full < 16 || x >= full) return x;
+    return (x & 7u) * (full >> 3) + (x >> 3);
+}
+
 // ------------------------------------------------------ single workgroup
 template <class Mod>
 __device__ __forceinline__ void small_forward_body(const Mod& md, const Tables<typename Mod::Word>& T0, typename Mod::Word* X,
@@ -488,36 +496,21 @@ __device__ __forceinline__ void row_fwd_fused(const Mod& md, const Tables<typena
     staged_copy<8>(1u << logW, [&](uint32_t i) { return buf[pad(i)]; }, [&](uint32_t i, Word v) { row[i] = v; });
 }
 
-// Inverse of row_fwd_fused: coefficients of row g from its W values at row
-// (times Y pointwise first when yr is set).
-// PART: only words below lim < W exist at row (and yr); the missing ones enter
-// as 0 and the coefficient at index lim is stored to *beyond.
-template <class Mod, bool PART = false>
-__device__ __forceinline__ void row_inv_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
-                              typename Mod::Word* row, const typename Mod::Word* yr, uint32_t logW, uint64_t g,
-                              uint32_t lim = 0, typename Mod::Word* beyond = nullptr) {
+// Inverse of row_fwd_fused: coefficients of row g from its W values, stored
+// at row.  load(i, x) gives the values 8 i .. 8 i + 7 (it may read buf at
+// those positions only: the first group writes them back in place).
+// PART: only words below lim < W are stored at row; the coefficient at index
+// lim goes to *beyond.
+template <class Mod, bool PART, class Load>
+__device__ __forceinline__ void row_inv_run(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+                                            typename Mod::Word* row, uint32_t logW, uint64_t g, uint32_t lim,
+                                            typename Mod::Word* beyond, Load load) {
     using Word = typename Mod::Word;
     const uint32_t W = 1u << logW, W8 = W >> 3, nt = nthreads(), maskK = (1u << T.K) - 1;
     const Word* tab = T.i1;
     for (uint32_t i = threadIdx.x; i < W8; i += nt) {
         Word x[8];
-        if (PART) {
-#pragma unroll
-            for (int t = 0; t < 8; t++) x[t] = 8 * i + t < lim ? row[8 * i + t] : Word(0);
-        } else {
-            load8(row + 8 * i, x);
-        }
-        if (yr) {
-            Word y[8];
-            if (PART) {
-#pragma unroll
-                for (int t = 0; t < 8; t++) y[t] = 8 * i + t < lim ? yr[8 * i + t] : Word(0);
-            } else {
-                load8(yr + 8 * i, y);
-            }
-#pragma unroll
-            for (int t = 0; t < 8; t++) x[t] = md.mul(x[t], y[t]);
-        }
+        load(i, x);
         Unit<Mod, 3> un;
         un.load0(tab, 1, i);
         un.template inverse<false>(md, x);
@@ -549,6 +542,35 @@ __device__ __forceinline__ void row_inv_fused(const Mod& md, const Tables<typena
                 *beyond = v;
         }
     }
+}
+
+// row_inv_run on the W values at row (times Y pointwise first when yr is
+// set); PART: only the words below lim exist at row and yr, the others enter
+// as 0.
+template <class Mod, bool PART = false>
+__device__ __forceinline__ void row_inv_fused(const Mod& md, const Tables<typename Mod::Word>& T, typename Mod::Word* buf,
+                              typename Mod::Word* row, const typename Mod::Word* yr, uint32_t logW, uint64_t g,
+                              uint32_t lim = 0, typename Mod::Word* beyond = nullptr) {
+    using Word = typename Mod::Word;
+    row_inv_run<Mod, PART>(md, T, buf, row, logW, g, lim, beyond, [&](uint32_t i, Word (&x)[8]) {
+        if (PART) {
+#pragma unroll
+            for (int t = 0; t < 8; t++) x[t] = 8 * i + t < lim ? row[8 * i + t] : Word(0);
+        } else {
+            load8(row + 8 * i, x);
+        }
+        if (yr) {
+            Word y[8];
+            if (PART) {
+#pragma unroll
+                for (int t = 0; t < 8; t++) y[t] = 8 * i + t < lim ? yr[8 * i + t] : Word(0);
+            } else {
+                load8(yr + 8 * i, y);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; t++) x[t] = md.mul(x[t], y[t]);
+        }
+    });
 }
 
 // Forward row pass: row j < a is transformed in full (global block index j at
@@ -655,6 +677,122 @@ __device__ __forceinline__ void row_inv_body(const Mod& md, const Tables<typenam
     // no halvings in the butterflies, one scaling by 2^-lg len on the store
     full_inverse<Mod, false>(md, T, buf, 0, 0, len, g);
     for (uint32_t i = threadIdx.x; i < len; i += nt) row[i] = md.mul_tw(buf[pad(i)], sc);
+}
+
+// Row pass of a batched product whose inverse keeps the columns c < b for
+// after the last row (early == 0), records with g0 = 0.  Item k < a takes row
+// k of both operands' column-pass outputs (P.X and Q.X, W >= 64), transforms
+// both in LDS, multiplies them pointwise and inverts the row, storing the
+// coefficients over P's row: forward row pass, product and inverse row pass
+// in one HBM round trip.  Item a (b > 0) builds the partial last row of both
+// operands (b slots and V_c), keeps the product of their b outputs and
+// inverts its dyadic pieces, which read only those values (the inverse row
+// pass's piece items).
+template <class Mod>
+__device__ __forceinline__ void row_mul_body(const Mod& md, const Tables<typename Mod::Word>& T,
+                                             const TwoPass<typename Mod::Word>& P,
+                                             const TwoPass<typename Mod::Word>& Q, uint32_t k) {
+    using Word = typename Mod::Word;
+    const uint32_t W = 1u << P.logW;
+    Word* ba = lds_buf<Word>();
+    Word* bb = ba + padded_words(W);
+    Word* row = P.X + (uint64_t)k * W;
+    const Word* rb = Q.X + (uint64_t)k * W;
+    if (k < P.a) {
+        row_fwd_lds(md, T, ba, row, P.logW, k);
+        row_fwd_lds(md, T, bb, rb, P.logW, k);
+        row_inv_run<Mod, false>(md, T, ba, row, P.logW, k, 0, nullptr, [&](uint32_t i, Word (&x)[8]) {
+#pragma unroll
+            for (int t = 0; t < 8; t++) x[t] = md.mul(ba[pad(8 * i) + t], bb[pad(8 * i) + t]);
+        });
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < W; i += nthreads()) {
+        ba[pad(i)] = i < P.b ? row[i] : P.V[i];
+        bb[pad(i)] = i < P.b ? rb[i] : Q.V[i];
+    }
+    __syncthreads();
+    dif_forward(md, T, ba, 0, W, 0, P.b, P.a);
+    dif_forward(md, T, bb, 0, W, 0, P.b, P.a);
+    for (uint32_t i = threadIdx.x; i < P.b; i += nthreads()) ba[pad(i)] = md.mul(ba[pad(i)], bb[pad(i)]);
+    __syncthreads();
+    // 0 < b < W: the pieces are the dyadic blocks of [0, b), one per set bit
+    const int np = __popc(P.b);
+    for (int q = 0; q < np; q++) {
+        const Piece pc = gitft_piece(W, P.b, P.a, q);
+        full_inverse<Mod, false>(md, T, ba, 0, pc.off, pc.size, pc.g);
+        const Word sc = inv_pow2_tw(md, __builtin_ctz(pc.size));
+        for (uint32_t i = threadIdx.x; i < pc.size; i += nthreads()) row[pc.off + i] = md.mul_tw(ba[pad(pc.off + i)], sc);
+    }
+}
+
+// The same for R = 2^logR consecutive full rows j0 .. j0 + R - 1 (those below
+// a) at once, for rows too short to fill the workgroup: after the twist to
+// block index 0 every row takes the same twiddles, so the rows sit in LDS as
+// R interleaved columns (word i of row q at i R + q) and go through the
+// block-0 forward, the product and the block-0 inverse together, every
+// thread busy.
+template <class Mod>
+__device__ __forceinline__ void row_mul_rows(const Mod& md, const Tables<typename Mod::Word>& T,
+                                             const TwoPass<typename Mod::Word>& P,
+                                             const TwoPass<typename Mod::Word>& Q, uint32_t j0, int logR) {
+    using Word = typename Mod::Word;
+    const uint32_t logW = P.logW, W = 1u << logW, W8 = W >> 3, R = 1u << logR;
+    const uint32_t nt = nthreads(), maskK = (1u << T.K) - 1;
+    const uint32_t cnt = min(R, P.a - j0);
+    Word* ba = lds_buf<Word>();
+    Word* bb = ba + padded_words(R * W);
+    // unit (q, u): words u + t W/8 of row j0 + q, coalesced over u
+    for (uint32_t it = threadIdx.x; it < (R << (logW - 3)); it += nt) {
+        const uint32_t q = it >> (logW - 3), u = it & (W8 - 1);
+        const uint32_t j = j0 + q;
+        const uint32_t E = __builtin_bitreverse32(j << logW) >> (32 - T.K);
+        const Word z8 = root_pow(md, T, (W8 * E) & maskK);
+        Word f = root_pow(md, T, (u * E) & maskK);
+        const uint64_t base = (uint64_t)j * W + u;
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const uint32_t d = ((u + t * W8) << logR) + q;
+            Word xa = 0, xb = 0;
+            if (q < cnt) {
+                xa = P.X[base + t * W8];
+                xb = Q.X[base + t * W8];
+            }
+            ba[pad(d)] = md.mul_tw(xa, f);
+            bb[pad(d)] = md.mul_tw(xb, f);
+            f = md.tw_mul_tw(f, z8);
+        }
+    }
+    __syncthreads();
+    dif_forward(md, T, ba, logR, W, 0, W, 0);
+    dif_forward(md, T, bb, logR, W, 0, W, 0);
+    for (uint32_t i = threadIdx.x; i < (R << logW); i += nt) ba[pad(i)] = md.mul(ba[pad(i)], bb[pad(i)]);
+    __syncthreads();
+    // block-0 inverse (values times W), then z^-i / W on the store
+    full_inverse<Mod, false>(md, T, ba, logR, 0, W, 0);
+    const Word sc = inv_pow2_tw(md, (int)logW);
+    for (uint32_t it = threadIdx.x; it < (R << (logW - 3)); it += nt) {
+        const uint32_t q = it >> (logW - 3), u = it & (W8 - 1);
+        if (q >= cnt) continue;
+        const uint32_t j = j0 + q;
+        const uint32_t E = __builtin_bitreverse32(j << logW) >> (32 - T.K);
+        const Word z8 = root_pow_inv(md, T, (W8 * E) & maskK);
+        Word f = md.tw_mul_tw(sc, root_pow_inv(md, T, (u * E) & maskK));
+        const uint64_t base = (uint64_t)j * W + u;
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const uint32_t d = ((u + t * W8) << logR) + q;
+            P.X[base + t * W8] = md.mul_tw(ba[pad(d)], f);
+            f = md.tw_mul_tw(f, z8);
+        }
+    }
+}
+
+// Rows per row-product item: R W = 8 threads (one radix-8 unit per thread),
+// at least one row.
+__host__ __device__ inline int row_mul_log_rows(uint32_t logW, uint32_t threads) {
+    const int lt = 31 - __builtin_clz(threads) + 3;
+    return lt > (int)logW ? lt - (int)logW : 0;
 }
 
 // Number of inverse-row items: a rows plus the last row's pieces.
@@ -1390,8 +1528,9 @@ struct Item {
 template <class Mod, int LOGC>
 __global__ __launch_bounds__(kColThreads) void k_col_fwd_list(Mod md, Tables<typename Mod::Word> T,
                                                            const TwoPass<typename Mod::Word>* recs,
-                                                           const Item* items) {
-    const Item it = items[blockIdx.x];
+                                                           const Item* items, uint32_t spread) {
+    // spread: neighbouring tiles on one XCD (its L2 holds the shared lines)
+    const Item it = items[spread ? xcd_remap_list(blockIdx.x, gridDim.x) : blockIdx.x];
     col_fwd_body<Mod, LOGC>(md, T, recs[it.rec], it.idx);
 }
 template <class Mod>
@@ -1408,11 +1547,26 @@ __global__ __launch_bounds__(kRowThreads) void k_row_inv_list(Mod md, Tables<typ
     const Item it = items[blockIdx.x];
     row_inv_body(md, T, recs[it.rec], it.idx);
 }
+// Item (rec, k) of a batched product: records rec (first operand, result)
+// and rec + 1 (second operand); k < a: the rows from k (row_mul_rows, or
+// row_mul_body for one row per item), k = a: the partial last row.
+template <class Mod>
+__global__ __launch_bounds__(kRowThreads) void k_row_mul_list(Mod md, Tables<typename Mod::Word> T,
+                                                           const TwoPass<typename Mod::Word>* recs,
+                                                           const Item* items) {
+    const Item it = items[blockIdx.x];
+    const TwoPass<typename Mod::Word>& P = recs[it.rec];
+    const int logR = row_mul_log_rows(P.logW, nthreads());
+    if (it.idx < P.a && logR > 0)
+        row_mul_rows(md, T, P, recs[it.rec + 1], it.idx, logR);
+    else
+        row_mul_body(md, T, P, recs[it.rec + 1], it.idx);
+}
 template <class Mod, int LOGC>
 __global__ __launch_bounds__(kColThreads) void k_col_inv_list(Mod md, Tables<typename Mod::Word> T,
                                                            const TwoPass<typename Mod::Word>* recs,
-                                                           const Item* items, int phase) {
-    const Item it = items[blockIdx.x];
+                                                           const Item* items, int phase, uint32_t spread) {
+    const Item it = items[spread ? xcd_remap_list(blockIdx.x, gridDim.x) : blockIdx.x];
     col_inv_body<Mod, LOGC>(md, T, recs[it.rec], phase, it.idx);
 }
 template <class Mod>

@@ -85,6 +85,24 @@ def test_batch_products_match_oracle_and_solo(ctx998, ctxgl, which):
     b.close()
 
 
+@pytest.mark.parametrize("which", ["p998244353", "goldilocks"])
+def test_batch_products_long_rows(ctx998, ctxgl, which):
+    """Products long enough that a batch row holds 2048 words: the fused row
+    product then takes one row per workgroup (b > 0 and b = 0)."""
+    ctx = ctx998 if which == "p998244353" else ctxgl
+    p, g = PRIMES[which]
+    lens = [(1 << 20, (1 << 20) + 5), (1500000, 700001), (3000, 1 << 21), (1 << 20, (1 << 20) + 1), (5, 7)]
+    print(f"[gpu] batch of long products, {which}", flush=True)
+    jobs, host = make_jobs(ctx, p, lens, 900)
+    b = libtft.Batch(ctx, jobs)
+    b.run()
+    torch.cuda.synchronize()
+    for (A, B), (_, _, X, _) in zip(host, jobs):
+        got = X.cpu().numpy().astype(np.uint64)
+        assert (got == expected(p, g, A, B)).all(), f"batch product {len(A)}x{len(B)} differs"
+    b.close()
+
+
 def test_batch_graph_replay(ctx998):
     p, g = PRIMES["p998244353"]
     lens = seeded_lengths(40, 16, 20000, 91)
