@@ -1119,7 +1119,7 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
     // traffic instead of 7 r.  Otherwise forward rows per operand, then
     // inverse rows and the last row's pieces: twice the workgroups and a
     // third of the work each, which the serving queue's small, overlapping
-    // batches finish sooner (served p50 310 us against 413 us fused).
+    // batches finish sooner (served p50 and p99 about 5 % and 15 % lower).
     B->rowmul_thr = std::max<uint32_t>(B->row_thr, kRowMulThreads);
     B->lds_rowmul = 0;
     for (const RowGeom& g : rows) {
