@@ -76,6 +76,7 @@ constexpr size_t kLdsSoft = 76 * 1024;          // preferred LDS per workgroup (
 constexpr size_t kLdsHard = 160 * 1024;         // gfx950 LDS per workgroup
 constexpr size_t kLdsDynMax = 144 * 1024;       // dynamic LDS any launch may request
 constexpr uint32_t kRowMulThreads = 256;          // fused row-product workgroups of a batch (at least)
+constexpr int kBigJobThreads = 1024;              // single-workgroup batch jobs alone on a CU
 constexpr uint64_t kFewColumns = 128;   // classes this narrow run one column per workgroup
 
 typedef unsigned __int128 u128;
@@ -447,6 +448,7 @@ bool set_lds_limits() {
     const void* ks[] = {
         (const void*)tft::k_small_fwd<Mod>,       (const void*)tft::k_small_inv<Mod>,
         (const void*)tft::k_small_mul<Mod>,       (const void*)tft::k_small_list<Mod>,
+        (const void*)tft::k_small_list<Mod, kBigJobThreads>,
         (const void*)tft::k_restr_tail<Mod>,
         (const void*)tft::k_col_fwd<Mod, 3>,      (const void*)tft::k_col_fwd<Mod, 4>,
         (const void*)tft::k_col_inv<Mod, 3>,      (const void*)tft::k_col_inv<Mod, 4>,
@@ -966,7 +968,9 @@ struct tft_batch {
     uint32_t n_items[PH_COUNT];
     void* jobs;
     uint32_t* counter;
-    size_t lds_col, lds_row, lds_small;
+    size_t lds_col, lds_row, lds_small;   // lds_small: the single-workgroup jobs after the first n_big
+    size_t n_big, lds_big;     // single-workgroup jobs whose LDS allows one workgroup per CU: their
+    uint32_t big_grid;         // own persistent launch of kBigJobThreads threads, before the rest
     bool row_mul;              // products: forward rows, product and inverse rows fused (k_row_mul_list)
     uint32_t rowmul_thr;       // its workgroup size
     size_t lds_rowmul;         // and its two row buffers
@@ -1069,7 +1073,6 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
         const Plan P = make_plan(ctx, r, true);
         if (P.kind < 0) return TFT_ERANGE;
         if (batch_small(ctx, P, r, products)) {
-            const size_t small_lds = small_job_lds(w, r, products);
             tft::SmallJob<Word> J;
             J.A = (const Word*)D.a;
             J.B = products ? (const Word*)D.b : nullptr;
@@ -1078,7 +1081,6 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
             J.nb = products ? (uint32_t)D.lb : 0;
             J.M = (uint32_t)pow2ceil(r);
             jobs.push_back(J);
-            if (small_lds > B->lds_small) B->lds_small = small_lds;
             continue;
         }
         if (P.kind != 1) return TFT_ERANGE;
@@ -1147,6 +1149,20 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
         return (uint64_t)x.m + x.nb > (uint64_t)y.m + y.nb;
     });
     B->n_small = jobs.size();
+    // the jobs (longest first) in two classes by LDS: above a third of a CU's
+    // LDS one workgroup fits per CU, and it gets kBigJobThreads threads; the
+    // rest share the CUs at three or more workgroups of kThreads each
+    B->n_big = 0;
+    B->lds_big = B->lds_small = 0;
+    for (const auto& J : jobs) {
+        const size_t l = small_job_lds(w, (uint64_t)J.m + J.nb - (J.B ? 1 : 0), products);
+        if (l > kLdsHard / 3) {
+            B->n_big++;
+            B->lds_big = std::max(B->lds_big, l);
+        } else {
+            B->lds_small = std::max(B->lds_small, l);
+        }
+    }
     B->n_two = recs.size() / (products ? 2 : 1);
     // one device allocation: recs | items per phase | jobs | V areas | counter
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -1201,12 +1217,13 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
     }
     B->jobs = base + o_jobs;
     B->counter = (uint32_t*)(base + o_ctr);
-    // persistent grid: as many workgroups as fit at once (LDS-limited), at most one per job
-    uint32_t per_cu = B->lds_small ? (uint32_t)std::max<size_t>(1, kLdsHard / B->lds_small) : 1;
-    per_cu = std::min<uint32_t>(per_cu, 8);
+    // persistent grids: as many workgroups as fit at once (LDS-limited), at most one per job
     int ncu = 256;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) ncu = 256;
-    B->small_grid = (uint32_t)std::min<size_t>(jobs.size(), (size_t)ncu * per_cu);
+    uint32_t per_cu = B->lds_small ? (uint32_t)std::max<size_t>(1, kLdsHard / B->lds_small) : 1;
+    per_cu = std::min<uint32_t>(per_cu, 8);
+    B->small_grid = (uint32_t)std::min<size_t>(jobs.size() - B->n_big, (size_t)ncu * per_cu);
+    B->big_grid = (uint32_t)std::min<size_t>(B->n_big, (size_t)ncu);
     return TFT_OK;
 }
 
@@ -1225,9 +1242,14 @@ tft_status batch_run(tft_batch* B, hipStream_t st) {
         small_st = B->side;
     }
     if (B->n_small) {
+        const auto* jobs = (const tft::SmallJob<Word>*)B->jobs;
         launch(ctx, TFT_K_COPY, tft::k_reset_counter, dim3(1), dim3(64), 0, small_st, B->counter);
-        launch(ctx, TFT_K_SMALL_LIST, tft::k_small_list<Mod>, dim3(B->small_grid), dim3(kThreads), B->lds_small,
-               small_st, md, T, (const tft::SmallJob<Word>*)B->jobs, (uint32_t)B->n_small, B->counter);
+        if (B->n_big)
+            launch(ctx, TFT_K_SMALL_LIST, tft::k_small_list<Mod, kBigJobThreads>, dim3(B->big_grid),
+                   dim3(kBigJobThreads), B->lds_big, small_st, md, T, jobs, (uint32_t)B->n_big, B->counter);
+        if (B->n_small > B->n_big)
+            launch(ctx, TFT_K_SMALL_LIST, tft::k_small_list<Mod>, dim3(B->small_grid), dim3(kThreads), B->lds_small,
+                   small_st, md, T, jobs + B->n_big, (uint32_t)(B->n_small - B->n_big), B->counter + 1);
     }
     if (B->n_items[PH_COL_FWD])
         launch(ctx, TFT_K_COL_FWD, col_fwd_list_kernel<Mod>(B->logC),
@@ -1856,7 +1878,7 @@ tft_status tft_batch_info(const tft_batch* B, tft_batch_desc* out) {
     out->single_workgroup = B->n_small;
     out->two_pass = B->n_two;
     out->device_bytes = B->dbytes;
-    uint32_t launches = B->n_small ? 2 : 0;
+    uint32_t launches = B->n_small ? 1 + (B->n_big ? 1 : 0) + (B->n_small > B->n_big ? 1 : 0) : 0;
     for (int ph = 0; ph < PH_COUNT; ph++) launches += B->n_items[ph] ? 1 : 0;
     out->launches = launches;
     return TFT_OK;

@@ -1587,8 +1587,8 @@ struct SmallJob {
     Word* X;
     uint32_t m, nb, M;
 };
-template <class Mod>
-__global__ __launch_bounds__(kThreads) void k_small_list(Mod md, Tables<typename Mod::Word> T,
+template <class Mod, int NT = kThreads>
+__global__ __launch_bounds__(NT) void k_small_list(Mod md, Tables<typename Mod::Word> T,
                                                          const SmallJob<typename Mod::Word>* jobs, uint32_t count,
                                                          uint32_t* counter) {
     __shared__ uint32_t next;
@@ -1607,9 +1607,10 @@ __global__ __launch_bounds__(kThreads) void k_small_list(Mod md, Tables<typename
     }
 }
 
-// Reset of the work counter, as a kernel so that a captured graph replays it.
+// Reset of the work counters (two words), as a kernel so that a captured
+// graph replays it.
 __global__ void k_reset_counter(uint32_t* counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+    if (threadIdx.x < 2 && blockIdx.x == 0) counter[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------- elementwise
