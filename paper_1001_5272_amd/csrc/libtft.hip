@@ -75,8 +75,9 @@ constexpr size_t kFoldWords = 2 * kFoldItems + kFoldSpare + (size_t(4) << kRestr
 constexpr size_t kLdsSoft = 76 * 1024;          // preferred LDS per workgroup (two per CU)
 constexpr size_t kLdsHard = 160 * 1024;         // gfx950 LDS per workgroup
 constexpr size_t kLdsDynMax = 144 * 1024;       // dynamic LDS any launch may request
-constexpr uint32_t kRowMulThreads = 256;          // fused row-product workgroups of a batch (at least)
+constexpr uint32_t kRowMulThreads = 128;          // fused row-product workgroups of a batch (at least)
 constexpr int kBigJobThreads = 1024;              // single-workgroup batch jobs alone on a CU
+constexpr uint32_t kListColThreads = 128;         // column-list workgroups of a standalone batch (at most)
 constexpr uint64_t kFewColumns = 128;   // classes this narrow run one column per workgroup
 
 typedef unsigned __int128 u128;
@@ -979,6 +980,7 @@ struct tft_batch {
                                // products (throughput); otherwise the unfused row passes, more
                                // workgroups per pass (latency)
     uint32_t row_thr, col_thr;   // workgroup sizes of the pass launches (widest row / tile of the batch)
+    uint32_t list_col_thr;       // of its column lists
     int logC;
     uint32_t small_grid;
     hipStream_t side;          // the single-workgroup jobs run here, beside the two-pass phases
@@ -1123,6 +1125,13 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
     // third of the work each, which the serving queue's small, overlapping
     // batches finish sooner (served p50 and p99 about 5 % and 15 % lower).
     B->rowmul_thr = std::max<uint32_t>(B->row_thr, kRowMulThreads);
+    // Column tiles of a batch are mostly smaller than its largest one, whose
+    // size sets col_thr: where eight tiles fit in a CU's LDS, 128 threads let
+    // more of them share the CU with fewer idle threads (4096 products:
+    // 1.07 -> 0.94 ms).  The serving queue keeps one thread per radix-8 unit
+    // of the largest tile.
+    B->list_col_thr = B->spread && B->lds_col * 8 <= kLdsHard ? std::min<uint32_t>(B->col_thr, kListColThreads)
+                                                              : B->col_thr;
     B->lds_rowmul = 0;
     for (const RowGeom& g : rows) {
         const int logR = tft::row_mul_log_rows(g.logW, B->rowmul_thr);
@@ -1253,7 +1262,7 @@ tft_status batch_run(tft_batch* B, hipStream_t st) {
     }
     if (B->n_items[PH_COL_FWD])
         launch(ctx, TFT_K_COL_FWD, col_fwd_list_kernel<Mod>(B->logC),
-               dim3(B->n_items[PH_COL_FWD]), dim3(B->col_thr), B->lds_col, st, md, T, recs,
+               dim3(B->n_items[PH_COL_FWD]), dim3(B->list_col_thr), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_FWD], B->spread);
     if (B->n_items[PH_ROW_FWD] && B->row_mul)
         launch(ctx, TFT_K_ROW_FWD, tft::k_row_mul_list<Mod>, dim3(B->n_items[PH_ROW_FWD]), dim3(B->rowmul_thr),
@@ -1266,14 +1275,14 @@ tft_status batch_run(tft_batch* B, hipStream_t st) {
                st, md, T, recs, (const tft::Item*)B->items[PH_ROW_INV]);
     if (B->n_items[PH_COL_INV_SHORT])
         launch(ctx, TFT_K_COL_INV_SHORT, col_inv_list_kernel<Mod>(B->logC),
-               dim3(B->n_items[PH_COL_INV_SHORT]), dim3(B->col_thr), B->lds_col, st, md, T, recs,
+               dim3(B->n_items[PH_COL_INV_SHORT]), dim3(B->list_col_thr), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_INV_SHORT], 0, B->spread);
     if (B->n_items[PH_LAST_INV])
         launch(ctx, TFT_K_LAST_INV, tft::k_last_inv_list<Mod>, dim3(B->n_items[PH_LAST_INV]), dim3(B->row_thr),
                B->lds_row, st, md, T, recs, (const tft::Item*)B->items[PH_LAST_INV]);
     if (B->n_items[PH_COL_INV_LONG])
         launch(ctx, TFT_K_COL_INV_LONG, col_inv_list_kernel<Mod>(B->logC),
-               dim3(B->n_items[PH_COL_INV_LONG]), dim3(B->col_thr), B->lds_col, st, md, T, recs,
+               dim3(B->n_items[PH_COL_INV_LONG]), dim3(B->list_col_thr), B->lds_col, st, md, T, recs,
                (const tft::Item*)B->items[PH_COL_INV_LONG], 1, B->spread);
     if (both) {
         if (hipEventRecord(B->join, B->side) != hipSuccess || hipStreamWaitEvent(st, B->join, 0) != hipSuccess)
