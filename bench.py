@@ -615,9 +615,11 @@ def batched_c3():
     same = bool(torch.equal(Xall, X2all))
     batch.close()
     # the batch tuner: rows of the two-pass instances at the balanced split, one
-    # step wider (the default above) or two steps wider, fastest kept
+    # step wider (the default above) or two steps wider, then the column-list
+    # and fused-row workgroup sizes; fastest kept
     Xall.zero_()
     widen = libtft.tft_autotune_batch(ctx, jobs)
+    tuning = libtft.tft_batch_tuning_get(ctx)
     tuned_batch = libtft.Batch(ctx, jobs)
     with torch.cuda.stream(s):
         tuned_batch.run()
@@ -642,7 +644,8 @@ def batched_c3():
             "graph_ms": round(t_graph, 3), "run_ms": round(t_run, 3), "plain_ms": round(t_plain, 3),
             "mults_per_s_graph": round(count / (t_graph * 1e-3), 0), "mults_per_s_plain": round(count / (t_plain * 1e-3), 0),
             "speedup_vs_plain": round(t_plain / t_graph, 2), "batched_equals_plain": same,
-            "tuned": {"rows_wider_than_balanced": widen, "graph_ms": round(t_tuned, 3),
+            "tuned": {"rows_wider_than_balanced": widen, "list_col_threads": tuning["list_col_threads"],
+                      "row_mul_threads": tuning["row_mul_threads"], "graph_ms": round(t_tuned, 3),
                       "mults_per_s_graph": round(count / (t_tuned * 1e-3), 0), "batched_equals_plain": same_tuned},
             # algorithmic bytes of a product: three transforms (each word read
             # and written once) plus the pointwise read of Y: 7 r words

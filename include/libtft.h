@@ -313,11 +313,23 @@ tft_status tft_autotune(tft_ctx* ctx, size_t n, tft_plan_desc* chosen);
  * length, one step wider (the default) and two steps wider, timing each (median
  * of five runs after a warm-up; synchronous), and keeps the fastest -- a change
  * from the default only when 3 % faster -- for every later batch of the context,
- * the serving queue's included.  The descriptors' outputs are written by the
- * runs (products: the products themselves; forward transforms: transformed
- * several times over, so pass scratch copies).  *widen (may be NULL) receives
- * the choice, 0..2.  Any choice gives the same results. */
+ * the serving queue's included.  Then, at that width, it times the workgroup
+ * sizes of a standalone batch's column lists (at most 128 or 256 threads;
+ * default 128) and fused row products (at least 128 or 256; default 128) and
+ * keeps the fastest pair on the same 3 % rule.  The descriptors' outputs are
+ * written by the runs (products: the products themselves; forward transforms:
+ * transformed several times over, so pass scratch copies).  *widen (may be
+ * NULL) receives the width choice, 0..2; tft_batch_tuning_get reports all
+ * three.  Any choice gives the same results. */
 tft_status tft_autotune_batch(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int products, unsigned* widen);
+typedef struct {
+    unsigned widen;              /* rows this many steps wider than balanced, 0..2 */
+    unsigned list_col_threads;   /* column-list workgroups of a standalone batch, at most */
+    unsigned row_mul_threads;    /* fused row-product workgroups of a standalone batch, at least */
+} tft_batch_tuning;
+/* The context's current batch settings (the defaults until tft_autotune_batch
+ * changes them).  EINVAL for NULL arguments. */
+tft_status tft_batch_tuning_get(const tft_ctx* ctx, tft_batch_tuning* out);
 tft_status tft_plan_cache_get(tft_ctx* ctx, unsigned bucket, unsigned* code);
 tft_status tft_plan_cache_set(tft_ctx* ctx, unsigned bucket, unsigned code);
 unsigned tft_plan_bucket(size_t n);

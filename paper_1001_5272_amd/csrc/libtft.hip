@@ -164,6 +164,8 @@ struct tft_ctx {
     std::atomic<unsigned> override_logW;
     std::atomic<unsigned> tuned_logW[kPlanBuckets];   // plan cache by floor(4 lg n): plan codes, 0 = planner's choice
     std::atomic<unsigned> batch_widen;                // batches: rows this many steps wider than balanced (0..2)
+    std::atomic<unsigned> batch_col_thr;              // standalone batches: column-list workgroup size (at most)
+    std::atomic<unsigned> batch_rowmul_thr;           // and fused row-product workgroup size (at least)
     tft::ModU32 m32;
     tft::ModGL m64;
     tft::ModM64 mm64;    // 8-byte words, p other than 2^64 - 2^32 + 1
@@ -325,6 +327,8 @@ size_t col_tile_lds(const Plan& P, uint32_t len, bool fwd, unsigned w) {
 thread_local unsigned tl_force_code = 0;      // 0: none
 thread_local bool tl_ignore_cache = false;   // plan without the tuned widths
 thread_local int tl_batch_widen = -1;        // the batch tuner's candidate (-1: the context's setting)
+thread_local int tl_batch_col_thr = -1;      // its thread-count candidates (-1: the context's settings)
+thread_local int tl_batch_rowmul_thr = -1;
 
 Plan make_plan(const tft_ctx* ctx, uint64_t n, bool wide = false) {
     Plan P{};
@@ -1124,13 +1128,17 @@ tft_status batch_build(tft_ctx* ctx, const tft_mul_desc* d, size_t count, int pr
     // inverse rows and the last row's pieces: twice the workgroups and a
     // third of the work each, which the serving queue's small, overlapping
     // batches finish sooner (served p50 and p99 about 5 % and 15 % lower).
-    B->rowmul_thr = std::max<uint32_t>(B->row_thr, kRowMulThreads);
+    const uint32_t rowmul_min = tl_batch_rowmul_thr > 0 ? (uint32_t)tl_batch_rowmul_thr
+                                                        : ctx->batch_rowmul_thr.load(std::memory_order_relaxed);
+    const uint32_t list_col_max = tl_batch_col_thr > 0 ? (uint32_t)tl_batch_col_thr
+                                                       : ctx->batch_col_thr.load(std::memory_order_relaxed);
+    B->rowmul_thr = std::max<uint32_t>(B->row_thr, rowmul_min);
     // Column tiles of a batch are mostly smaller than its largest one, whose
     // size sets col_thr: where eight tiles fit in a CU's LDS, 128 threads let
     // more of them share the CU with fewer idle threads (4096 products:
     // 1.07 -> 0.94 ms).  The serving queue keeps one thread per radix-8 unit
     // of the largest tile.
-    B->list_col_thr = B->spread && B->lds_col * 8 <= kLdsHard ? std::min<uint32_t>(B->col_thr, kListColThreads)
+    B->list_col_thr = B->spread && B->lds_col * 8 <= kLdsHard ? std::min<uint32_t>(B->col_thr, list_col_max)
                                                               : B->col_thr;
     B->lds_rowmul = 0;
     for (const RowGeom& g : rows) {
@@ -1636,6 +1644,8 @@ tft_status tft_ctx_create(uint64_t p, uint64_t g, int device, tft_ctx** out) {
     c->wbytes = wide ? 8 : 4;
     c->override_logW.store(0);
     c->batch_widen.store(1);
+    c->batch_col_thr.store(kListColThreads);
+    c->batch_rowmul_thr.store(kRowMulThreads);
     for (unsigned i = 0; i < kPlanBuckets; i++) c->tuned_logW[i].store(0);
     c->timing.store(false);
     c->timing_mask.store(~0u);
@@ -2266,15 +2276,16 @@ tft_status tft_autotune_batch(tft_ctx* ctx, const tft_mul_desc* d, size_t count,
     hipEvent_t e0 = nullptr, e1 = nullptr;
     tft_status st = TFT_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = TFT_EDEVICE;
-    // median of five timed runs per candidate (after one warm-up run); another
-    // width replaces the default (one step wider) only when 3 % faster
-    float ms[3] = {0.f, 0.f, 0.f};
-    for (int w = 0; w < 3 && st == TFT_OK; w++) {
+    // median of five timed runs of a candidate (after one warm-up run), with
+    // the candidate set through the thread-local overrides
+    auto time_candidate = [&](int w, int col, int rowmul, float* out) {
         tl_batch_widen = w;
+        tl_batch_col_thr = col;
+        tl_batch_rowmul_thr = rowmul;
         tft_batch* B = nullptr;
         st = tft_batch_create(ctx, d, count, products, &B);
-        tl_batch_widen = -1;
-        if (st != TFT_OK) break;
+        tl_batch_widen = tl_batch_col_thr = tl_batch_rowmul_thr = -1;
+        if (st != TFT_OK) return;
         float t[6];
         for (int rep = 0; rep < 6 && st == TFT_OK; rep++) {
             if (hipEventRecord(e0, nullptr) != hipSuccess) st = TFT_EDEVICE;
@@ -2285,19 +2296,48 @@ tft_status tft_autotune_batch(tft_ctx* ctx, const tft_mul_desc* d, size_t count,
             if (st == TFT_OK) (void)hipEventElapsedTime(&t[rep], e0, e1);
         }
         tft_batch_destroy(B);
-        if (st != TFT_OK) break;
         std::sort(t + 1, t + 6);
-        ms[w] = t[3];
-    }
-    tl_batch_widen = -1;
+        *out = t[3];
+    };
+    // first the row width at the default thread counts; another width
+    // replaces the default (one step wider) only when 3 % faster
+    float ms[3] = {0.f, 0.f, 0.f};
+    for (int w = 0; w < 3 && st == TFT_OK; w++) time_candidate(w, (int)kListColThreads, (int)kRowMulThreads, &ms[w]);
+    unsigned best = 1;
+    if (st == TFT_OK)
+        for (unsigned w = 0; w < 3; w++)
+            if (ms[w] < 0.97f * ms[best]) best = w;
+    // then, at that width, the column-list and fused-row workgroup sizes
+    // (likewise kept only when 3 % faster than the defaults)
+    static const int kCols[] = {128, 256}, kRows[] = {128, 256};
+    int best_col = (int)kListColThreads, best_row = (int)kRowMulThreads;
+    float best_ms = ms[best];
+    for (int c : kCols)
+        for (int r : kRows) {
+            if (st != TFT_OK || (c == (int)kListColThreads && r == (int)kRowMulThreads)) continue;
+            float t = 0.f;
+            time_candidate((int)best, c, r, &t);
+            if (st == TFT_OK && t < 0.97f * ms[best] && t < best_ms) {
+                best_ms = t;
+                best_col = c;
+                best_row = r;
+            }
+        }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (st != TFT_OK) return st;
-    unsigned best = 1;
-    for (unsigned w = 0; w < 3; w++)
-        if (ms[w] < 0.97f * ms[best]) best = w;
     ctx->batch_widen.store(best);
+    ctx->batch_col_thr.store((unsigned)best_col);
+    ctx->batch_rowmul_thr.store((unsigned)best_row);
     if (widen) *widen = best;
+    return TFT_OK;
+}
+
+tft_status tft_batch_tuning_get(const tft_ctx* ctx, tft_batch_tuning* out) {
+    if (!ctx || !out) return TFT_EINVAL;
+    out->widen = ctx->batch_widen.load();
+    out->list_col_threads = ctx->batch_col_thr.load();
+    out->row_mul_threads = ctx->batch_rowmul_thr.load();
     return TFT_OK;
 }
 

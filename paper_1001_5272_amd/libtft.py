@@ -74,6 +74,7 @@ SIGNATURES = {
     "tft_calibrate": (_st, [_vp, ctypes.POINTER(_Calibration)]),
     "tft_autotune": (_st, [_vp, _sz, ctypes.POINTER(PlanDesc)]),
     "tft_autotune_batch": (_st, [_vp, _vp, _sz, ctypes.c_int, ctypes.POINTER(ctypes.c_uint)]),
+    "tft_batch_tuning_get": (_st, [_vp, ctypes.c_void_p]),
     "tft_plan_cache_get": (_st, [_vp, ctypes.c_uint, ctypes.POINTER(ctypes.c_uint)]),
     "tft_plan_cache_set": (_st, [_vp, ctypes.c_uint, ctypes.c_uint]),
     "tft_plan_bucket": (ctypes.c_uint, [_sz]),
@@ -285,13 +286,27 @@ def tft_autotune(ctx: Context, n: int) -> dict:
 
 def tft_autotune_batch(ctx: Context, jobs, products=True) -> int:
     """Time the batch of jobs (as Batch would run it) with the two-pass rows at
-    the balanced split, one step wider and two steps wider, keep the fastest
-    for the context's later batches, and return it (0..2).  Runs the batch."""
+    the balanced split, one step wider and two steps wider, then the column-list
+    and fused-row workgroup sizes at the chosen width; keep the fastest for the
+    context's later batches and return the width (0..2; tft_batch_tuning_get
+    gives all three).  Runs the batch."""
     arr = _descs(ctx, jobs, products)
     w = ctypes.c_uint()
     _check(load().tft_autotune_batch(ctx.handle, arr, len(jobs), 1 if products else 0, ctypes.byref(w)),
            "tft_autotune_batch")
     return int(w.value)
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("widen", ctypes.c_uint), ("list_col_threads", ctypes.c_uint), ("row_mul_threads", ctypes.c_uint)]
+
+
+def tft_batch_tuning_get(ctx: Context) -> dict:
+    """The context's batch settings: row width (steps wider than balanced) and
+    the workgroup sizes of a standalone batch's column lists and fused rows."""
+    t = BatchTuning()
+    _check(load().tft_batch_tuning_get(ctx.handle, ctypes.byref(t)), "tft_batch_tuning_get")
+    return {f: getattr(t, f) for f, _ in BatchTuning._fields_}
 
 
 def tft_plan_cache_get(ctx: Context, bucket: int) -> int:

@@ -125,6 +125,9 @@ def test_batch_4096_every_instance():
     widen = libtft.tft_autotune_batch(ctx, jobs)
     print(f"[gpu] batch tuner chose rows {widen} steps wider than balanced", flush=True)
     assert widen in (0, 1, 2)
+    tuning = libtft.tft_batch_tuning_get(ctx)
+    assert tuning["widen"] == widen
+    assert tuning["list_col_threads"] in (128, 256) and tuning["row_mul_threads"] in (128, 256), tuning
     for _, _, X, _ in jobs:
         X.zero_()
     b = libtft.Batch(ctx, jobs)
