@@ -365,7 +365,30 @@ __device__ __forceinline__ void col_fwd_body(const Mod& md, const Tables<typenam
         if (share) put_share();
         return;
     }
-    if (P.g0 == 0 && P.M >= 16) {
+    // A zero-extended source (a product's operand) may fill only the first zr
+    // rows of the tile's columns.  With Z = 2^ceil(lg zr), the stages of block
+    // size above Z pair every value with a zero (the high half), so each only
+    // copies a block into both children: after them every block of size Z
+    // holds the same Z values.  Those stages are skipped by writing the Z rows
+    // into every block that meets [0, Lout) and running the stages below.
+    uint32_t zr = P.M, Z = P.M;
+    if (P.g0 == 0 && P.n_src < P.n) {
+        const uint64_t rows = P.n_src > c0 ? (P.n_src - c0 + W - 1) / W : 0;
+        zr = (uint32_t)(rows < P.Lout ? rows : P.Lout);
+        Z = 1;
+        while (Z < zr) Z <<= 1;
+    }
+    if (8 * Z <= P.M) {
+        const uint32_t live = (P.Lout + Z - 1) / Z * Z;   // rows of the blocks that meet [0, Lout), <= M
+        for (uint32_t it = threadIdx.x; it < (Z << LOGC); it += nthreads()) {
+            const uint32_t c = it & (C - 1), d = it >> LOGC;
+            const uint64_t idx = (c0 + c) + (uint64_t)d * W;
+            const Word v = (d < zr && idx < P.n_src) ? P.src[idx] : Word(0);
+            for (uint32_t k = d; k < live; k += Z) buf[pad((k << LOGC) + c)] = v;
+        }
+        __syncthreads();
+        if (Z >= 2) dif_stages(md, T, buf, LOGC, P.M, Z >> 1, 1, 0, P.Lout, 0);
+    } else if (P.g0 == 0 && P.M >= 16) {
         // the first radix-8 group (stages M/2, M/4, M/8 of block 0) straight
         // from HBM: the unit of lane c at u holds rows u + t M/8
         const uint32_t M8 = P.M >> 3;
