@@ -100,6 +100,11 @@ struct ModU32 {
     __device__ __forceinline__ Word mul(Word a, Word b) const { return mont(mont(a, b), r2); }
     __device__ __forceinline__ Word half(Word x) const { return (x >> 1) + ((x & 1u) ? halfp1 : 0u); }
     __device__ __forceinline__ Word one_tw() const { return mont(1u, r2); }   // 1 in twiddle (Montgomery) form
+    // a b / R: the product of two residues up to a constant factor 1/R, which
+    // a later scaling by a twiddle takes back with kappa_tw() (R in twiddle
+    // form, R^2 mod p): one Montgomery reduction instead of mul's two
+    __device__ __forceinline__ Word mul_scaled(Word a, Word b) const { return mont(a, b); }
+    __device__ __forceinline__ Word kappa_tw() const { return r2; }
 };
 
 // ------------------------------------------------ other primes p < 2^63
@@ -139,6 +144,9 @@ struct ModM64 {
     __device__ __forceinline__ Word mul(Word a, Word b) const { return mont(mont(a, b), r2); }
     __device__ __forceinline__ Word half(Word x) const { return (x >> 1) + ((x & 1u) ? halfp1 : 0u); }
     __device__ __forceinline__ Word one_tw() const { return mont(1u, r2); }   // 2^64 mod p
+    // a b / R and R in twiddle form (R^2 mod p), as ModU32
+    __device__ __forceinline__ Word mul_scaled(Word a, Word b) const { return mont(a, b); }
+    __device__ __forceinline__ Word kappa_tw() const { return r2; }
 };
 
 // ------------------------------------------------- p = 2^64 - 2^32 + 1
@@ -175,6 +183,9 @@ struct ModGL {
     __device__ __forceinline__ Word tw_mul_tw(Word t1, Word t2) const { return mul(t1, t2); }
     __device__ __forceinline__ Word half(Word x) const { return (x >> 1) + ((x & 1ull) ? HALF : 0ull); }
     __device__ __forceinline__ Word one_tw() const { return 1ull; }
+    // twiddles are plain residues: no constant factor
+    __device__ __forceinline__ Word mul_scaled(Word a, Word b) const { return mul(a, b); }
+    __device__ __forceinline__ Word kappa_tw() const { return 1ull; }
 };
 
 template <class Mod>

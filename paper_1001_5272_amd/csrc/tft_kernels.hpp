@@ -105,10 +105,11 @@ __device__ __forceinline__ void small_mul_body(const Mod& md, const Tables<typen
     __syncthreads();
     dif_forward(md, L, ba, 0, M, 0, M, 0);
     dif_forward(md, L, bb, 0, M, 0, M, 0);
-    for (uint32_t i = threadIdx.x; i < M; i += nthreads()) ba[pad(i)] = md.mul(ba[pad(i)], bb[pad(i)]);
+    // the products up to the factor that the store's scaling takes back
+    for (uint32_t i = threadIdx.x; i < M; i += nthreads()) ba[pad(i)] = md.mul_scaled(ba[pad(i)], bb[pad(i)]);
     __syncthreads();
     full_inverse<Mod, false>(md, L, ba, 0, 0, M, 0);
-    const Word sc = inv_pow2_tw(md, __builtin_ctz(M));
+    const Word sc = md.tw_mul_tw(inv_pow2_tw(md, __builtin_ctz(M)), md.kappa_tw());
     for (uint32_t i = threadIdx.x; i < r; i += nthreads()) X[i] = md.mul_tw(ba[pad(i)], sc);
 }
 
@@ -789,11 +790,12 @@ __device__ __forceinline__ void row_mul_rows(const Mod& md, const Tables<typenam
     __syncthreads();
     dif_forward(md, T, ba, logR, W, 0, W, 0);
     dif_forward(md, T, bb, logR, W, 0, W, 0);
-    for (uint32_t i = threadIdx.x; i < (R << logW); i += nt) ba[pad(i)] = md.mul(ba[pad(i)], bb[pad(i)]);
+    // the products up to the factor that the store's scaling takes back
+    for (uint32_t i = threadIdx.x; i < (R << logW); i += nt) ba[pad(i)] = md.mul_scaled(ba[pad(i)], bb[pad(i)]);
     __syncthreads();
     // block-0 inverse (values times W), then z^-i / W on the store
     full_inverse<Mod, false>(md, T, ba, logR, 0, W, 0);
-    const Word sc = inv_pow2_tw(md, (int)logW);
+    const Word sc = md.tw_mul_tw(inv_pow2_tw(md, (int)logW), md.kappa_tw());
     for (uint32_t it = threadIdx.x; it < (R << (logW - 3)); it += nt) {
         const uint32_t q = it >> (logW - 3), u = it & (W8 - 1);
         if (q >= cnt) continue;
