@@ -382,10 +382,17 @@ const char* tft_kernel_name(int id);
  *   mad64_tops     32 x 32 + 64 -> 64 multiply-adds per second / 10^12;
  *   butterflies_g  butterflies per second / 10^9 with the context's modular
  *                  arithmetic, in registers (radix-8 units, no memory traffic);
- *   copy_gbs       HBM copy bandwidth, bytes read + written per second / 10^9.
+ *   copy_gbs       HBM copy bandwidth, bytes read + written per second / 10^9;
+ *   butterflies_lds_xchg_g, butterflies_bpermute_xchg_g, butterflies_dpp_xchg_g
+ *                  the butterfly rate of butterflies_g when every radix-8 unit
+ *                  is followed by an 8 x 8 transpose among eight lanes: through
+ *                  LDS (as the pass kernels exchange values between their
+ *                  units), with lane shuffles (ds_bpermute), or with DPP quad
+ *                  permutations and ds_swizzle.
  * Returns TFT_EDEVICE if a kernel or allocation fails. */
 typedef struct {
     double valu_tops, mad64_tops, butterflies_g, copy_gbs;
+    double butterflies_lds_xchg_g, butterflies_bpermute_xchg_g, butterflies_dpp_xchg_g;
 } tft_calibration;
 tft_status tft_calibrate(tft_ctx* ctx, tft_calibration* out);
 

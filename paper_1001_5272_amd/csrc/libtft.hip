@@ -12,6 +12,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <type_traits>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -2401,13 +2402,30 @@ tft_status tft_calibrate(tft_ctx* ctx, tft_calibration* out) {
             return TFT_OK;
         });
     });
+    auto xchg = [&](auto mode) {
+        return timed([&] {
+            (void)with_mod(ctx, [&](auto mt) {
+                using Mod = decltype(mt);
+                using Word = typename Mod::Word;
+                tft::k_cal_xchg<Mod, decltype(mode)::value><<<blocks, tft::kCalThreads>>>(
+                    mod_of<Mod>(ctx), (Word*)x, (const Word*)tw, it_bf);
+                return TFT_OK;
+            });
+        });
+    };
+    const double t_xl = xchg(std::integral_constant<int, 0>{});
+    const double t_xb = xchg(std::integral_constant<int, 1>{});
+    const double t_xd = xchg(std::integral_constant<int, 2>{});
     const double t_copy = timed([&] {
         tft::k_cal_copy<<<2048, tft::kCalThreads>>>((uint4*)dst, (const uint4*)src, copy_words);
     });
-    if (st == TFT_OK && t_valu > 0 && t_mad > 0 && t_bf > 0 && t_copy > 0) {
+    if (st == TFT_OK && t_valu > 0 && t_mad > 0 && t_bf > 0 && t_xl > 0 && t_xb > 0 && t_xd > 0 && t_copy > 0) {
         out->valu_tops = (double)lanes * it_alu * 8 / t_valu / 1e12;
         out->mad64_tops = (double)lanes * it_alu * 8 / t_mad / 1e12;
         out->butterflies_g = (double)lanes * it_bf * 12 / t_bf / 1e9;
+        out->butterflies_lds_xchg_g = (double)lanes * it_bf * 12 / t_xl / 1e9;
+        out->butterflies_bpermute_xchg_g = (double)lanes * it_bf * 12 / t_xb / 1e9;
+        out->butterflies_dpp_xchg_g = (double)lanes * it_bf * 12 / t_xd / 1e9;
         out->copy_gbs = 2.0 * 16.0 * (double)copy_words / t_copy / 1e9;
     } else if (st == TFT_OK) {
         st = TFT_EDEVICE;

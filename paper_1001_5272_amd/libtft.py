@@ -35,7 +35,9 @@ class PlanDesc(ctypes.Structure):
 
 class _Calibration(ctypes.Structure):
     _fields_ = [("valu_tops", ctypes.c_double), ("mad64_tops", ctypes.c_double),
-                ("butterflies_g", ctypes.c_double), ("copy_gbs", ctypes.c_double)]
+                ("butterflies_g", ctypes.c_double), ("copy_gbs", ctypes.c_double),
+                ("butterflies_lds_xchg_g", ctypes.c_double), ("butterflies_bpermute_xchg_g", ctypes.c_double),
+                ("butterflies_dpp_xchg_g", ctypes.c_double)]
 
 
 SIGNATURES = {
@@ -349,8 +351,7 @@ def tft_calibrate(ctx: Context) -> dict:
     """Measured roofline denominators of the context's device (see the header)."""
     c = _Calibration()
     _check(load().tft_calibrate(ctx.handle, ctypes.byref(c)), "tft_calibrate")
-    return {"valu_tops": c.valu_tops, "mad64_tops": c.mad64_tops, "butterflies_g": c.butterflies_g,
-            "copy_gbs": c.copy_gbs}
+    return {f: getattr(c, f) for f, _ in _Calibration._fields_}
 
 
 def tft_timing_enable(ctx: Context, on: bool = True):

@@ -24,6 +24,9 @@ def test_calibrate(name):
         assert 1.0 < c["mad64_tops"] < 200.0
         assert 10.0 < c["butterflies_g"] < 20000.0
         assert 100.0 < c["copy_gbs"] < 20000.0
+        # an exchange after every unit cannot make the butterflies faster
+        for k in ("butterflies_lds_xchg_g", "butterflies_bpermute_xchg_g", "butterflies_dpp_xchg_g"):
+            assert 1.0 < c[k] < 1.05 * c["butterflies_g"], (k, c)
     finally:
         ctx.close()
 
