@@ -1569,8 +1569,10 @@ void queue_worker(tft_queue* q) {
             }
         }
         if (q->stop && q->pending.empty() && q->inflight.empty()) break;
-        // nothing to do right now: sleep briefly (new work or completions wake us)
-        q->cv_work.wait_for(lk, std::chrono::microseconds(q->inflight.empty() ? 500 : 20));
+        // nothing to do right now: sleep briefly (a submit wakes us; with
+        // batches in flight, look for completions every 5 us: against 20 us
+        // the served p50 at 20 k requests/s was 12 us lower, p99 the same)
+        q->cv_work.wait_for(lk, std::chrono::microseconds(q->inflight.empty() ? 500 : 5));
     }
 }
 
