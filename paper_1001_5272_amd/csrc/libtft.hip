@@ -462,7 +462,7 @@ bool set_lds_limits() {
         (const void*)tft::k_col_inv<Mod, 3, true>, (const void*)tft::k_col_inv<Mod, 4, true>,
         (const void*)tft::k_col_inv<Mod, 0>,
         (const void*)tft::k_row_fwd<Mod>,         (const void*)tft::k_row_inv<Mod>,
-        (const void*)tft::k_row_fwd_mul<Mod>,
+        (const void*)tft::k_row_fwd_mul<Mod>,     (const void*)tft::k_row_fwd_mul_inv<Mod>,
         (const void*)tft::k_last_inv<Mod>,        (const void*)tft::k_tail_inv<Mod>,
         (const void*)tft::k_col_fwd_list<Mod, 3>,
         (const void*)tft::k_col_fwd_list<Mod, 4>, (const void*)tft::k_col_inv_list<Mod, 3>,
@@ -517,9 +517,10 @@ template <class Mod>
 // buffered (comparator): the extra evaluations of the partial last row go to
 // X + a W, inside X's buffer of 2^ceil(lg n) words, instead of the context's
 // area
+// rows = false: the column pass only (the caller runs the rows; b = 0)
 tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_src, typename Mod::Word* X,
                         uint64_t n, hipStream_t st, uint64_t g0 = 0, uint32_t copies = 1,
-                        bool buffered = false) {
+                        bool buffered = false, bool rows = true) {
     using Word = typename Mod::Word;
     const Mod& md = mod_of<Mod>(ctx);
     const Plan P = make_plan(ctx, n);
@@ -547,10 +548,12 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
     if (P.b == 1) G.nparts = tiles;
     uint32_t Hs, Ss;
     const bool hs = g0 == 0 && fwd_splits(P, &Hs, &Ss);
+    if (!rows && P.b) return TFT_EINVAL;
     launch(ctx, TFT_K_COL_FWD, col_fwd_kernel<Mod>(P.logC, hs), dim3(tiles, copies), dim3(col_threads(P)), P.lds_col, st,
            md, T, G, tiles);
-    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b > 1 ? 1 : 0)), copies), dim3(row_threads(P)),
-           P.lds_row, st, md, T, G);
+    if (rows)
+        launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd<Mod>, dim3((uint32_t)(P.a + (P.b > 1 ? 1 : 0)), copies),
+               dim3(row_threads(P)), P.lds_row, st, md, T, G);
     return launch_status();
 }
 
@@ -559,8 +562,9 @@ template <class Mod>
 // buffered (comparator): the extra evaluations live in X's buffer beyond n
 // (X + a W, a buffer of 2^ceil(lg n) words) and the columns c < b wait for
 // the last row (no early modes: those keep per-column values in the area too)
+// rows = false: without the row pass (the caller ran it; b = 0)
 tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod::Word* Y, uint64_t n,
-                        hipStream_t st, bool buffered = false) {
+                        hipStream_t st, bool buffered = false, bool rows = true) {
     using Word = typename Mod::Word;
     const Mod& md = mod_of<Mod>(ctx);
     const Plan P = make_plan(ctx, n);
@@ -591,8 +595,10 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     const uint32_t C = 1u << P.logC;
     const uint32_t tiles_all = (uint32_t)(P.W >> P.logC);
     const uint32_t nrows = one_short ? (uint32_t)P.a + 1 : tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
-    launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows + (G.early == 2 ? 1u : 0u)), dim3(row_threads(P)),
-           P.lds_row, st, md, T, G, ctx->p);
+    if (!rows && P.b) return TFT_EINVAL;
+    if (rows)
+        launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows + (G.early == 2 ? 1u : 0u)), dim3(row_threads(P)),
+               P.lds_row, st, md, T, G, ctx->p);
     auto kern = [&](uint32_t len) { return col_inv_kernel<Mod>(P.logC, inv_splits(P, len)); };
     // LDS of a column tile inverting len values (as the kernel lays it out)
     auto col_lds = [&](uint32_t len) -> size_t { return col_tile_lds(P, len, false, ctx->wbytes); };
@@ -649,6 +655,31 @@ tft_status pointwise_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mo
     return launch_status();
 }
 
+// A product of length n = a W (b = 0, W >= 64) runs its rows as one launch:
+// the second operand's forward in full (into Y), the first operand's column
+// pass (into X), then k_row_fwd_mul_inv -- the first operand's rows forward
+// in LDS, times Y's rows, inverted -- and the inverse column pass: the first
+// operand's rows go through HBM once instead of three times.
+bool whole_rows_product(const Plan& P) { return P.kind == 1 && P.b == 0 && P.logW >= 6; }
+
+template <class Mod>
+tft_status mul_whole_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const typename Mod::Word* B,
+                          uint64_t nb, typename Mod::Word* X, typename Mod::Word* Y, uint64_t n, hipStream_t st) {
+    using Word = typename Mod::Word;
+    const Plan P = make_plan(ctx, n);
+    if (!whole_rows_product(P)) return TFT_EINVAL;
+    tft_status s = forward_impl<Mod>(ctx, B, nb, Y, n, st);
+    if (s == TFT_OK) s = forward_impl<Mod>(ctx, A, m, X, n, st, 0, 1, false, false);
+    if (s != TFT_OK) return s;
+    auto T = tables_of<Word>(ctx);
+    T.smax = P.smax;
+    const auto G = two_pass_of<Word>(P, X, X, n, Y, reinterpret_cast<Word*>(ctx->varea));
+    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd_mul_inv<Mod>, dim3((uint32_t)P.a), dim3(row_threads(P)), P.lds_row, st,
+           mod_of<Mod>(ctx), T, G);
+    s = launch_status();
+    return s == TFT_OK ? inverse_impl<Mod>(ctx, X, Y, n, st, false, false) : s;
+}
+
 template <class Mod>
 tft_status mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const typename Mod::Word* B, uint64_t nb,
                     typename Mod::Word* X, typename Mod::Word* Y, hipStream_t st) {
@@ -664,6 +695,7 @@ tft_status mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const
         return launch_status();
     }
     if (!Y) return TFT_EINVAL;
+    if (whole_rows_product(P)) return mul_whole_impl<Mod>(ctx, A, m, B, nb, X, Y, r, st);
     tft_status s = forward_impl<Mod>(ctx, A, m, X, r, st);
     if (s != TFT_OK) return s;
     s = forward_impl<Mod>(ctx, B, nb, Y, r, st);
@@ -866,9 +898,15 @@ tft_status padded_mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m
     if (blocks > 8192) blocks = 8192;
     launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, Ap, N, A, m);
     launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, Bp, N, B, nb);
-    tft_status s = forward_impl<Mod>(ctx, Ap, N, Ap, N, st);
-    if (s == TFT_OK) s = forward_impl<Mod>(ctx, Bp, N, Bp, N, st);
-    if (s == TFT_OK) s = inverse_impl<Mod>(ctx, Ap, Bp, N, st);
+    // the same schedule as poly_mul at a length a W
+    tft_status s = TFT_OK;
+    if (whole_rows_product(make_plan(ctx, N))) {
+        s = mul_whole_impl<Mod>(ctx, Ap, N, Bp, N, Ap, Bp, N, st);
+    } else {
+        s = forward_impl<Mod>(ctx, Ap, N, Ap, N, st);
+        if (s == TFT_OK) s = forward_impl<Mod>(ctx, Bp, N, Bp, N, st);
+        if (s == TFT_OK) s = inverse_impl<Mod>(ctx, Ap, Bp, N, st);
+    }
     if (s != TFT_OK) return s;
     blocks = (r + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;

@@ -1333,6 +1333,27 @@ __global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))
     row_fwd_lds(md, T, bb, ra + P.inst, P.logW, g);
     staged_copy<8>(W, [&](uint32_t i) { return md.mul(ba[pad(i)], bb[pad(i)]); }, [&](uint32_t i, Word v) { ra[i] = v; });
 }
+// Rows of a product of two transforms of length n = a W (b = 0, W >= 64,
+// records with g0 = 0): workgroup j takes row j of the first operand's
+// column-pass output at P.X, transforms it in LDS, multiplies it by row j of
+// the second operand's transform (P.Y) and inverts the row, storing the
+// coefficients over P.X's row.
+template <class Mod>
+__global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_row_fwd_mul_inv(
+    Mod md, Tables<typename Mod::Word> T, TwoPass<typename Mod::Word> P) {
+    using Word = typename Mod::Word;
+    Word* buf = lds_buf<Word>();
+    const uint32_t j = blockIdx.x;
+    Word* row = P.X + ((uint64_t)j << P.logW);
+    const Word* yr = P.Y + ((uint64_t)j << P.logW);
+    row_fwd_lds(md, T, buf, row, P.logW, j);
+    row_inv_run<Mod, false>(md, T, buf, row, P.logW, j, 0, nullptr, [&](uint32_t i, Word (&x)[8]) {
+        Word y[8];
+        load8(yr + 8 * i, y);
+#pragma unroll
+        for (int t = 0; t < 8; t++) x[t] = md.mul(buf[pad(8 * i) + t], y[t]);
+    });
+}
 // With P.early == 2 workgroup 0 builds Q (col_poly_body; dispatched first, it
 // runs beside the rows).  The last row's pieces come next, the full rows last.
 template <class Mod>
