@@ -517,7 +517,8 @@ template <class Mod>
 // buffered (comparator): the extra evaluations of the partial last row go to
 // X + a W, inside X's buffer of 2^ceil(lg n) words, instead of the context's
 // area
-// rows = false: the column pass only (the caller runs the rows; b = 0)
+// rows = false: the column pass only (the caller runs the rows; b = 0 or
+// the product's one-short plans)
 tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_src, typename Mod::Word* X,
                         uint64_t n, hipStream_t st, uint64_t g0 = 0, uint32_t copies = 1,
                         bool buffered = false, bool rows = true) {
@@ -548,7 +549,7 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
     if (P.b == 1) G.nparts = tiles;
     uint32_t Hs, Ss;
     const bool hs = g0 == 0 && fwd_splits(P, &Hs, &Ss);
-    if (!rows && P.b) return TFT_EINVAL;
+    if (!rows && P.b && !(P.b + 1 == P.W && !buffered && g0 == 0 && copies == 1)) return TFT_EINVAL;
     launch(ctx, TFT_K_COL_FWD, col_fwd_kernel<Mod>(P.logC, hs), dim3(tiles, copies), dim3(col_threads(P)), P.lds_col, st,
            md, T, G, tiles);
     if (rows)
@@ -558,11 +559,19 @@ tft_status forward_impl(tft_ctx* ctx, const typename Mod::Word* src, uint64_t n_
 }
 
 // -------------------------------------------------------------- inverse
+// b = W - 1 with a + 1 a power of two, rows of at least 64 words and the
+// tail's LDS within the limit: the inverse's early mode 3 (k_tail_inv)
+bool one_short_plan(const Plan& P, unsigned wbytes) {
+    const bool full_long = P.b && ((P.a + 1) & P.a) == 0;
+    const size_t lds_tail = ((size_t)tft::padded_words((uint32_t)P.a + 1) + (P.a + 1) / 2) * wbytes;
+    return full_long && P.b + 1 == P.W && P.logW >= 6 && lds_tail <= kLdsDynMax;
+}
+
 template <class Mod>
 // buffered (comparator): the extra evaluations live in X's buffer beyond n
 // (X + a W, a buffer of 2^ceil(lg n) words) and the columns c < b wait for
 // the last row (no early modes: those keep per-column values in the area too)
-// rows = false: without the row pass (the caller ran it; b = 0)
+// rows = false: without the row pass (the caller ran it; b = 0 or early mode 3)
 tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod::Word* Y, uint64_t n,
                         hipStream_t st, bool buffered = false, bool rows = true) {
     using Word = typename Mod::Word;
@@ -589,13 +598,13 @@ tft_status inverse_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mod:
     // b = W - 1 as well: the one short column and the last row are full
     // inverses with one value missing (k_tail_inv), no truncated walks
     const size_t lds_tail = ((size_t)tft::padded_words((uint32_t)P.a + 1) + (P.a + 1) / 2) * ctx->wbytes;
-    const bool one_short = !buffered && full_long && P.b + 1 == P.W && P.logW >= 6 && lds_tail <= kLdsDynMax;
+    const bool one_short = !buffered && one_short_plan(P, ctx->wbytes);
     G.early = buffered ? 0u : one_short ? 3u : (P.b && !full_long) ? (P.split ? 1u : 2u) : 0u;
     G.Q = V + kVWords;
     const uint32_t C = 1u << P.logC;
     const uint32_t tiles_all = (uint32_t)(P.W >> P.logC);
     const uint32_t nrows = one_short ? (uint32_t)P.a + 1 : tft::row_inv_items((uint32_t)P.W, (uint32_t)P.a, (uint32_t)P.b);
-    if (!rows && P.b) return TFT_EINVAL;
+    if (!rows && P.b && !one_short) return TFT_EINVAL;
     if (rows)
         launch(ctx, TFT_K_ROW_INV, tft::k_row_inv<Mod>, dim3(nrows + (G.early == 2 ? 1u : 0u)), dim3(row_threads(P)),
                P.lds_row, st, md, T, G, ctx->p);
@@ -655,27 +664,31 @@ tft_status pointwise_impl(tft_ctx* ctx, typename Mod::Word* X, const typename Mo
     return launch_status();
 }
 
-// A product of length n = a W (b = 0, W >= 64) runs its rows as one launch:
-// the second operand's forward in full (into Y), the first operand's column
-// pass (into X), then k_row_fwd_mul_inv -- the first operand's rows forward
-// in LDS, times Y's rows, inverted -- and the inverse column pass: the first
+// A product of length n = a W (b = 0, W >= 64), or with the one-short plan
+// of the inverse (b = W - 1, a + 1 a power of two), runs its rows as one
+// launch: the second operand's forward in full (into Y), the first operand's
+// column pass (into X), then k_row_fwd_mul_inv -- the first operand's rows
+// forward in LDS, times Y's rows, inverted (the partial last row as the
+// inverse's one-short row) -- and the rest of the inverse: the first
 // operand's rows go through HBM once instead of three times.
-bool whole_rows_product(const Plan& P) { return P.kind == 1 && P.b == 0 && P.logW >= 6; }
+bool whole_rows_product(const Plan& P, unsigned wbytes) {
+    return P.kind == 1 && P.logW >= 6 && (P.b == 0 || one_short_plan(P, wbytes));
+}
 
 template <class Mod>
 tft_status mul_whole_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const typename Mod::Word* B,
                           uint64_t nb, typename Mod::Word* X, typename Mod::Word* Y, uint64_t n, hipStream_t st) {
     using Word = typename Mod::Word;
     const Plan P = make_plan(ctx, n);
-    if (!whole_rows_product(P)) return TFT_EINVAL;
+    if (!whole_rows_product(P, ctx->wbytes)) return TFT_EINVAL;
     tft_status s = forward_impl<Mod>(ctx, B, nb, Y, n, st);
     if (s == TFT_OK) s = forward_impl<Mod>(ctx, A, m, X, n, st, 0, 1, false, false);
     if (s != TFT_OK) return s;
     auto T = tables_of<Word>(ctx);
     T.smax = P.smax;
     const auto G = two_pass_of<Word>(P, X, X, n, Y, reinterpret_cast<Word*>(ctx->varea));
-    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd_mul_inv<Mod>, dim3((uint32_t)P.a), dim3(row_threads(P)), P.lds_row, st,
-           mod_of<Mod>(ctx), T, G);
+    launch(ctx, TFT_K_ROW_FWD, tft::k_row_fwd_mul_inv<Mod>, dim3((uint32_t)P.a + (P.b ? 1u : 0u)), dim3(row_threads(P)),
+           P.lds_row, st, mod_of<Mod>(ctx), T, G);
     s = launch_status();
     return s == TFT_OK ? inverse_impl<Mod>(ctx, X, Y, n, st, false, false) : s;
 }
@@ -695,7 +708,7 @@ tft_status mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m, const
         return launch_status();
     }
     if (!Y) return TFT_EINVAL;
-    if (whole_rows_product(P)) return mul_whole_impl<Mod>(ctx, A, m, B, nb, X, Y, r, st);
+    if (whole_rows_product(P, ctx->wbytes)) return mul_whole_impl<Mod>(ctx, A, m, B, nb, X, Y, r, st);
     tft_status s = forward_impl<Mod>(ctx, A, m, X, r, st);
     if (s != TFT_OK) return s;
     s = forward_impl<Mod>(ctx, B, nb, Y, r, st);
@@ -900,7 +913,7 @@ tft_status padded_mul_impl(tft_ctx* ctx, const typename Mod::Word* A, uint64_t m
     launch(ctx, TFT_K_COPY, tft::k_copy_pad<Word>, dim3((uint32_t)blocks), dim3(kThreads), 0, st, Bp, N, B, nb);
     // the same schedule as poly_mul at a length a W
     tft_status s = TFT_OK;
-    if (whole_rows_product(make_plan(ctx, N))) {
+    if (whole_rows_product(make_plan(ctx, N), ctx->wbytes)) {
         s = mul_whole_impl<Mod>(ctx, Ap, N, Bp, N, Ap, Bp, N, st);
     } else {
         s = forward_impl<Mod>(ctx, Ap, N, Ap, N, st);

@@ -1333,17 +1333,37 @@ __global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))
     row_fwd_lds(md, T, bb, ra + P.inst, P.logW, g);
     staged_copy<8>(W, [&](uint32_t i) { return md.mul(ba[pad(i)], bb[pad(i)]); }, [&](uint32_t i, Word v) { ra[i] = v; });
 }
-// Rows of a product of two transforms of length n = a W (b = 0, W >= 64,
-// records with g0 = 0): workgroup j takes row j of the first operand's
-// column-pass output at P.X, transforms it in LDS, multiplies it by row j of
-// the second operand's transform (P.Y) and inverts the row, storing the
-// coefficients over P.X's row.
+// Rows of a product of two transforms of length n = a W + b (W >= 64,
+// records with g0 = 0; b = 0, or b = W - 1 with a + 1 a power of two):
+// workgroup j takes row j of the first operand's column-pass output at P.X,
+// transforms it in LDS, multiplies it by row j of the second operand's
+// transform (P.Y) and inverts the row, storing the coefficients over P.X's
+// row.  With b = W - 1 workgroup 0 takes the partial last row: its b
+// outputs (b slots and V_{W-1}), their product with Y's, and the inverse of
+// the full row with the missing value 0, whose coefficient W - 1 goes to
+// V[W - 1] (the one-short inverse's row, completed by k_tail_inv).
 template <class Mod>
 __global__ __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_row_fwd_mul_inv(
     Mod md, Tables<typename Mod::Word> T, TwoPass<typename Mod::Word> P) {
     using Word = typename Mod::Word;
     Word* buf = lds_buf<Word>();
-    const uint32_t j = blockIdx.x;
+    if (P.b && blockIdx.x == 0) {
+        const uint32_t W = 1u << P.logW;
+        Word* row = P.X + (uint64_t)P.a * W;
+        const Word* yr = P.Y + (uint64_t)P.a * W;
+        for (uint32_t i = threadIdx.x; i < W; i += nthreads()) buf[pad(i)] = i < P.b ? row[i] : P.V[i];
+        __syncthreads();
+        dif_forward(md, T, buf, 0, W, 0, P.b, P.a);
+        row_inv_run<Mod, true>(md, T, buf, row, P.logW, P.a, P.b, P.V + (W - 1), [&](uint32_t i, Word (&x)[8]) {
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const uint32_t idx = 8 * i + t;
+                x[t] = idx < P.b ? md.mul(buf[pad(8 * i) + t], yr[idx]) : Word(0);
+            }
+        });
+        return;
+    }
+    const uint32_t j = blockIdx.x - (P.b ? 1u : 0u);
     Word* row = P.X + ((uint64_t)j << P.logW);
     const Word* yr = P.Y + ((uint64_t)j << P.logW);
     row_fwd_lds(md, T, buf, row, P.logW, j);

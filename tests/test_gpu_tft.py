@@ -139,11 +139,14 @@ def test_other_primes(ctxs, name):
 def test_products(ctxs, name):
     p, g = PRIMES[name]
     ctx = ctxs[name]
-    # the last four: one operand much shorter than the product, so its column
-    # tiles hold only a few nonzero rows (the column pass skips the stages
-    # that only copy them)
+    # (3, 200000) .. (20000, 280000): one operand much shorter than the
+    # product, so its column tiles hold only a few nonzero rows (the column
+    # pass skips the stages that only copy them); r = 2^17 - 1 and 2^17: the
+    # products whose rows run as one launch (b = W - 1 with a + 1 a power of
+    # two, and b = 0)
     for m, nb in [(1, 1), (1, 7), (5, 1), (3, 4), (1000, 1500), (4096, 4097), (5000, 3000), (30000, 40001),
-                  (3, 200000), (150000, 7), (100, 300001), (20000, 280000)]:
+                  (3, 200000), (150000, 7), (100, 300001), (20000, 280000), (65536, 65536), (40000, 91072),
+                  (65536, 65537)]:
         print(f"[gpu] {name} product {m}x{nb}", flush=True)
         A = synth.residues(p, m, 100 + m)
         B = synth.residues(p, nb, 200 + nb)
