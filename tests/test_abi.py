@@ -60,3 +60,16 @@ def test_plan_bucket_without_device():
         while n ** 4 >= 2 ** (t + 1):
             t += 1
         assert lib.tft_plan_bucket(n) == t, n
+
+
+def test_argument_checks_without_device():
+    # NULL arguments are rejected before any device call
+    from paper_1001_5272_amd import libtft
+    lib = ctypes.CDLL(LIB)
+    lib.tft_batch_tuning_get.restype = ctypes.c_int
+    lib.tft_batch_tuning_get.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    t = libtft.BatchTuning()
+    assert lib.tft_batch_tuning_get(None, ctypes.byref(t)) == libtft.TFT_EINVAL
+    lib.tft_calibrate.restype = ctypes.c_int
+    lib.tft_calibrate.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.tft_calibrate(None, None) == libtft.TFT_EINVAL
