@@ -786,11 +786,11 @@ def served_c4(ctx, seconds, plain_seconds, capacity=True):
     cap = None
     if capacity:
         print("[bench] served capacity", file=sys.stderr, flush=True)
-        cap = {"criterion": "2 s Poisson streams at increasing offered rates, each after a 0.25 s warm-up "
+        cap = {"criterion": "2 s Poisson streams at increasing offered rates, each after a 1 s warm-up "
                             "stream at the same rate (not counted)", "runs": []}
         held = None
         for rate in (10000.0, 15000.0, 20000.0, 30000.0, 40000.0, 60000.0):
-            served_stream(ctx, q, rate, 0.25, 4400 + int(rate) // 1000, pool, ring)
+            served_stream(ctx, q, rate, 1.0, 4400 + int(rate) // 1000, pool, ring)
             r = served_stream(ctx, q, rate, 2.0, 4500 + int(rate) // 1000, pool, ring)
             cap["runs"].append({k: r[k] for k in ("rate_offered", "mults_per_s", "p50_us", "p99_us")})
             if r["p99_us"] < 2000.0:
